@@ -1,0 +1,234 @@
+"""Seeded generators: fat-tree instances, tenant requests and serving traces.
+
+Random streams are numpy PCG64 generators spawned from one SeedSequence per
+configuration, so instance i of a batch always sees the same numbers no
+matter how many instances are drawn.  Units are integers throughout:
+CPU in cores, RAM in GB, bandwidth in Mbps.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+
+@dataclasses.dataclass(frozen=True)
+class FatTree:
+    """Sizes of a k-ary fat-tree (k even): k^3/4 hosts, k^2/2 edge and
+    aggregation switches, k^2/4 core switches, and k^3/4 links per level."""
+    k: int
+
+    def __post_init__(self):
+        if self.k < 2 or self.k % 2:
+            raise ValueError("fat-tree arity k must be even and >= 2")
+
+    @property
+    def half(self) -> int:
+        return self.k // 2
+
+    @property
+    def n_hosts(self) -> int:
+        return self.k ** 3 // 4
+
+    @property
+    def n_edge(self) -> int:
+        return self.k * self.k // 2
+
+    @property
+    def n_agg(self) -> int:
+        return self.k * self.k // 2
+
+    @property
+    def n_core(self) -> int:
+        return self.k * self.k // 4
+
+    @property
+    def n_links(self) -> int:
+        return 3 * self.n_hosts
+
+
+@dataclasses.dataclass
+class Instance:
+    """One data center: capacities plus background load already consumed."""
+    k: int
+    host_cpu: int
+    host_ram: int
+    bw_host_edge: int
+    bw_edge_agg: int
+    bw_agg_core: int
+    host_used: Optional[np.ndarray] = None   # int32 [2][N]
+    link_used: Optional[np.ndarray] = None   # int32 [3][N]
+
+    @property
+    def tree(self) -> FatTree:
+        return FatTree(self.k)
+
+    @property
+    def n_hosts(self) -> int:
+        return self.tree.n_hosts
+
+
+@dataclasses.dataclass
+class Request:
+    """A tenant request: n containers with CPU/RAM demands and undirected
+    communication edges (i, j, bw) with i < j."""
+    cpu: np.ndarray     # int32 [n]
+    ram: np.ndarray     # int32 [n]
+    edges: np.ndarray   # int32 [m][3]
+
+    @property
+    def n(self) -> int:
+        return int(self.cpu.shape[0])
+
+    @property
+    def m(self) -> int:
+        return int(self.edges.shape[0])
+
+
+def _rng(seed_seq: np.random.SeedSequence) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed_seq))
+
+
+def make_instance(k: int, host_cpu: int, host_ram: int, bw_host_edge: int,
+                  bw_edge_agg: int, bw_agg_core: int,
+                  background: float = 0.0,
+                  rng: Optional[np.random.Generator] = None) -> Instance:
+    """Fat-tree with homogeneous hosts and per-level link capacities.
+
+    With background > 0 every host resource and every link independently
+    has floor(U[0, background) * capacity) already in use."""
+    inst = Instance(k, host_cpu, host_ram, bw_host_edge, bw_edge_agg, bw_agg_core)
+    if background > 0.0:
+        assert rng is not None
+        n = inst.n_hosts
+        hu = np.empty((2, n), dtype=np.int32)
+        hu[0] = np.floor(rng.uniform(0.0, background, n) * host_cpu).astype(np.int32)
+        hu[1] = np.floor(rng.uniform(0.0, background, n) * host_ram).astype(np.int32)
+        lu = np.empty((3, n), dtype=np.int32)
+        for lvl, cap in enumerate((bw_host_edge, bw_edge_agg, bw_agg_core)):
+            lu[lvl] = np.floor(rng.uniform(0.0, background, n) * cap).astype(np.int32)
+        inst.host_used, inst.link_used = hu, lu
+    return inst
+
+
+def _random_connected_edges(n: int, density: float, rng: np.random.Generator,
+                            bw_lo: int, bw_hi: int) -> np.ndarray:
+    """Random connected graph: a random spanning tree (node t joins a uniform
+    earlier node) plus uniformly drawn extra pairs up to
+    max(n-1, ceil(density * n(n-1)/2)) edges; bandwidth uniform in
+    [bw_lo, bw_hi]."""
+    if n < 2:
+        return np.zeros((0, 3), dtype=np.int32)
+    target = max(n - 1, int(math.ceil(density * n * (n - 1) / 2)))
+    pairs = []
+    present = set()
+    for t in range(1, n):
+        parent = int(rng.integers(0, t))
+        pairs.append((parent, t))
+        present.add((parent, t))
+    if target > len(pairs):
+        rest = [(i, j) for i in range(n) for j in range(i + 1, n) if (i, j) not in present]
+        pick = rng.choice(len(rest), size=target - len(pairs), replace=False)
+        for p in sorted(int(x) for x in pick):
+            pairs.append(rest[p])
+    bw = rng.integers(bw_lo, bw_hi + 1, size=len(pairs))
+    out = np.empty((len(pairs), 3), dtype=np.int32)
+    for e, (i, j) in enumerate(pairs):
+        out[e] = (i, j, bw[e])
+    return out
+
+
+def make_requests(count: int, rng: np.random.Generator, n_lo: int, n_hi: int,
+                  cpu_lo: int = 1, cpu_hi: int = 8, ram_lo: int = 1, ram_hi: int = 32,
+                  bw_lo: int = 100, bw_hi: int = 2000, density: float = 0.5) -> List[Request]:
+    reqs = []
+    for _ in range(count):
+        n = int(rng.integers(n_lo, n_hi + 1))
+        cpu = rng.integers(cpu_lo, cpu_hi + 1, size=n).astype(np.int32)
+        ram = rng.integers(ram_lo, ram_hi + 1, size=n).astype(np.int32)
+        edges = _random_connected_edges(n, density, rng, bw_lo, bw_hi)
+        reqs.append(Request(cpu, ram, edges))
+    return reqs
+
+
+def pack_requests(reqs: Sequence[Request]):
+    """Flatten requests into CSR arrays: container offsets, cpu, ram, edge
+    offsets and edges [m][3]."""
+    coff = np.zeros(len(reqs) + 1, dtype=np.int64)
+    eoff = np.zeros(len(reqs) + 1, dtype=np.int64)
+    for r, q in enumerate(reqs):
+        coff[r + 1] = coff[r] + q.n
+        eoff[r + 1] = eoff[r] + q.m
+    cpu = np.concatenate([q.cpu for q in reqs]).astype(np.int32) if reqs else np.zeros(0, np.int32)
+    ram = np.concatenate([q.ram for q in reqs]).astype(np.int32) if reqs else np.zeros(0, np.int32)
+    edges = (np.concatenate([q.edges for q in reqs]).astype(np.int32)
+             if reqs else np.zeros((0, 3), np.int32)).reshape(-1, 3)
+    return coff, cpu, ram, eoff, edges
+
+
+# --------------------------------------------------------------------------
+# Workload presets.  Capacities: 32 cores / 256 GB per host.  The small
+# case uses 10 Gbps everywhere and no background; the large ones use
+# 40 Gbps host links, 100 Gbps edge-aggregation and aggregation-core links
+# and a uniform 0-70 % background load on every host resource and link.
+# --------------------------------------------------------------------------
+
+CONFIGS = {
+    "tiny":    dict(k=4,  caps=(32, 256, 10000, 10000, 10000), background=0.0,
+                    n_req=(20, 20), n=(2, 6), instances=1),
+    "plain":   dict(k=16, caps=(32, 256, 40000, 100000, 100000), background=0.7,
+                    n_req=(2000, 2000), n=(2, 32), instances=1),
+    "ahp":     dict(k=32, caps=(32, 256, 40000, 100000, 100000), background=0.7,
+                    n_req=(500, 500), n=(8, 64), instances=1),
+    "batched": dict(k=16, caps=(32, 256, 40000, 100000, 100000), background=0.7,
+                    n_req=(64, 512), n=(2, 48), instances=256),
+    "serving": dict(k=48, caps=(32, 256, 40000, 100000, 100000), background=0.7,
+                    n_req=None, n=(2, 64), instances=1),
+}
+
+
+def make_config(name: str, seed: int = 0, instances: Optional[int] = None,
+                n_req: Optional[int] = None, k: Optional[int] = None):
+    """Return (instances, requests_per_instance) for a named preset.
+
+    `instances`, `n_req` and `k` override the preset (smaller test cases of
+    the same shape); instance i draws from SeedSequence(seed).spawn()[i]."""
+    cfg = CONFIGS[name]
+    n_inst = cfg["instances"] if instances is None else instances
+    kk = cfg["k"] if k is None else k
+    kids = np.random.SeedSequence(seed).spawn(n_inst)
+    insts, reqs = [], []
+    for i in range(n_inst):
+        rng = _rng(kids[i])
+        inst = make_instance(kk, *cfg["caps"], background=cfg["background"], rng=rng)
+        if n_req is not None:
+            cnt = n_req
+        else:
+            lo, hi = cfg["n_req"] if cfg["n_req"] else (100, 100)
+            cnt = int(rng.integers(lo, hi + 1))
+        reqs.append(make_requests(cnt, rng, *cfg["n"]))
+        insts.append(inst)
+    return insts, reqs
+
+
+def make_trace(seed: int, duration_s: float, rate_per_s: float = 5000.0,
+               mean_life_s: float = 60.0, n_lo: int = 2, n_hi: int = 64):
+    """Poisson arrivals (exponential inter-arrival, mean 1/rate) with
+    exponential lifetimes on a simulated clock.  Returns (requests,
+    arrival_times, departure_times); a departure after the end of the trace
+    is reported as +inf."""
+    rng = _rng(np.random.SeedSequence([seed, 5]))
+    t, arr = 0.0, []
+    while True:
+        t += float(rng.exponential(1.0 / rate_per_s))
+        if t >= duration_s:
+            break
+        arr.append(t)
+    arr = np.asarray(arr)
+    life = rng.exponential(mean_life_s, size=arr.shape[0])
+    dep = arr + life
+    dep[dep >= duration_s] = np.inf
+    reqs = make_requests(arr.shape[0], rng, n_lo, n_hi)
+    return reqs, arr, dep
