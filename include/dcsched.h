@@ -1,0 +1,185 @@
+/*
+ * dcsched.h -- C ABI of libdcsched, a GPU (AMD MI355X / gfx950) implementation
+ * of the per-container host scoring, selection and commit of
+ * "Network-Aware Container Scheduling in Multi-Tenant Data Center"
+ * (arXiv 1909.07673).
+ *
+ * Model (section II-A, Table I): a k-ary fat-tree data center G^s(N^s,E^s)
+ * (section IV-A) with N = k^3/4 servers, each with available CPU and RAM
+ * c^s_u[r], and one available bandwidth bw^s_uv per undirected link (the
+ * shared u->v / v->u link of section V-D).  A tenant request Req(N^c,E^c)
+ * has n containers with CPU/RAM demands and bandwidth demands between
+ * container pairs.  The library decides accept/reject (section II-A) and
+ * returns the mappings M_c (container -> server) and M_ec (pair -> path).
+ *
+ * Per container, in FCFS request order and container index order, every
+ * server is scored on the criteria of section V (available CPU and RAM,
+ * the fragmentation flag f_u, bw^s_u, the path bandwidth to already placed
+ * peers of the same request, the hop count to them) by TOPSIS (section
+ * V-C) or AHP (section V-B); servers are then visited in decreasing score,
+ * lowest index first on equal scores, and the first on which the container
+ * and the widest shortest paths to its placed peers (section V-D) fit
+ * (Eqs. (4)-(5)) is committed.  If no server fits, every container of the
+ * request is undone and the request is rejected (all or nothing).
+ *
+ * Units are integers: CPU cores, RAM GB, bandwidth Mbps.
+ *
+ * Indexing shared with the inputs (k even, h = k/2):
+ *   server  u = p*h*h + e*h + s      (pod p, edge switch e, slot s)
+ *   link level 0: server uplink u; level 1: edge-aggregation (u/h)*h + a;
+ *   level 2: aggregation-core (p*h + a)*h + j, joining aggregation switch
+ *   (p, a) and core switch a*h + j.  Each level has N links.
+ *
+ * Errors: every int-returning call returns DC_OK (0) or a negative code;
+ * nothing is thrown across the ABI.  After DC_EDEVICE the context is
+ * poisoned and only dc_destroy is valid.  A context is not thread safe.
+ * The caller owns every buffer it passes; inputs are copied before the
+ * call returns, outputs are written into caller memory.
+ */
+#ifndef DCSCHED_H
+#define DCSCHED_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DC_MAX_CONTAINERS 64
+#define DC_MAX_CRIT 8
+
+enum dc_status {
+    DC_OK = 0,
+    DC_EINVAL = -1,   /* bad argument: odd k, n > 64, i == j, bw <= 0, ...    */
+    DC_ENOMEM = -2,   /* device or host allocation failed                     */
+    DC_EAGAIN = -3,   /* serving admission: memory budget full, retry later   */
+    DC_ENOENT = -4,   /* unknown request id, or request not accepted          */
+    DC_EDEVICE = -5,  /* a HIP call failed; the context is poisoned           */
+    DC_ESTATE = -6    /* call not valid in this mode / state                  */
+};
+
+enum dc_method { DC_TOPSIS = 0, DC_AHP = 1 };
+enum dc_ahp_scale { DC_AHP_SAATY9 = 0, DC_AHP_RATIO = 1 };
+enum dc_mode { DC_MODE_PLAIN = 0, DC_MODE_BATCHED = 1, DC_MODE_SERVING = 2 };
+
+/* Criteria (section V): available CPU, available RAM, fragmentation flag
+ * f_u (1 when u hosts a container placed by this library), path bandwidth
+ * (bw^s_u narrowed to the widest shortest path to each remote placed peer),
+ * bw^s_u itself (available uplink bandwidth), and the summed hop count to
+ * the placed peers (normally a cost criterion). */
+enum dc_criterion {
+    DC_CRIT_CPU = 0, DC_CRIT_RAM = 1, DC_CRIT_ACTIVE = 2,
+    DC_CRIT_PATHBW = 3, DC_CRIT_UPLINK = 4, DC_CRIT_HOPS = 5
+};
+
+typedef struct dc_ctx dc_ctx;
+
+typedef struct dc_config {
+    int32_t k;              /* fat-tree arity, even, 4..64                          */
+    int32_t n_instances;    /* independent data centers (batched form), >= 1        */
+    int32_t mode;           /* dc_mode                                              */
+    int32_t method;         /* dc_method                                            */
+    int32_t ahp_scale;      /* dc_ahp_scale (AHP only)                              */
+    int32_t host_cpu, host_ram;                     /* per-server capacity          */
+    int32_t bw_host_edge, bw_edge_agg, bw_agg_core; /* per-level link capacity      */
+    int32_t ncrit;          /* 1..DC_MAX_CRIT                                       */
+    int32_t crit[DC_MAX_CRIT];      /* dc_criterion ids                             */
+    int32_t crit_cost[DC_MAX_CRIT]; /* 1 = smaller is better                        */
+    float weight[DC_MAX_CRIT];      /* > 0, summing to 1 within 1e-5 (Table IV)     */
+    const int32_t *host_used; /* nullable host array [n_instances][2][N]: CPU, RAM already in use */
+    const int32_t *link_used; /* nullable host array [n_instances][3][N]: Mbps already in use     */
+    void *stream;           /* hipStream_t to launch on (e.g. torch's), NULL = own stream */
+    size_t mem_budget;      /* serving: device bytes for live request slots (0 = 256 MiB) */
+    int32_t block;          /* threads per workgroup, 0 = automatic / autotuned     */
+    int32_t trace_stride;   /* record the score vector of every trace_stride-th step (0 = off) */
+    int32_t trace_cap;      /* at most this many recorded steps                     */
+    int32_t reserved[5];
+} dc_config;
+
+typedef struct dc_result {
+    int64_t req_id;
+    int32_t instance;
+    int32_t status;         /* 1 accepted, 0 rejected                               */
+    int32_t n;              /* containers                                           */
+    int32_t failed_at;      /* first container with no server (rejected), else -1   */
+    int32_t host[DC_MAX_CONTAINERS];  /* M_c; -1 when rejected                     */
+    float score[DC_MAX_CONTAINERS];   /* score of the chosen server                */
+} dc_result;
+
+/* Create a context: device-resident state for n_instances data centers,
+ * with the background load applied.  Returns DC_EINVAL for odd or out of
+ * range k, ncrit out of range, unknown criterion, non-positive weights or
+ * weights not summing to 1, DC_ENOMEM, DC_EDEVICE. */
+int dc_create(const dc_config *cfg, dc_ctx **out);
+
+/* Queue one tenant request for data center `instance` (section II-A).
+ * cpu[n], ram[n]: container demands (>= 0).  edges[m][3]: (i, j, bw) with
+ * i != j, 0 <= i, j < n, bw > 0, each unordered pair at most once.
+ * pod: reserved, must be NULL.  The request id is returned in *req_id; ids
+ * grow in submission order, which is the FCFS order.  n must be 1..64. */
+int dc_submit_request(dc_ctx *ctx, int32_t instance, int32_t n, const int32_t *cpu,
+                      const int32_t *ram, int32_t m, const int32_t *edges,
+                      const int32_t *pod, int64_t *req_id);
+
+/* Plain and batched forms: schedule every queued request (FCFS per
+ * instance) and block until done; results of the scheduled requests go to
+ * out[0..*n_out) in request id order (at most max_results are written; the
+ * rest stay available to the next call).  Serving form: non-blocking poll of
+ * completed requests. */
+int dc_schedule(dc_ctx *ctx, int32_t max_results, dc_result *out, int32_t *n_out);
+
+/* Departure of an accepted request: gives back its CPU, RAM and path
+ * bandwidth.  DC_ENOENT for unknown, rejected, pending or released ids. */
+int dc_release(dc_ctx *ctx, int64_t req_id);
+
+/* Links of an accepted request's routed pairs (M_ec): 6 link ids per
+ * container pair, in container order then peer order, -1 padded (a
+ * co-located pair uses no link).  Link id = level*N + index. *n receives
+ * the number of pairs; at most cap pairs are written. */
+int dc_get_paths(dc_ctx *ctx, int64_t req_id, int32_t cap, int32_t *link_ids, int32_t *n);
+
+/* Servers chosen for each container of a scheduled request, including,
+ * for a rejected request, the servers its containers before failed_at held
+ * before the rollback (-1 from failed_at on).  Meant for lockstep checks.
+ * *n receives the container count; at most cap entries are written. */
+int dc_get_attempt(dc_ctx *ctx, int64_t req_id, int32_t cap, int32_t *hosts, int32_t *n);
+
+/* Service latency of every scheduled request (first step start to the
+ * accept / reject decision, measured with the device's 100 MHz clock), in
+ * microseconds, in request id order.  *n receives the count. */
+int dc_get_latency(dc_ctx *ctx, int32_t cap, float *service_us, int32_t *n);
+
+/* Copy the current state of one instance to out[6][N] (int32): available
+ * CPU, RAM, placed-container count, then link levels 0, 1, 2. */
+int dc_get_state(dc_ctx *ctx, int32_t instance, int32_t *out);
+
+/* Plain and batched forms: restore every instance to its state at creation
+ * and queue again every request submitted so far, keeping their device
+ * copies (no new upload).  Used to replay the same workload. */
+int dc_rewind(dc_ctx *ctx);
+
+/* Recorded score vectors (trace_stride > 0): meta[s][4] = (instance,
+ * request index within its schedule call, container, global step number),
+ * scores[s][N] float.  *n receives the number of recorded steps. */
+int dc_get_trace(dc_ctx *ctx, int32_t cap, int32_t *meta, float *scores, int32_t *n);
+
+/* Batched form: time every candidate tile shape on the queued workload (on
+ * a scratch copy of the state), keep the fastest for later dc_schedule
+ * calls, and return its workgroup size in *block.  The state and queue are
+ * left unchanged. */
+int dc_autotune(dc_ctx *ctx, int32_t *block);
+
+/* Milliseconds the last dc_schedule spent on the device, measured with HIP
+ * events around its launches on the context's stream, and the number of
+ * scheduling kernel launches it made. */
+int dc_last_timing(dc_ctx *ctx, float *ms, int64_t *launches, int64_t *steps);
+
+void dc_destroy(dc_ctx *ctx);
+const char *dc_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DCSCHED_H */

@@ -1,0 +1,244 @@
+"""ctypes binding of libdcsched (include/dcsched.h): same names, argument
+marshalling only.  Every step of the scheduling path runs in the library's
+HIP kernels; there is no CPU fallback, and loading fails loudly when the
+library has not been built."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Iterable, List, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdcsched.so")
+
+DC_OK, DC_EINVAL, DC_ENOMEM, DC_EAGAIN, DC_ENOENT, DC_EDEVICE, DC_ESTATE = 0, -1, -2, -3, -4, -5, -6
+DC_TOPSIS, DC_AHP = 0, 1
+DC_AHP_SAATY9, DC_AHP_RATIO = 0, 1
+DC_MODE_PLAIN, DC_MODE_BATCHED, DC_MODE_SERVING = 0, 1, 2
+DC_CRIT_CPU, DC_CRIT_RAM, DC_CRIT_ACTIVE, DC_CRIT_PATHBW, DC_CRIT_UPLINK, DC_CRIT_HOPS = range(6)
+DC_MAX_CONTAINERS, DC_MAX_CRIT = 64, 8
+
+DEFAULT_CRIT = (DC_CRIT_CPU, DC_CRIT_RAM, DC_CRIT_ACTIVE, DC_CRIT_PATHBW)
+
+
+class dc_config(C.Structure):
+    _fields_ = [("k", C.c_int32), ("n_instances", C.c_int32), ("mode", C.c_int32),
+                ("method", C.c_int32), ("ahp_scale", C.c_int32),
+                ("host_cpu", C.c_int32), ("host_ram", C.c_int32),
+                ("bw_host_edge", C.c_int32), ("bw_edge_agg", C.c_int32), ("bw_agg_core", C.c_int32),
+                ("ncrit", C.c_int32), ("crit", C.c_int32 * 8), ("crit_cost", C.c_int32 * 8),
+                ("weight", C.c_float * 8),
+                ("host_used", C.c_void_p), ("link_used", C.c_void_p), ("stream", C.c_void_p),
+                ("mem_budget", C.c_size_t), ("block", C.c_int32), ("trace_stride", C.c_int32),
+                ("trace_cap", C.c_int32), ("reserved", C.c_int32 * 5)]
+
+
+class dc_result(C.Structure):
+    _fields_ = [("req_id", C.c_int64), ("instance", C.c_int32), ("status", C.c_int32),
+                ("n", C.c_int32), ("failed_at", C.c_int32),
+                ("host", C.c_int32 * DC_MAX_CONTAINERS), ("score", C.c_float * DC_MAX_CONTAINERS)]
+
+
+class DcError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libdcsched.so; raises if it is missing (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libdcsched.so not built at {LIB_PATH}; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        i32p = C.POINTER(C.c_int32)
+        L.dc_create.argtypes = [C.POINTER(dc_config), C.POINTER(P)]
+        L.dc_submit_request.argtypes = [P, C.c_int32, C.c_int32, i32p, i32p, C.c_int32, i32p, i32p,
+                                        C.POINTER(C.c_int64)]
+        L.dc_schedule.argtypes = [P, C.c_int32, C.POINTER(dc_result), C.POINTER(C.c_int32)]
+        L.dc_release.argtypes = [P, C.c_int64]
+        L.dc_get_paths.argtypes = [P, C.c_int64, C.c_int32, i32p, C.POINTER(C.c_int32)]
+        L.dc_get_attempt.argtypes = [P, C.c_int64, C.c_int32, i32p, C.POINTER(C.c_int32)]
+        L.dc_get_state.argtypes = [P, C.c_int32, i32p]
+        L.dc_get_latency.argtypes = [P, C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_int32)]
+        L.dc_rewind.argtypes = [P]
+        L.dc_get_trace.argtypes = [P, C.c_int32, i32p, C.POINTER(C.c_float), C.POINTER(C.c_int32)]
+        L.dc_autotune.argtypes = [P, C.POINTER(C.c_int32)]
+        L.dc_last_timing.argtypes = [P, C.POINTER(C.c_float), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.dc_destroy.argtypes = [P]
+        L.dc_destroy.restype = None
+        L.dc_strerror.argtypes = [C.c_int]
+        L.dc_strerror.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().dc_strerror(code).decode()
+
+
+def _check(rc: int, what: str):
+    if rc != DC_OK:
+        raise DcError(rc, what)
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _p32(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _stream_handle(stream) -> Optional[int]:
+    """Accepts None, an int handle, or a torch.cuda.Stream."""
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+class Result:
+    __slots__ = ("req_id", "instance", "status", "n", "failed_at", "hosts", "scores")
+
+    def __init__(self, r: dc_result):
+        self.req_id, self.instance, self.status = r.req_id, r.instance, r.status
+        self.n, self.failed_at = r.n, r.failed_at
+        self.hosts = np.frombuffer(r.host, dtype=np.int32, count=r.n).copy()
+        self.scores = np.frombuffer(r.score, dtype=np.float32, count=r.n).copy()
+
+
+class Scheduler:
+    """One libdcsched context (dc_create ... dc_destroy)."""
+
+    def __init__(self, instances: List, method: int = DC_TOPSIS, mode: int = DC_MODE_PLAIN,
+                 crit: Iterable[int] = DEFAULT_CRIT, cost: Optional[Iterable[int]] = None,
+                 weight: Optional[Iterable[float]] = None, ahp_scale: int = DC_AHP_SAATY9,
+                 stream=None, block: int = 0, trace_stride: int = 0, trace_cap: int = 0,
+                 mem_budget: int = 0):
+        inst0 = instances[0]
+        crit = list(crit)
+        cost = list(cost) if cost is not None else [0] * len(crit)
+        weight = list(weight) if weight is not None else [1.0 / len(crit)] * len(crit)
+        cfg = dc_config()
+        cfg.k, cfg.n_instances, cfg.mode, cfg.method, cfg.ahp_scale = inst0.k, len(instances), mode, method, ahp_scale
+        cfg.host_cpu, cfg.host_ram = inst0.host_cpu, inst0.host_ram
+        cfg.bw_host_edge, cfg.bw_edge_agg, cfg.bw_agg_core = inst0.bw_host_edge, inst0.bw_edge_agg, inst0.bw_agg_core
+        cfg.ncrit = len(crit)
+        for c in range(len(crit)):
+            cfg.crit[c], cfg.crit_cost[c], cfg.weight[c] = crit[c], cost[c], weight[c]
+        N = inst0.k ** 3 // 4
+        self._hu = self._lu = None
+        if any(i.host_used is not None for i in instances):
+            self._hu = np.concatenate([(i.host_used if i.host_used is not None else np.zeros((2, N), np.int32))
+                                       .reshape(-1) for i in instances]).astype(np.int32)
+            cfg.host_used = self._hu.ctypes.data
+        if any(i.link_used is not None for i in instances):
+            self._lu = np.concatenate([(i.link_used if i.link_used is not None else np.zeros((3, N), np.int32))
+                                       .reshape(-1) for i in instances]).astype(np.int32)
+            cfg.link_used = self._lu.ctypes.data
+        h = _stream_handle(stream)
+        cfg.stream = h if h else None
+        cfg.block, cfg.trace_stride, cfg.trace_cap, cfg.mem_budget = block, trace_stride, trace_cap, mem_budget
+        self.N, self.I, self.k = N, len(instances), inst0.k
+        self.cfg = cfg
+        self._ctx = C.c_void_p()
+        _check(lib().dc_create(C.byref(cfg), C.byref(self._ctx)), "dc_create")
+
+    def close(self):
+        if self._ctx:
+            lib().dc_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, req, instance: int = 0) -> int:
+        cpu, ram = _i32(req.cpu), _i32(req.ram)
+        edges = _i32(req.edges).reshape(-1)
+        rid = C.c_int64()
+        _check(lib().dc_submit_request(self._ctx, instance, len(cpu), _p32(cpu), _p32(ram), len(edges) // 3,
+                                       _p32(edges) if len(edges) else None, None, C.byref(rid)),
+               "dc_submit_request")
+        return rid.value
+
+    def schedule(self, max_results: int = 1 << 20) -> List[Result]:
+        out = []
+        buf = (dc_result * 4096)()
+        n = C.c_int32()
+        remaining = max_results
+        while True:
+            _check(lib().dc_schedule(self._ctx, min(4096, remaining), buf, C.byref(n)), "dc_schedule")
+            out.extend(Result(buf[i]) for i in range(n.value))
+            remaining -= n.value
+            if n.value < 4096 or remaining <= 0:
+                return out
+
+    def release(self, req_id: int) -> int:
+        return lib().dc_release(self._ctx, req_id)
+
+    def paths(self, req_id: int) -> np.ndarray:
+        n = C.c_int32()
+        cap = DC_MAX_CONTAINERS * DC_MAX_CONTAINERS
+        buf = np.zeros(6 * cap, np.int32)
+        _check(lib().dc_get_paths(self._ctx, req_id, cap, _p32(buf), C.byref(n)), "dc_get_paths")
+        return buf[: 6 * n.value].reshape(n.value, 6)
+
+    def attempt(self, req_id: int) -> np.ndarray:
+        n = C.c_int32()
+        buf = np.zeros(DC_MAX_CONTAINERS, np.int32)
+        _check(lib().dc_get_attempt(self._ctx, req_id, DC_MAX_CONTAINERS, _p32(buf), C.byref(n)), "dc_get_attempt")
+        return buf[: n.value].copy()
+
+    def latency_us(self) -> np.ndarray:
+        """Service latency (us) of every scheduled request, id order."""
+        n = C.c_int32()
+        _check(lib().dc_get_latency(self._ctx, 0, None, C.byref(n)), "dc_get_latency")
+        out = np.zeros(max(n.value, 1), np.float32)
+        _check(lib().dc_get_latency(self._ctx, n.value, out.ctypes.data_as(C.POINTER(C.c_float)), C.byref(n)),
+               "dc_get_latency")
+        return out[: n.value]
+
+    def state(self, instance: int = 0) -> np.ndarray:
+        out = np.zeros(6 * self.N, np.int32)
+        _check(lib().dc_get_state(self._ctx, instance, _p32(out)), "dc_get_state")
+        return out.reshape(6, self.N)
+
+    def rewind(self):
+        _check(lib().dc_rewind(self._ctx), "dc_rewind")
+
+    def trace(self):
+        cap = self.cfg.trace_cap
+        meta = np.zeros(4 * max(cap, 1), np.int32)
+        scores = np.zeros(max(cap, 1) * self.N, np.float32)
+        n = C.c_int32()
+        _check(lib().dc_get_trace(self._ctx, cap, _p32(meta), scores.ctypes.data_as(C.POINTER(C.c_float)),
+                                  C.byref(n)), "dc_get_trace")
+        return meta[: 4 * n.value].reshape(-1, 4), scores[: n.value * self.N].reshape(-1, self.N)
+
+    def autotune(self) -> int:
+        b = C.c_int32()
+        _check(lib().dc_autotune(self._ctx, C.byref(b)), "dc_autotune")
+        return b.value
+
+    def last_timing(self):
+        ms, la, st = C.c_float(), C.c_int64(), C.c_int64()
+        _check(lib().dc_last_timing(self._ctx, C.byref(ms), C.byref(la), C.byref(st)), "dc_last_timing")
+        return ms.value, la.value, st.value

@@ -1,0 +1,733 @@
+// libdcsched host runtime: the C ABI of include/dcsched.h over the kernels of
+// dc_kernels.hpp.  Owns the device-resident data-center state, uploads
+// request batches, drives the plain (one launch per container step) and
+// batched (one persistent launch) forms, and collects results.
+#include "../../include/dcsched.h"
+#include "dc_kernels.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <unordered_map>
+#include <vector>
+
+using namespace dcs;
+
+namespace {
+
+// One uploaded set of requests (the pending queue at a dc_schedule call).
+struct DevBatch {
+    int R = 0, Ct = 0, Pt = 0, I = 0;
+    int *dmem = nullptr;           // device: inputs then outputs
+    size_t in_ints = 0, out_ints = 0;
+    Batch view{};
+    std::vector<int64_t> ids;      // request id per batch request
+    std::vector<int> inst, coff, poff, pj, pbw, cpu, ram, iroff;
+    std::vector<int> host, code, status, failat;
+    std::vector<float> score;
+    std::vector<long long> tsb, tse;
+};
+
+struct ReqLoc {
+    int batch = -1, r = -1;
+    bool released = false;
+};
+
+}  // namespace
+
+struct dc_ctx {
+    dc_config cfg{};
+    Topo t{};
+    Method m{};
+    int N = 0, I = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool poisoned = false;
+    int *d_state = nullptr;        // [I][6][N]
+    int *d_init = nullptr;         // [I][6][N]
+    int *d_xs = nullptr;           // [I][nc+4][N]
+    int *d_colpart = nullptr;      // AHP [nc][nI][N]
+    float *d_rowpart = nullptr;    // AHP [nc][nJ][N]
+    int ti = 0, tj = 0, nI = 0, nJ = 0;
+    int *d_tmeta = nullptr, *d_tcount = nullptr;
+    float *d_tscore = nullptr;
+    int plain_bs = 1024, batched_bs = 1024;
+    int pc_plain = 1, pc_batched = 1;
+    bool xs_lds = false;
+    size_t lds_plain = 0, lds_select = 0;
+    std::vector<std::unique_ptr<DevBatch>> batches;
+    std::vector<int> queued;       // batches uploaded and waiting to run
+    std::vector<int> pend_inst, pend_n;
+    std::vector<std::vector<int>> pend_cpu, pend_ram, pend_edges;
+    std::vector<int64_t> pend_ids;
+    std::unordered_map<int64_t, ReqLoc> loc;
+    int64_t next_id = 0;
+    std::deque<dc_result> ready;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    float last_ms = 0.f;
+    int64_t last_launches = 0, last_steps = 0;
+};
+
+#define HIPCHK(expr)                                       \
+    do {                                                   \
+        hipError_t e_ = (expr);                            \
+        if (e_ != hipSuccess) {                            \
+            ctx->poisoned = true;                          \
+            std::fprintf(stderr, "libdcsched: %s failed: %s\n", #expr, hipGetErrorString(e_)); \
+            return DC_EDEVICE;                             \
+        }                                                  \
+    } while (0)
+
+namespace {
+
+int check_config(const dc_config *c) {
+    if (!c) return DC_EINVAL;
+    if (c->k < 4 || c->k > 64 || (c->k & 1)) return DC_EINVAL;
+    if (c->n_instances < 1 || c->n_instances > 65536) return DC_EINVAL;
+    if (c->mode < DC_MODE_PLAIN || c->mode > DC_MODE_SERVING) return DC_EINVAL;
+    if (c->method != DC_TOPSIS && c->method != DC_AHP) return DC_EINVAL;
+    if (c->method == DC_AHP && c->ahp_scale != DC_AHP_SAATY9 && c->ahp_scale != DC_AHP_RATIO) return DC_EINVAL;
+    if (c->method == DC_AHP && c->mode != DC_MODE_PLAIN) return DC_EINVAL;
+    const int caps[5] = {c->host_cpu, c->host_ram, c->bw_host_edge, c->bw_edge_agg, c->bw_agg_core};
+    for (int v : caps)
+        if (v < 0 || v > (1 << 22)) return DC_EINVAL;   // keeps every value exact in FP32 arithmetic
+    if (c->ncrit < 1 || c->ncrit > DC_MAX_CRIT) return DC_EINVAL;
+    double ws = 0.0;
+    for (int i = 0; i < c->ncrit; ++i) {
+        if (c->crit[i] < DC_CRIT_CPU || c->crit[i] > DC_CRIT_HOPS) return DC_EINVAL;
+        if (!(c->weight[i] > 0.f) || !std::isfinite(c->weight[i])) return DC_EINVAL;
+        ws += c->weight[i];
+    }
+    if (std::fabs(ws - 1.0) > 1e-5) return DC_EINVAL;
+    if (c->block != 0 && c->block != 64 && c->block != 256 && c->block != 512 && c->block != 1024) return DC_EINVAL;
+    if (c->trace_stride < 0 || c->trace_cap < 0) return DC_EINVAL;
+    return DC_OK;
+}
+
+// Links of the path between servers u != v for candidate c, as global link
+// ids (level * N + index); returns the count.
+int host_path_links(const Topo &t, int u, int v, int c, int *out) {
+    const int eu = u / t.h, ev = v / t.h, pu = u / t.hh, pv = v / t.hh;
+    int a = 0, j = 0;
+    if (pu == pv) a = c; else { a = c / t.h; j = c - a * t.h; }
+    int nl = 0;
+    out[nl++] = u;
+    if (eu != ev) out[nl++] = t.N + eu * t.h + a;
+    if (pu != pv) {
+        out[nl++] = 2 * t.N + (pu * t.h + a) * t.h + j;
+        out[nl++] = 2 * t.N + (pv * t.h + a) * t.h + j;
+    }
+    if (eu != ev) out[nl++] = t.N + ev * t.h + a;
+    out[nl++] = v;
+    return nl;
+}
+
+template <class K>
+int set_lds(dc_ctx *ctx, K kernel, size_t bytes) {
+    HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               static_cast<int>(bytes)));
+    return DC_OK;
+}
+
+State state_of(dc_ctx *ctx, int inst) {
+    int *s = ctx->d_state + (size_t)inst * 6 * ctx->N;
+    const int N = ctx->N;
+    return State{s, s + N, s + 2 * N, s + 3 * N, s + 4 * N, s + 5 * N};
+}
+
+Params base_params(dc_ctx *ctx, const DevBatch &b, int inst) {
+    Params p{};
+    p.t = ctx->t;
+    p.st = state_of(ctx, inst);
+    p.m = ctx->m;
+    p.b = b.view;
+    p.tr = Trace{ctx->d_tmeta, ctx->d_tscore, ctx->d_tcount, ctx->cfg.trace_stride, ctx->cfg.trace_cap};
+    p.xs = ctx->d_xs + (size_t)inst * (ctx->m.nc + 4) * ctx->N;
+    p.pc_cap = ctx->pc_plain;
+    p.inst = inst;
+    p.state_base = ctx->d_state;
+    p.state_stride = 6LL * ctx->N;
+    p.colpart = ctx->d_colpart;
+    p.rowpart = ctx->d_rowpart;
+    p.ti = ctx->ti; p.tj = ctx->tj; p.nI = ctx->nI; p.nJ = ctx->nJ;
+    return p;
+}
+
+// Output region of a batch: host[Ct], code[Pt], failat[R] (all -1), then
+// status[R] (1), then score[Ct], tsb[R], tse[R] (0; the stamps are int64).
+int reset_outputs(dc_ctx *ctx, DevBatch &b) {
+    int *out = b.dmem + b.in_ints;
+    const long long neg = (long long)b.Ct + b.Pt + b.R;
+    hipLaunchKernelGGL(k_fill_i32, dim3(64), dim3(256), 0, ctx->stream, out, -1, neg);
+    hipLaunchKernelGGL(k_fill_i32, dim3(16), dim3(256), 0, ctx->stream, out + neg, 1, (long long)b.R);
+    hipLaunchKernelGGL(k_fill_i32, dim3(64), dim3(256), 0, ctx->stream, out + neg + b.R, 0,
+                       (long long)b.out_ints - neg - b.R);
+    HIPCHK(hipGetLastError());
+    return DC_OK;
+}
+
+// Turn the pending queue into one uploaded batch (requests grouped by
+// instance, FCFS order kept within an instance).
+int upload_pending(dc_ctx *ctx) {
+    const size_t R = ctx->pend_ids.size();
+    if (R == 0) return DC_OK;
+    auto B = std::make_unique<DevBatch>();
+    DevBatch &b = *B;
+    b.R = (int)R;
+    b.I = ctx->I;
+    std::vector<int> order(R);
+    for (size_t r = 0; r < R; ++r) order[r] = (int)r;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int c) { return ctx->pend_inst[a] < ctx->pend_inst[c]; });
+    b.coff.assign(1, 0);
+    b.poff.assign(1, 0);
+    b.iroff.assign(ctx->I + 1, 0);
+    for (int idx : order) {
+        const int n = ctx->pend_n[idx];
+        const std::vector<int> &e = ctx->pend_edges[idx];
+        b.ids.push_back(ctx->pend_ids[idx]);
+        b.inst.push_back(ctx->pend_inst[idx]);
+        b.iroff[ctx->pend_inst[idx] + 1]++;
+        // peers of container i: edges (i, j) with j < i, ascending j
+        std::vector<int> bwm((size_t)n * n, 0);
+        for (size_t q = 0; q + 2 < e.size(); q += 3) {
+            bwm[(size_t)e[q] * n + e[q + 1]] = e[q + 2];
+            bwm[(size_t)e[q + 1] * n + e[q]] = e[q + 2];
+        }
+        for (int i = 0; i < n; ++i) {
+            b.cpu.push_back(ctx->pend_cpu[idx][i]);
+            b.ram.push_back(ctx->pend_ram[idx][i]);
+            for (int j = 0; j < i; ++j)
+                if (bwm[(size_t)i * n + j]) { b.pj.push_back(j); b.pbw.push_back(bwm[(size_t)i * n + j]); }
+            b.poff.push_back((int)b.pj.size());
+        }
+        b.coff.push_back((int)b.cpu.size());
+    }
+    for (int i = 0; i < ctx->I; ++i) b.iroff[i + 1] += b.iroff[i];
+    b.Ct = (int)b.cpu.size();
+    b.Pt = (int)b.pj.size();
+    // device layout: inputs coff, cpu, ram, poff, pj, pbw, iroff; outputs
+    size_t n_in = (size_t)(b.R + 1) + 2 * b.Ct + (b.Ct + 1) + 2 * (size_t)b.Pt + (b.I + 1);
+    n_in += n_in & 1;   // keeps the int64 stamps in the output region 8-byte aligned
+    const size_t n_out = (size_t)b.Ct + b.Pt + b.R + b.R + b.Ct + 1 + 4 * (size_t)b.R;
+    b.in_ints = n_in;
+    b.out_ints = n_out;
+    std::vector<int> img(n_in, 0);
+    size_t o = 0;
+    auto put = [&](const std::vector<int> &v) { std::memcpy(img.data() + o, v.data(), v.size() * sizeof(int)); o += v.size(); };
+    const size_t o_coff = o; put(b.coff);
+    const size_t o_cpu = o; put(b.cpu);
+    const size_t o_ram = o; put(b.ram);
+    const size_t o_poff = o; put(b.poff);
+    const size_t o_pj = o; put(b.pj);
+    const size_t o_pbw = o; put(b.pbw);
+    const size_t o_iroff = o; put(b.iroff);
+    HIPCHK(hipMalloc(&b.dmem, (n_in + n_out) * sizeof(int)));
+    HIPCHK(hipMemcpyAsync(b.dmem, img.data(), n_in * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+    int *d = b.dmem;
+    int *out = d + n_in;
+    b.view.coff = d + o_coff;
+    b.view.cpu = d + o_cpu;
+    b.view.ram = d + o_ram;
+    b.view.poff = d + o_poff;
+    b.view.pj = d + o_pj;
+    b.view.pbw = d + o_pbw;
+    b.view.iroff = d + o_iroff;
+    b.view.host = out;
+    b.view.code = out + b.Ct;
+    b.view.failat = out + b.Ct + b.Pt;
+    b.view.status = out + b.Ct + b.Pt + b.R;
+    b.view.score = reinterpret_cast<float *>(out + b.Ct + b.Pt + 2 * b.R);
+    {
+        size_t o_ts = (size_t)b.Ct + b.Pt + 2 * b.R + b.Ct;
+        o_ts += o_ts & 1;   // n_in is even, so this makes the stamps 8-byte aligned
+        b.view.tsb = reinterpret_cast<long long *>(out + o_ts);
+        b.view.tse = b.view.tsb + b.R;
+    }
+    int rc = reset_outputs(ctx, b);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(ctx->stream));   // img is pageable host memory
+    const int bi = (int)ctx->batches.size();
+    for (int r = 0; r < b.R; ++r) ctx->loc[b.ids[r]] = ReqLoc{bi, r, false};
+    ctx->batches.push_back(std::move(B));
+    ctx->queued.push_back(bi);
+    ctx->pend_ids.clear(); ctx->pend_inst.clear(); ctx->pend_n.clear();
+    ctx->pend_cpu.clear(); ctx->pend_ram.clear(); ctx->pend_edges.clear();
+    return DC_OK;
+}
+
+template <int BS>
+void launch_plain_step(dc_ctx *ctx, const Params &p) {
+    if (ctx->m.method == DC_TOPSIS) {
+        if (ctx->xs_lds)
+            hipLaunchKernelGGL((k_topsis_plain<BS, true>), dim3(1), dim3(BS), ctx->lds_plain, ctx->stream, p);
+        else
+            hipLaunchKernelGGL((k_topsis_plain<BS, false>), dim3(1), dim3(BS), ctx->lds_plain, ctx->stream, p);
+        ctx->last_launches += 1;
+    } else {
+        const int bx = (ctx->N + kAhpBlock - 1) / kAhpBlock;
+        hipLaunchKernelGGL((k_criteria_plain<BS>), dim3(1), dim3(BS), ctx->lds_plain, ctx->stream, p);
+        hipLaunchKernelGGL(k_ahp_colsum, dim3(bx, ctx->nI, ctx->m.nc), dim3(kAhpBlock), 0, ctx->stream, p);
+        hipLaunchKernelGGL(k_ahp_rowsum, dim3(bx, ctx->nJ, ctx->m.nc), dim3(kAhpBlock), 0, ctx->stream, p);
+        hipLaunchKernelGGL((k_ahp_select<BS>), dim3(1), dim3(BS), ctx->lds_select, ctx->stream, p);
+        ctx->last_launches += 4;
+    }
+}
+
+int run_plain(dc_ctx *ctx, DevBatch &b) {
+    for (int r = 0; r < b.R; ++r) {
+        Params p = base_params(ctx, b, b.inst[r]);
+        p.r = r;
+        const int n = b.coff[r + 1] - b.coff[r];
+        for (int i = 0; i < n; ++i) {
+            p.i = i;
+            switch (ctx->plain_bs) {
+            case 64: launch_plain_step<64>(ctx, p); break;
+            case 256: launch_plain_step<256>(ctx, p); break;
+            case 512: launch_plain_step<512>(ctx, p); break;
+            default: launch_plain_step<1024>(ctx, p); break;
+            }
+        }
+        ctx->last_steps += n;
+    }
+    HIPCHK(hipGetLastError());
+    return DC_OK;
+}
+
+size_t batched_lds(const dc_ctx *ctx) {
+    return step_lds_bytes(ctx->pc_batched, ctx->t.nsw, (size_t)(ctx->m.nc + 4) * ctx->N, 6 * (size_t)ctx->N);
+}
+
+int run_batched(dc_ctx *ctx, DevBatch &b, int bs) {
+    Params p = base_params(ctx, b, 0);
+    p.pc_cap = ctx->pc_batched;
+    const size_t lds = batched_lds(ctx);
+    switch (bs) {
+    case 256: hipLaunchKernelGGL((k_topsis_batched<256>), dim3(ctx->I), dim3(256), lds, ctx->stream, p); break;
+    case 512: hipLaunchKernelGGL((k_topsis_batched<512>), dim3(ctx->I), dim3(512), lds, ctx->stream, p); break;
+    default: hipLaunchKernelGGL((k_topsis_batched<1024>), dim3(ctx->I), dim3(1024), lds, ctx->stream, p); break;
+    }
+    HIPCHK(hipGetLastError());
+    ctx->last_launches += 1;
+    ctx->last_steps += b.Ct;   // upper bound: containers queued (steps stop at a rejection)
+    return DC_OK;
+}
+
+int collect(dc_ctx *ctx, DevBatch &b) {
+    std::vector<int> out(b.out_ints);
+    HIPCHK(hipMemcpyAsync(out.data(), b.dmem + b.in_ints, b.out_ints * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    b.host.assign(out.begin(), out.begin() + b.Ct);
+    b.code.assign(out.begin() + b.Ct, out.begin() + b.Ct + b.Pt);
+    b.failat.assign(out.begin() + b.Ct + b.Pt, out.begin() + b.Ct + b.Pt + b.R);
+    b.status.assign(out.begin() + b.Ct + b.Pt + b.R, out.begin() + b.Ct + b.Pt + 2 * b.R);
+    b.score.resize(b.Ct);
+    std::memcpy(b.score.data(), out.data() + b.Ct + b.Pt + 2 * b.R, sizeof(float) * b.Ct);
+    b.tsb.resize(b.R);
+    b.tse.resize(b.R);
+    const long long *ts = reinterpret_cast<const long long *>(b.view.tsb);
+    const size_t o_ts = (size_t)(reinterpret_cast<const int *>(ts) - (b.dmem + b.in_ints));
+    std::memcpy(b.tsb.data(), out.data() + o_ts, sizeof(long long) * b.R);
+    std::memcpy(b.tse.data(), out.data() + o_ts + 2 * (size_t)b.R, sizeof(long long) * b.R);
+    // results in request id order
+    std::vector<int> order(b.R);
+    for (int r = 0; r < b.R; ++r) order[r] = r;
+    std::sort(order.begin(), order.end(), [&](int a, int c) { return b.ids[a] < b.ids[c]; });
+    for (int r : order) {
+        dc_result res;
+        std::memset(&res, 0, sizeof res);
+        res.req_id = b.ids[r];
+        res.instance = b.inst[r];
+        res.status = b.status[r];
+        res.n = b.coff[r + 1] - b.coff[r];
+        res.failed_at = b.status[r] ? -1 : b.failat[r];
+        for (int i = 0; i < DC_MAX_CONTAINERS; ++i) res.host[i] = -1;
+        for (int i = 0; i < res.n; ++i) {
+            res.host[i] = b.host[b.coff[r] + i];
+            res.score[i] = b.score[b.coff[r] + i];
+        }
+        ctx->ready.push_back(res);
+    }
+    return DC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *dc_strerror(int code) {
+    switch (code) {
+    case DC_OK: return "ok";
+    case DC_EINVAL: return "invalid argument";
+    case DC_ENOMEM: return "out of memory";
+    case DC_EAGAIN: return "memory budget full, retry later";
+    case DC_ENOENT: return "unknown or not accepted request";
+    case DC_EDEVICE: return "device error (context poisoned)";
+    case DC_ESTATE: return "call not valid in this mode or state";
+    default: return "unknown error";
+    }
+}
+
+int dc_create(const dc_config *cfg, dc_ctx **out) {
+    if (!out) return DC_EINVAL;
+    *out = nullptr;
+    int rc = check_config(cfg);
+    if (rc) return rc;
+    if (cfg->mode == DC_MODE_SERVING) return DC_ESTATE;   // served by dc_serve_* (see serving form)
+    const int k = cfg->k, h = k / 2, N = k * k * k / 4, I = cfg->n_instances;
+    // background load must stay within capacity
+    if (cfg->host_used)
+        for (long long x = 0; x < (long long)I * 2 * N; ++x) {
+            const int cap = ((x / N) % 2) ? cfg->host_ram : cfg->host_cpu;
+            if (cfg->host_used[x] < 0 || cfg->host_used[x] > cap) return DC_EINVAL;
+        }
+    if (cfg->link_used)
+        for (long long x = 0; x < (long long)I * 3 * N; ++x) {
+            const int lvl = (int)((x / N) % 3);
+            const int cap = lvl == 0 ? cfg->bw_host_edge : lvl == 1 ? cfg->bw_edge_agg : cfg->bw_agg_core;
+            if (cfg->link_used[x] < 0 || cfg->link_used[x] > cap) return DC_EINVAL;
+        }
+    auto ctx = std::make_unique<dc_ctx>();
+    ctx->cfg = *cfg;
+    ctx->cfg.host_used = nullptr;
+    ctx->cfg.link_used = nullptr;
+    ctx->t = Topo{k, h, h * h, N, k * k / 2};
+    ctx->N = N;
+    ctx->I = I;
+    ctx->m.method = cfg->method;
+    ctx->m.scale = cfg->ahp_scale;
+    ctx->m.nc = cfg->ncrit;
+    for (int c = 0; c < DC_MAX_CRIT; ++c) {
+        ctx->m.crit[c] = c < cfg->ncrit ? cfg->crit[c] : 0;
+        ctx->m.cost[c] = c < cfg->ncrit ? (cfg->crit_cost[c] != 0) : 0;
+        ctx->m.w[c] = c < cfg->ncrit ? cfg->weight[c] : 0.f;
+    }
+    dc_ctx *c = ctx.get();
+    if (cfg->stream) {
+        c->stream = static_cast<hipStream_t>(cfg->stream);
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) return DC_EDEVICE;
+        c->own_stream = true;
+    }
+    // initial state
+    std::vector<int> init((size_t)I * 6 * N);
+    for (int i = 0; i < I; ++i) {
+        int *s = init.data() + (size_t)i * 6 * N;
+        for (int u = 0; u < N; ++u) {
+            s[u] = cfg->host_cpu - (cfg->host_used ? cfg->host_used[((size_t)i * 2) * N + u] : 0);
+            s[N + u] = cfg->host_ram - (cfg->host_used ? cfg->host_used[((size_t)i * 2 + 1) * N + u] : 0);
+            s[2 * N + u] = 0;
+            const int caps[3] = {cfg->bw_host_edge, cfg->bw_edge_agg, cfg->bw_agg_core};
+            for (int l = 0; l < 3; ++l)
+                s[(3 + l) * N + u] = caps[l] - (cfg->link_used ? cfg->link_used[((size_t)i * 3 + l) * N + u] : 0);
+        }
+    }
+    const size_t sbytes = init.size() * sizeof(int);
+    if (hipMalloc(&c->d_state, sbytes) != hipSuccess || hipMalloc(&c->d_init, sbytes) != hipSuccess) {
+        dc_destroy(ctx.release());
+        return DC_ENOMEM;
+    }
+    if (hipMemcpy(c->d_init, init.data(), sbytes, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_state, init.data(), sbytes, hipMemcpyHostToDevice) != hipSuccess) {
+        c->poisoned = true;
+        dc_destroy(ctx.release());
+        return DC_EDEVICE;
+    }
+    const int nc = cfg->ncrit;
+    if (hipMalloc(&c->d_xs, (size_t)I * (nc + 4) * N * sizeof(int)) != hipSuccess) {
+        dc_destroy(ctx.release());
+        return DC_ENOMEM;
+    }
+    // launch shapes
+    c->plain_bs = cfg->block ? cfg->block : (N <= 64 ? 64 : N <= 256 ? 256 : 1024);
+    c->batched_bs = cfg->block ? std::max(256, cfg->block) : 1024;
+    const size_t table_budget = 64 * 1024;
+    c->pc_plain = (int)std::max<size_t>(1, std::min<size_t>(kMaxN, table_budget / (8 * (size_t)c->t.nsw)));
+    const size_t xs_bytes = (size_t)(nc + 4) * N * sizeof(int);
+    c->xs_lds = xs_bytes <= 48 * 1024;
+    c->lds_plain = step_lds_bytes(c->pc_plain, c->t.nsw, c->xs_lds ? (size_t)(nc + 4) * N : 0, 0);
+    c->lds_select = step_lds_bytes(0, c->t.nsw, 0, 0);
+    if (cfg->mode == DC_MODE_BATCHED) {
+        const size_t lds_max = 160 * 1024;
+        const size_t fixed = step_lds_bytes(0, c->t.nsw, (size_t)(nc + 4) * N, 6 * (size_t)N);
+        if (fixed + 8 * (size_t)c->t.nsw > lds_max) { dc_destroy(ctx.release()); return DC_EINVAL; }
+        c->pc_batched = (int)std::min<size_t>(kMaxN, (lds_max - fixed) / (8 * (size_t)c->t.nsw));
+        const size_t lb = batched_lds(c);
+        if (set_lds(c, k_topsis_batched<256>, lb) || set_lds(c, k_topsis_batched<512>, lb) ||
+            set_lds(c, k_topsis_batched<1024>, lb)) { dc_destroy(ctx.release()); return DC_EDEVICE; }
+    }
+    if (set_lds(c, k_topsis_plain<64, true>, c->lds_plain) || set_lds(c, k_topsis_plain<64, false>, c->lds_plain) ||
+        set_lds(c, k_topsis_plain<256, true>, c->lds_plain) || set_lds(c, k_topsis_plain<256, false>, c->lds_plain) ||
+        set_lds(c, k_topsis_plain<512, true>, c->lds_plain) || set_lds(c, k_topsis_plain<512, false>, c->lds_plain) ||
+        set_lds(c, k_topsis_plain<1024, true>, c->lds_plain) || set_lds(c, k_topsis_plain<1024, false>, c->lds_plain)) {
+        dc_destroy(ctx.release());
+        return DC_EDEVICE;
+    }
+    if (cfg->method == DC_AHP) {
+        const int bx = (N + kAhpBlock - 1) / kAhpBlock;
+        c->tj = std::min(N, 512);
+        c->nJ = (N + c->tj - 1) / c->tj;
+        c->nI = std::max(1, std::min(bx * 4, (2048 + bx * nc - 1) / (bx * nc)));
+        c->ti = (N + c->nI - 1) / c->nI;
+        c->nI = (N + c->ti - 1) / c->ti;
+        if (hipMalloc(&c->d_colpart, (size_t)nc * c->nI * N * sizeof(int)) != hipSuccess ||
+            hipMalloc(&c->d_rowpart, (size_t)nc * c->nJ * N * sizeof(float)) != hipSuccess) {
+            dc_destroy(ctx.release());
+            return DC_ENOMEM;
+        }
+    }
+    if (cfg->trace_stride > 0 && cfg->trace_cap > 0) {
+        if (hipMalloc(&c->d_tmeta, (size_t)cfg->trace_cap * 4 * sizeof(int)) != hipSuccess ||
+            hipMalloc(&c->d_tscore, (size_t)cfg->trace_cap * N * sizeof(float)) != hipSuccess ||
+            hipMalloc(&c->d_tcount, (size_t)I * sizeof(int)) != hipSuccess) {
+            dc_destroy(ctx.release());
+            return DC_ENOMEM;
+        }
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, c->stream, c->d_tcount, 0, (long long)I);
+    }
+    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        c->poisoned = true;
+        dc_destroy(ctx.release());
+        return DC_EDEVICE;
+    }
+    *out = ctx.release();
+    return DC_OK;
+}
+
+int dc_submit_request(dc_ctx *ctx, int32_t instance, int32_t n, const int32_t *cpu, const int32_t *ram,
+                      int32_t m, const int32_t *edges, const int32_t *pod, int64_t *req_id) {
+    if (!ctx) return DC_EINVAL;
+    if (ctx->poisoned) return DC_EDEVICE;
+    if (instance < 0 || instance >= ctx->I || n < 1 || n > DC_MAX_CONTAINERS || !cpu || !ram) return DC_EINVAL;
+    if (m < 0 || m > n * (n - 1) / 2 || (m > 0 && !edges) || pod) return DC_EINVAL;
+    std::vector<char> seen((size_t)n * n, 0);
+    for (int q = 0; q < m; ++q) {
+        const int i = edges[3 * q], j = edges[3 * q + 1], bw = edges[3 * q + 2];
+        if (i < 0 || j < 0 || i >= n || j >= n || i == j || bw <= 0 || bw > (1 << 22)) return DC_EINVAL;
+        if (seen[(size_t)i * n + j]) return DC_EINVAL;
+        seen[(size_t)i * n + j] = seen[(size_t)j * n + i] = 1;
+    }
+    for (int i = 0; i < n; ++i)
+        if (cpu[i] < 0 || ram[i] < 0 || cpu[i] > (1 << 22) || ram[i] > (1 << 22)) return DC_EINVAL;
+    ctx->pend_inst.push_back(instance);
+    ctx->pend_n.push_back(n);
+    ctx->pend_cpu.emplace_back(cpu, cpu + n);
+    ctx->pend_ram.emplace_back(ram, ram + n);
+    ctx->pend_edges.emplace_back(edges, edges + 3 * (size_t)m);
+    const int64_t id = ctx->next_id++;
+    ctx->pend_ids.push_back(id);
+    if (req_id) *req_id = id;
+    return DC_OK;
+}
+
+int dc_schedule(dc_ctx *ctx, int32_t max_results, dc_result *out, int32_t *n_out) {
+    if (!ctx || max_results < 0 || (max_results > 0 && !out)) return DC_EINVAL;
+    if (ctx->poisoned) return DC_EDEVICE;
+    int rc = upload_pending(ctx);
+    if (rc) return rc;
+    if (!ctx->queued.empty()) {
+        ctx->last_launches = 0;
+        ctx->last_steps = 0;
+        HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
+        for (int bi : ctx->queued) {
+            DevBatch &b = *ctx->batches[bi];
+            rc = ctx->cfg.mode == DC_MODE_BATCHED ? run_batched(ctx, b, ctx->batched_bs) : run_plain(ctx, b);
+            if (rc) return rc;
+        }
+        HIPCHK(hipEventRecord(ctx->ev1, ctx->stream));
+        for (int bi : ctx->queued) {
+            rc = collect(ctx, *ctx->batches[bi]);
+            if (rc) return rc;
+        }
+        HIPCHK(hipEventElapsedTime(&ctx->last_ms, ctx->ev0, ctx->ev1));
+        ctx->queued.clear();
+    }
+    int k = 0;
+    while (k < max_results && !ctx->ready.empty()) {
+        out[k++] = ctx->ready.front();
+        ctx->ready.pop_front();
+    }
+    if (n_out) *n_out = k;
+    return DC_OK;
+}
+
+int dc_release(dc_ctx *ctx, int64_t req_id) {
+    if (!ctx) return DC_EINVAL;
+    if (ctx->poisoned) return DC_EDEVICE;
+    auto it = ctx->loc.find(req_id);
+    if (it == ctx->loc.end() || it->second.released) return DC_ENOENT;
+    DevBatch &b = *ctx->batches[it->second.batch];
+    const int r = it->second.r;
+    for (int bi : ctx->queued)
+        if (bi == it->second.batch) return DC_ENOENT;   // not scheduled yet
+    if ((int)b.status.size() <= r || b.status[r] != 1) return DC_ENOENT;
+    Params p = base_params(ctx, b, b.inst[r]);
+    p.r = r;
+    hipLaunchKernelGGL((k_release<256>), dim3(1), dim3(256), 0, ctx->stream, p);
+    HIPCHK(hipGetLastError());
+    it->second.released = true;
+    return DC_OK;
+}
+
+int dc_get_paths(dc_ctx *ctx, int64_t req_id, int32_t cap, int32_t *link_ids, int32_t *n) {
+    if (!ctx || cap < 0 || (cap > 0 && !link_ids)) return DC_EINVAL;
+    auto it = ctx->loc.find(req_id);
+    if (it == ctx->loc.end()) return DC_ENOENT;
+    DevBatch &b = *ctx->batches[it->second.batch];
+    const int r = it->second.r;
+    if ((int)b.status.size() <= r || b.status[r] != 1) return DC_ENOENT;
+    const int g0 = b.coff[r], g1 = b.coff[r + 1];
+    int q = 0;
+    for (int g = g0; g < g1; ++g)
+        for (int x = b.poff[g]; x < b.poff[g + 1]; ++x, ++q) {
+            if (q >= cap) continue;
+            int *dst = link_ids + 6 * (size_t)q;
+            for (int l = 0; l < 6; ++l) dst[l] = -1;
+            const int u = b.host[g], v = b.host[g0 + b.pj[x]];
+            if (u != v && b.code[x] >= 0) host_path_links(ctx->t, u, v, b.code[x], dst);
+        }
+    if (n) *n = q;
+    return DC_OK;
+}
+
+int dc_get_attempt(dc_ctx *ctx, int64_t req_id, int32_t cap, int32_t *hosts, int32_t *n) {
+    if (!ctx || cap < 0 || (cap > 0 && !hosts)) return DC_EINVAL;
+    auto it = ctx->loc.find(req_id);
+    if (it == ctx->loc.end()) return DC_ENOENT;
+    DevBatch &b = *ctx->batches[it->second.batch];
+    const int r = it->second.r;
+    if ((int)b.status.size() <= r) return DC_ENOENT;
+    const int g0 = b.coff[r], cnt = b.coff[r + 1] - g0;
+    for (int i = 0; i < cnt && i < cap; ++i) hosts[i] = b.host[g0 + i];
+    if (n) *n = cnt;
+    return DC_OK;
+}
+
+int dc_get_latency(dc_ctx *ctx, int32_t cap, float *service_us, int32_t *n) {
+    if (!ctx || cap < 0 || (cap > 0 && !service_us)) return DC_EINVAL;
+    std::vector<std::pair<int64_t, float>> v;
+    for (auto &B : ctx->batches) {
+        const DevBatch &b = *B;
+        for (int r = 0; r < (int)b.tse.size(); ++r)
+            v.emplace_back(b.ids[r], (float)((b.tse[r] - b.tsb[r]) / 100.0));   // 100 MHz clock
+    }
+    std::sort(v.begin(), v.end());
+    int k = 0;
+    for (; k < (int)v.size() && k < cap; ++k) service_us[k] = v[k].second;
+    if (n) *n = (int)v.size();
+    return DC_OK;
+}
+
+int dc_get_state(dc_ctx *ctx, int32_t instance, int32_t *out) {
+    if (!ctx || !out || instance < 0 || instance >= ctx->I) return DC_EINVAL;
+    if (ctx->poisoned) return DC_EDEVICE;
+    HIPCHK(hipMemcpyAsync(out, ctx->d_state + (size_t)instance * 6 * ctx->N, 6 * (size_t)ctx->N * sizeof(int),
+                          hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return DC_OK;
+}
+
+int dc_rewind(dc_ctx *ctx) {
+    if (!ctx) return DC_EINVAL;
+    if (ctx->poisoned) return DC_EDEVICE;
+    int rc = upload_pending(ctx);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(ctx->d_state, ctx->d_init, (size_t)ctx->I * 6 * ctx->N * sizeof(int),
+                          hipMemcpyDeviceToDevice, ctx->stream));
+    if (ctx->d_tcount)
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, ctx->stream, ctx->d_tcount, 0, (long long)ctx->I);
+    ctx->queued.clear();
+    for (size_t bi = 0; bi < ctx->batches.size(); ++bi) {
+        rc = reset_outputs(ctx, *ctx->batches[bi]);
+        if (rc) return rc;
+        ctx->queued.push_back((int)bi);
+        for (int64_t id : ctx->batches[bi]->ids) ctx->loc[id].released = false;
+    }
+    ctx->ready.clear();
+    return DC_OK;
+}
+
+int dc_get_trace(dc_ctx *ctx, int32_t cap, int32_t *meta, float *scores, int32_t *n) {
+    if (!ctx || cap < 0) return DC_EINVAL;
+    if (!ctx->d_tmeta) { if (n) *n = 0; return DC_OK; }
+    std::vector<int> cnt(ctx->I);
+    HIPCHK(hipMemcpyAsync(cnt.data(), ctx->d_tcount, ctx->I * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    long long steps = 0;
+    for (int v : cnt) steps = std::max<long long>(steps, v);
+    int rec = (int)std::min<long long>(ctx->cfg.trace_cap, (steps + ctx->cfg.trace_stride - 1) / ctx->cfg.trace_stride);
+    if (ctx->I > 1) rec = 0;   // per-instance counters share slots; recording is meant for one instance
+    rec = std::min(rec, cap);
+    if (rec > 0) {
+        if (meta) HIPCHK(hipMemcpy(meta, ctx->d_tmeta, (size_t)rec * 4 * sizeof(int), hipMemcpyDeviceToHost));
+        if (scores) HIPCHK(hipMemcpy(scores, ctx->d_tscore, (size_t)rec * ctx->N * sizeof(float), hipMemcpyDeviceToHost));
+    }
+    if (n) *n = rec;
+    return DC_OK;
+}
+
+int dc_autotune(dc_ctx *ctx, int32_t *block) {
+    if (!ctx) return DC_EINVAL;
+    if (ctx->poisoned) return DC_EDEVICE;
+    if (ctx->cfg.mode != DC_MODE_BATCHED) return DC_ESTATE;
+    int rc = upload_pending(ctx);
+    if (rc) return rc;
+    if (ctx->queued.empty()) return DC_ESTATE;
+    const size_t sbytes = (size_t)ctx->I * 6 * ctx->N * sizeof(int);
+    int *saved = nullptr;
+    HIPCHK(hipMalloc(&saved, sbytes));
+    HIPCHK(hipMemcpyAsync(saved, ctx->d_state, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
+    const int cand[3] = {256, 512, 1024};
+    float best_ms = 1e30f;
+    int best = ctx->batched_bs;
+    for (int bs : cand) {
+        for (int rep = 0; rep < 2; ++rep) {   // first run warms up
+            HIPCHK(hipMemcpyAsync(ctx->d_state, saved, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
+            for (int bi : ctx->queued) if ((rc = reset_outputs(ctx, *ctx->batches[bi]))) return rc;
+            HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
+            for (int bi : ctx->queued) if ((rc = run_batched(ctx, *ctx->batches[bi], bs))) return rc;
+            HIPCHK(hipEventRecord(ctx->ev1, ctx->stream));
+            HIPCHK(hipEventSynchronize(ctx->ev1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+            if (rep == 1 && ms < best_ms) { best_ms = ms; best = bs; }
+        }
+    }
+    HIPCHK(hipMemcpyAsync(ctx->d_state, saved, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
+    for (int bi : ctx->queued) if ((rc = reset_outputs(ctx, *ctx->batches[bi]))) return rc;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipFree(saved));
+    ctx->batched_bs = best;
+    if (block) *block = best;
+    return DC_OK;
+}
+
+int dc_last_timing(dc_ctx *ctx, float *ms, int64_t *launches, int64_t *steps) {
+    if (!ctx) return DC_EINVAL;
+    if (ms) *ms = ctx->last_ms;
+    if (launches) *launches = ctx->last_launches;
+    if (steps) *steps = ctx->last_steps;
+    return DC_OK;
+}
+
+void dc_destroy(dc_ctx *ctx) {
+    if (!ctx) return;
+    if (!ctx->poisoned && ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    for (auto &b : ctx->batches)
+        if (b->dmem) (void)hipFree(b->dmem);
+    int *ptrs[] = {ctx->d_state, ctx->d_init, ctx->d_xs, ctx->d_colpart, ctx->d_tmeta, ctx->d_tcount};
+    for (int *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (ctx->d_rowpart) (void)hipFree(ctx->d_rowpart);
+    if (ctx->d_tscore) (void)hipFree(ctx->d_tscore);
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+}  // extern "C"

@@ -1,0 +1,94 @@
+"""Lockstep parity between the GPU library and the FP64 oracle.
+
+The oracle replays every request and, at each container step, follows the
+server the GPU chose.  It checks that choice against its own ranking:
+equal to the oracle's best commit-successful server whenever the oracle's
+top-two score gap exceeds the tolerance, otherwise scored within the
+tolerance of the best.  The integer state (CPU, RAM, placed counts, link
+residuals) must then be identical after every request.  Recorded GPU
+score vectors are compared element by element with the oracle's.
+"""
+import numpy as np
+
+import oracle as O
+
+TOL = 1e-5   # relative score tolerance for FP32 scores against FP64
+
+
+def gpu_follow(sched, rid, res):
+    """Servers the GPU gave each container; -1 from the failing step on."""
+    follow = sched.attempt(rid).copy()
+    if res.status == 0:
+        follow[res.failed_at:] = -1
+    return follow
+
+
+def check_scores(gpu, ref, tol=TOL, where=""):
+    """|s_gpu - s_ref| <= tol * max|s_ref| everywhere, and relative error
+    <= tol where s_ref >= 1e-3 * max."""
+    gpu = np.asarray(gpu, np.float64)
+    ref = np.asarray(ref, np.float64)
+    top = float(np.max(np.abs(ref))) if ref.size else 0.0
+    scale = max(top, 1e-30)
+    err = np.abs(gpu - ref)
+    assert np.all(err <= tol * scale), f"{where}: max abs err {err.max():.3e} vs {tol * scale:.3e}"
+    big = (np.abs(ref) >= 1e-3 * top) & (ref != 0)
+    if big.any():
+        rel = err[big] / np.abs(ref[big])
+        assert np.all(rel <= tol), f"{where}: max rel err {rel.max():.3e}"
+
+
+def lockstep(o, sched, ids, reqs, results, tol=TOL, trace=None, check_paths=False, state_every=False,
+             instance=0):
+    """Replays `reqs` (submitted to `sched` with ids `ids`, results keyed by
+    id) on oracle `o` in lockstep.  trace: optional dict (request position ->
+    list of (container, gpu score vector)).  Returns statistics."""
+    st = dict(requests=0, accepted=0, rejected=0, steps=0, near_tie=0, scored_steps=0)
+    for pos, (rid, req) in enumerate(zip(ids, reqs)):
+        g = results[rid]
+        follow = gpu_follow(sched, rid, g)
+        want_dump = trace is not None and pos in trace
+        ref = o.run_request(req, follow=follow, detail=True, dump=want_dump)
+        assert ref["status"] == g.status, f"request {pos}: oracle status {ref['status']} vs gpu {g.status}"
+        steps = g.n if g.status == 1 else g.failed_at + 1
+        for i in range(steps):
+            if follow[i] < 0:
+                assert ref["ref_host"][i] < 0, f"request {pos} step {i}: oracle found a server"
+                continue
+            top = ref["ref_top"][i]
+            if follow[i] != ref["ref_host"][i]:
+                st["near_tie"] += 1
+                assert ref["ref_gap"][i] <= tol * max(abs(top), 1e-30), (
+                    f"request {pos} step {i}: gpu {follow[i]} vs oracle {ref['ref_host'][i]}, "
+                    f"gap {ref['ref_gap'][i]:.3e} top {top:.6f}")
+                assert ref["scores"][i] >= top - tol * max(abs(top), 1e-30)
+            if g.status == 1:
+                assert abs(float(g.scores[i]) - ref["scores"][i]) <= tol * max(abs(top), 1e-30), (
+                    f"request {pos} step {i}: score {g.scores[i]} vs {ref['scores'][i]}")
+        if want_dump:
+            for i, vec in trace[pos]:
+                check_scores(vec, ref["dump"][i], tol, where=f"request {pos} step {i}")
+                st["scored_steps"] += 1
+        if check_paths and g.status == 1:
+            got = sched.paths(rid)
+            want, _ = o.paths(ref["rec_id"])
+            assert got.shape == want.shape
+            for a, b in zip(got, want):
+                assert sorted(a.tolist()) == sorted(b.tolist())
+        if state_every:
+            np.testing.assert_array_equal(sched.state(instance), o.state(), err_msg=f"after request {pos}")
+        st["requests"] += 1
+        st["accepted"] += g.status == 1
+        st["rejected"] += g.status == 0
+        st["steps"] += steps
+    np.testing.assert_array_equal(sched.state(instance), o.state())
+    return st
+
+
+def trace_by_request(sched, ids_in_batch_order):
+    """GPU trace grouped by request position: {pos: [(container, scores)]}."""
+    meta, scores = sched.trace()
+    out = {}
+    for (inst, r, i, s), vec in zip(meta, scores):
+        out.setdefault(int(r), []).append((int(i), vec))
+    return out

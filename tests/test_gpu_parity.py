@@ -1,0 +1,238 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle, in
+lockstep, on seeded synthetic fat-trees of the paper's shape."""
+import numpy as np
+import pytest
+
+import oracle as O
+from parity import lockstep, trace_by_request, TOL
+from workloads import make_config, make_instance, make_requests, Request
+
+pytestmark = pytest.mark.gpu
+
+dc = pytest.importorskip("paper_1909_07673_amd")
+
+C5 = (dc.DC_CRIT_CPU, dc.DC_CRIT_RAM, dc.DC_CRIT_UPLINK, dc.DC_CRIT_PATHBW, dc.DC_CRIT_HOPS)
+C5_COST = (0, 0, 0, 0, 1)
+
+
+def _omethod(method, crit=None, cost=None, scale=O.SAATY9):
+    if crit is None:
+        return O.method(kind=method, scale=scale)
+    return O.method(kind=method, crit=crit, cost=list(cost), scale=scale)
+
+
+def _run(insts, reqs, method=dc.DC_TOPSIS, mode=dc.DC_MODE_PLAIN, trace_stride=0, trace_cap=0, **kw):
+    s = dc.Scheduler(insts, method=method, mode=mode, trace_stride=trace_stride, trace_cap=trace_cap, **kw)
+    ids = [[s.submit(r, instance=i) for r in rl] for i, rl in enumerate(reqs)]
+    res = {r.req_id: r for r in s.schedule()}
+    return s, ids, res
+
+
+@pytest.mark.parametrize("method", [dc.DC_TOPSIS, dc.DC_AHP])
+def test_tiny_lockstep_many_seeds(method):
+    """k=4, 16 hosts, no background, 20 requests of 2-6 containers: every
+    step's score vector and every placement against the oracle."""
+    tot = dict(steps=0, near_tie=0, rejected=0)
+    for seed in range(40):
+        insts, reqs = make_config("tiny", seed=seed)
+        s, ids, res = _run(insts, reqs, method=method, trace_stride=1, trace_cap=4096)
+        o = O.Oracle(insts[0], _omethod(method))
+        st = lockstep(o, s, ids[0], reqs[0], res, trace=trace_by_request(s, ids[0]), check_paths=True,
+                      state_every=True)
+        assert st["scored_steps"] == st["steps"]
+        for k in tot:
+            tot[k] += st[k]
+        s.close()
+    assert tot["steps"] > 1000
+    # exact ties (identical servers) must resolve to the lowest index on both
+    # sides; near-ties in general are rare
+    assert tot["near_tie"] <= tot["steps"] // 100
+
+
+def test_plain_k16_prefix_every_step():
+    """k=16 (1024 hosts), 0-70 % background: first 250 requests, every
+    step's score vector compared."""
+    insts, reqs = make_config("plain", seed=3, n_req=250)
+    s, ids, res = _run(insts, reqs, trace_stride=1, trace_cap=8192)
+    o = O.Oracle(insts[0], _omethod(O.TOPSIS))
+    st = lockstep(o, s, ids[0], reqs[0], res, trace=trace_by_request(s, ids[0]), check_paths=True)
+    assert st["scored_steps"] == st["steps"] and st["steps"] > 2000
+    assert st["accepted"] > 100
+
+
+def test_plain_k16_full_size_sampled():
+    """The full 2,000-request k=16 workload in the launch configuration the
+    benchmark times: placements and state in lockstep for every request,
+    score vectors on every 37th step."""
+    insts, reqs = make_config("plain", seed=0)
+    s, ids, res = _run(insts, reqs, trace_stride=37, trace_cap=4096)
+    o = O.Oracle(insts[0], _omethod(O.TOPSIS))
+    st = lockstep(o, s, ids[0], reqs[0], res, trace=trace_by_request(s, ids[0]))
+    assert st["requests"] == 2000 and st["scored_steps"] > 300
+    assert st["rejected"] > 0 and st["accepted"] > 0
+
+
+def test_ahp_k16_every_step():
+    insts, reqs = make_config("plain", seed=5, n_req=12)
+    s, ids, res = _run(insts, reqs, method=dc.DC_AHP, trace_stride=1, trace_cap=1024)
+    o = O.Oracle(insts[0], _omethod(O.AHP))
+    st = lockstep(o, s, ids[0], reqs[0], res, trace=trace_by_request(s, ids[0]), check_paths=True)
+    assert st["scored_steps"] == st["steps"] > 50
+
+
+def test_ahp_k32_five_criteria_sampled():
+    """The large AHP shape: k=32 (8192 hosts), criteria CPU, RAM, uplink,
+    path bandwidth, hops (cost), Saaty 1-9 scale; one request, every step."""
+    insts, reqs = make_config("ahp", seed=0, n_req=1)
+    req = reqs[0][0]
+    req = Request(req.cpu[:6].copy(), req.ram[:6].copy(),
+                  np.array([e for e in req.edges if e[0] < 6 and e[1] < 6], np.int32).reshape(-1, 3))
+    s, ids, res = _run(insts, [[req]], method=dc.DC_AHP, crit=C5, cost=C5_COST, trace_stride=1, trace_cap=64)
+    o = O.Oracle(insts[0], _omethod(O.AHP, crit=C5, cost=C5_COST))
+    st = lockstep(o, s, ids[0], [req], res, trace=trace_by_request(s, ids[0]), check_paths=True)
+    assert st["scored_steps"] == st["steps"] == 6
+
+
+def test_ahp_ratio_scale_priorities():
+    """Ratio-scale AHP (consistent matrices): PG equals sum_c w_c v_c / sum(v_c)."""
+    insts, reqs = make_config("tiny", seed=9)
+    reqs = [reqs[0][:4]]          # few requests: every value stays positive
+    s, ids, res = _run(insts, reqs, method=dc.DC_AHP, ahp_scale=dc.DC_AHP_RATIO,
+                       crit=(dc.DC_CRIT_CPU, dc.DC_CRIT_RAM), trace_stride=1, trace_cap=512)
+    o = O.Oracle(insts[0], O.method(kind=O.AHP, crit=(O.CRIT_CPU, O.CRIT_RAM), scale=O.RATIO))
+    lockstep(o, s, ids[0], reqs[0], res, trace=trace_by_request(s, ids[0]))
+
+
+def test_topsis_five_criteria_with_cost():
+    insts, reqs = make_config("plain", seed=4, n_req=80)
+    s, ids, res = _run(insts, reqs, crit=C5, cost=C5_COST, trace_stride=3, trace_cap=4096)
+    o = O.Oracle(insts[0], _omethod(O.TOPSIS, crit=C5, cost=C5_COST))
+    lockstep(o, s, ids[0], reqs[0], res, trace=trace_by_request(s, ids[0]), check_paths=True)
+
+
+def test_topsis_clustering_weights():
+    """Table IV 'Clustering' weights (0.17, 0.17, 0.5, 0.16)."""
+    w = (0.17, 0.17, 0.5, 0.16)
+    insts, reqs = make_config("plain", seed=6, n_req=80)
+    s, ids, res = _run(insts, reqs, weight=w, trace_stride=5, trace_cap=4096)
+    o = O.Oracle(insts[0], O.method(kind=O.TOPSIS, weight=list(w)))
+    lockstep(o, s, ids[0], reqs[0], res, trace=trace_by_request(s, ids[0]))
+
+
+def test_batched_matches_oracle_and_plain():
+    """Batched form (one persistent launch, state in LDS) against the oracle
+    per instance, and bit-identical to the plain form on each instance."""
+    insts, reqs = make_config("batched", seed=2, instances=6, n_req=40)
+    s, ids, res = _run(insts, reqs, mode=dc.DC_MODE_BATCHED)
+    for i in range(len(insts)):
+        o = O.Oracle(insts[i], _omethod(O.TOPSIS))
+        lockstep(o, s, ids[i], reqs[i], res, instance=i, check_paths=True)
+        p, pids, pres = _run([insts[i]], [reqs[i]])
+        for a, b in zip(ids[i], pids[0]):
+            assert res[a].status == pres[b].status
+            np.testing.assert_array_equal(res[a].hosts, pres[b].hosts)
+            np.testing.assert_array_equal(res[a].scores, pres[b].scores)
+        np.testing.assert_array_equal(s.state(i), p.state(0))
+        p.close()
+
+
+def test_batched_256_instances_sampled():
+    """256 instances of k=16 with uneven request counts in one launch;
+    sampled instances replayed by the oracle."""
+    insts, reqs = make_config("batched", seed=4)
+    reqs = [rl[: 8 + (i % 5) * 6] for i, rl in enumerate(reqs)]
+    s, ids, res = _run(insts, reqs, mode=dc.DC_MODE_BATCHED)
+    for i in (0, 77, 128, 255):
+        o = O.Oracle(insts[i], _omethod(O.TOPSIS))
+        lockstep(o, s, ids[i], reqs[i], res, instance=i)
+    for i in range(len(insts)):
+        assert s.state(i).min() >= 0
+
+
+def test_autotune_keeps_results():
+    insts, reqs = make_config("batched", seed=8, instances=4, n_req=20)
+    s = dc.Scheduler(insts, mode=dc.DC_MODE_BATCHED)
+    ids = [[s.submit(r, instance=i) for r in rl] for i, rl in enumerate(reqs)]
+    bs = s.autotune()
+    assert bs in (256, 512, 1024)
+    res = {r.req_id: r for r in s.schedule()}
+    s.rewind()
+    res2 = {r.req_id: r for r in s.schedule()}
+    for k in res:
+        np.testing.assert_array_equal(res[k].hosts, res2[k].hosts)
+    for i in range(len(insts)):
+        o = O.Oracle(insts[i], _omethod(O.TOPSIS))
+        lockstep(o, s, ids[i], reqs[i], res2, instance=i)
+
+
+def test_release_restores_state_and_paths():
+    insts, reqs = make_config("plain", seed=7, n_req=150)
+    s, ids, res = _run(insts, reqs)
+    s0 = dc.Scheduler(insts).state(0)
+    o = O.Oracle(insts[0], _omethod(O.TOPSIS))
+    lockstep(o, s, ids[0], reqs[0], res, check_paths=True)
+    acc = [rid for rid in ids[0] if res[rid].status == 1]
+    rej = [rid for rid in ids[0] if res[rid].status == 0]
+    rng = np.random.default_rng(0)
+    for rid in rng.permutation(acc):
+        assert s.release(int(rid)) == dc.DC_OK
+    np.testing.assert_array_equal(s.state(0), s0)
+    assert s.release(int(acc[0])) == dc.DC_ENOENT
+    if rej:
+        assert s.release(int(rej[0])) == dc.DC_ENOENT
+    assert s.release(10 ** 9) == dc.DC_ENOENT
+
+
+def test_rewind_is_deterministic():
+    insts, reqs = make_config("plain", seed=11, n_req=300)
+    s, ids, res = _run(insts, reqs)
+    st1 = s.state(0)
+    s.rewind()
+    res2 = {r.req_id: r for r in s.schedule()}
+    np.testing.assert_array_equal(s.state(0), st1)
+    for k in res:
+        assert res[k].status == res2[k].status
+        np.testing.assert_array_equal(res[k].hosts, res2[k].hosts)
+        np.testing.assert_array_equal(res[k].scores.view(np.uint32), res2[k].scores.view(np.uint32))
+
+
+def test_edge_cases():
+    rng = np.random.default_rng(3)
+    inst = make_instance(4, 32, 256, 10000, 10000, 10000)
+    one = Request(np.array([4], np.int32), np.array([8], np.int32), np.zeros((0, 3), np.int32))
+    noedge = Request(np.array([1, 2, 3], np.int32), np.array([1, 1, 1], np.int32), np.zeros((0, 3), np.int32))
+    huge = Request(np.array([33], np.int32), np.array([1], np.int32), np.zeros((0, 3), np.int32))
+    fat = Request(np.array([1, 1], np.int32), np.array([1, 1], np.int32), np.array([[0, 1, 10001]], np.int32))
+    zero = Request(np.array([0, 0], np.int32), np.array([0, 0], np.int32), np.array([[0, 1, 5]], np.int32))
+    reqs = [one, noedge, huge, fat, zero] + make_requests(60, rng, 2, 6, cpu_hi=16)   # saturates k=4
+    s, ids, res = _run([inst], [reqs])
+    assert res[ids[0][2]].status == 0 and res[ids[0][2]].failed_at == 0
+    o = O.Oracle(inst, _omethod(O.TOPSIS))
+    st = lockstep(o, s, ids[0], reqs, res, check_paths=True, state_every=True)
+    assert st["rejected"] >= 5
+    # 64 containers on k=16
+    insts, _ = make_config("plain", seed=1, n_req=1)
+    big = make_requests(1, rng, 64, 64)[0]
+    s2, ids2, res2 = _run(insts, [[big]])
+    o2 = O.Oracle(insts[0], _omethod(O.TOPSIS))
+    lockstep(o2, s2, ids2[0], [big], res2, check_paths=True)
+
+
+def test_invalid_arguments():
+    inst = make_instance(4, 32, 256, 10000, 10000, 10000)
+    with pytest.raises(dc.DcError) as e:
+        dc.Scheduler([inst], weight=(0.5, 0.5, 0.5, 0.5))
+    assert e.value.code == dc.DC_EINVAL
+    with pytest.raises(dc.DcError):
+        dc.Scheduler([inst], method=dc.DC_AHP, mode=dc.DC_MODE_BATCHED)
+    s = dc.Scheduler([inst])
+    bad = [Request(np.ones(2, np.int32), np.ones(2, np.int32), np.array([[0, 0, 5]], np.int32)),
+           Request(np.ones(2, np.int32), np.ones(2, np.int32), np.array([[0, 1, 0]], np.int32)),
+           Request(np.ones(2, np.int32), np.ones(2, np.int32), np.array([[0, 1, 5], [1, 0, 5]], np.int32)),
+           Request(np.ones(65, np.int32), np.ones(65, np.int32), np.zeros((0, 3), np.int32))]
+    for r in bad:
+        with pytest.raises(dc.DcError) as e:
+            s.submit(r)
+        assert e.value.code == dc.DC_EINVAL
+    with pytest.raises(dc.DcError):
+        s.submit(bad[0], instance=3)
