@@ -98,7 +98,7 @@ def main():
         for r in rl:
             s.submit(r, instance=i)
     s.rewind()                      # uploads the requests; they stay resident in HBM
-    tuned = s.autotune() if mode == dc.DC_MODE_BATCHED else None
+    tuned = s.autotune()            # workgroup size picked by timing the candidates
     torch.cuda.synchronize()
 
     for _ in range(args.warmup):

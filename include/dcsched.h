@@ -160,14 +160,15 @@ int dc_get_state(dc_ctx *ctx, int32_t instance, int32_t *out);
 int dc_rewind(dc_ctx *ctx);
 
 /* Recorded score vectors (trace_stride > 0): meta[s][4] = (instance,
- * request index within its schedule call, container, global step number),
+ * request id (low 31 bits), container, global step number),
  * scores[s][N] float.  *n receives the number of recorded steps. */
 int dc_get_trace(dc_ctx *ctx, int32_t cap, int32_t *meta, float *scores, int32_t *n);
 
-/* Batched form: time every candidate tile shape on the queued workload (on
- * a scratch copy of the state), keep the fastest for later dc_schedule
- * calls, and return its workgroup size in *block.  The state and queue are
- * left unchanged. */
+/* Plain and batched forms: time every candidate workgroup size (256, 512,
+ * 1024 threads) on the queued workload (on a scratch copy of the state),
+ * keep the fastest for later dc_schedule calls, and return it in *block.
+ * The state and queue are left unchanged.  DC_ESTATE when nothing is
+ * queued or in the serving form. */
 int dc_autotune(dc_ctx *ctx, int32_t *block);
 
 /* Milliseconds the last dc_schedule spent on the device, measured with HIP

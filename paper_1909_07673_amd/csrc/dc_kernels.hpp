@@ -12,7 +12,7 @@ struct Params {
     Method m;
     Batch b;
     Trace tr;
-    int *xs;         // global host scratch [(nc+4)][N] of that instance
+    int *xs;         // global per-server scratch [nc+6][N] of that instance
     int pc_cap;      // peers per path-table chunk
     int inst;
     // batched form: state of instance i at state_base + i * state_stride
@@ -22,16 +22,26 @@ struct Params {
     int *colpart;    // [nc][nI][N]
     float *rowpart;  // [nc][nJ][N]
     int ti, tj, nI, nJ;
-    int r, i;        // request and container of a plain step
+    StepIn s;        // the container step of a plain launch
+    int pj[kMaxN], pbw[kMaxN];   // its placed peers (container index, demand)
 };
 
 constexpr int kAhpBlock = 256;
 constexpr int kAhpTile = 1024;   // values staged per LDS tile in the AHP passes
 constexpr int kAhpAcc = 8;       // independent partial sums per row in pass B
 
-// Dynamic LDS of the single-workgroup step.
+// Dynamic LDS of the single-workgroup step: fixed part, capacity sums and
+// peer tables, then optionally the criteria scratch xs and the state.
 inline size_t step_lds_bytes(int pc_cap, int nsw, size_t xs_ints, size_t state_ints) {
-    return smem_fixed_bytes() + sizeof(int) * (2 * (size_t)pc_cap * nsw + xs_ints + state_ints);
+    return smem_fixed_bytes() + sizeof(int) * (smem_var_ints(pc_cap, nsw) + xs_ints + state_ints);
+}
+
+// Rows of the per-server scratch: the criteria, the feasibility flag and
+// five accumulators kept across peer chunks.
+__host__ __device__ inline int xs_rows(int nc) { return nc + 6; }
+
+__device__ __forceinline__ int *lds_after_tables(char *dsm, int pc_cap, int nsw) {
+    return reinterpret_cast<int *>(dsm + smem_fixed_bytes() + sizeof(int) * smem_var_ints(pc_cap, nsw));
 }
 
 __device__ __forceinline__ State state_at(int *base, long long stride, int inst, int N) {
@@ -39,27 +49,68 @@ __device__ __forceinline__ State state_at(int *base, long long stride, int inst,
     return State{s, s + N, s + 2 * N, s + 3 * N, s + 4 * N, s + 5 * N};
 }
 
+// Copies n int32 (n % 4 == 0, 16-byte aligned) between global memory and
+// LDS in int4 pieces, four loads in flight per thread.
+template <int BS>
+__device__ __forceinline__ void stage_in(int *lds, const int *g, int n) {
+    const int4 *src = reinterpret_cast<const int4 *>(g);
+    int4 *dst = reinterpret_cast<int4 *>(lds);
+    const int n4 = n >> 2;
+    int x = threadIdx.x;
+    for (; x + 3 * BS < n4; x += 4 * BS) {
+        const int4 a = src[x], b = src[x + BS], c = src[x + 2 * BS], d = src[x + 3 * BS];
+        dst[x] = a; dst[x + BS] = b; dst[x + 2 * BS] = c; dst[x + 3 * BS] = d;
+    }
+    for (; x < n4; x += BS) dst[x] = src[x];
+}
+
+template <int BS>
+__device__ __forceinline__ void stage_out(int *g, const int *lds, int n) {
+    const int4 *src = reinterpret_cast<const int4 *>(lds);
+    int4 *dst = reinterpret_cast<int4 *>(g);
+    for (int x = threadIdx.x; x < (n >> 2); x += BS) dst[x] = src[x];
+}
+
 // ---------------------------------------------------------------- plain form
-// One launch per container step, one workgroup; xs in LDS when XL.
-template <int BS, bool XL>
+// The plain form passes the container's peer list in the kernel arguments,
+// so only the peers' servers are read from memory.
+__device__ __forceinline__ ReqView plain_view(const Params &p) {
+    return ReqView{p.pj, p.pbw, p.b.host + p.s.g0, nullptr};
+}
+
+// One launch per container step, one workgroup.  With RES the instance's
+// state (6N int32) is staged into LDS for the step and written back, and
+// the criteria scratch lives in LDS too; otherwise both stay in HBM/L2.
+template <int BS, bool RES>
 __global__ __launch_bounds__(BS) void k_topsis_plain(Params p) {
     extern __shared__ __align__(16) char dsm[];
+    if (p.b.status[p.s.r] == 0) return;        // request already rejected
     Smem sm = carve(dsm, p.pc_cap, p.t.nsw);
-    int *xs = XL ? reinterpret_cast<int *>(dsm + smem_fixed_bytes() + sizeof(int) * 2 * p.pc_cap * p.t.nsw) : p.xs;
-    topsis_step<BS>(p.t, p.st, p.m, p.b, sm, xs, p.pc_cap, p.tr, p.inst, p.r, p.i);
+    const ReqView rv = plain_view(p);
+    if (!RES) {
+        topsis_step<BS>(p.t, p.st, p.m, p.b, sm, p.xs, p.pc_cap, p.tr, p.inst, p.s, rv);
+        return;
+    }
+    const int N = p.t.N;
+    int *xs = lds_after_tables(dsm, p.pc_cap, p.t.nsw);
+    int *ls = xs + (size_t)xs_rows(p.m.nc) * N;
+    stage_in<BS>(ls, p.st.cpu, 6 * N);        // the six arrays are contiguous
+    // (the barrier at the end of load_peers orders these writes before any read)
+    const State st{ls, ls + N, ls + 2 * N, ls + 3 * N, ls + 4 * N, ls + 5 * N};
+    topsis_step<BS>(p.t, st, p.m, p.b, sm, xs, p.pc_cap, p.tr, p.inst, p.s, rv);
+    __syncthreads();
+    stage_out<BS>(p.st.cpu, ls, 6 * N);
 }
 
 // AHP step, stage 1: criteria of every server into the global xs rows.
 template <int BS>
 __global__ __launch_bounds__(BS) void k_criteria_plain(Params p) {
     extern __shared__ __align__(16) char dsm[];
-    if (p.b.status[p.r] == 0) return;
-    if (p.i == 0 && threadIdx.x == 0) p.b.tsb[p.r] = dev_clock();
+    if (p.b.status[p.s.r] == 0) return;
+    if (p.s.i == 0 && threadIdx.x == 0) p.b.tsb[p.s.r] = dev_clock();
     Smem sm = carve(dsm, p.pc_cap, p.t.nsw);
-    const int g0 = p.b.coff[p.r], g = g0 + p.i;
-    const int P = load_peers<BS>(p.st, p.b, sm, g0, g);
-    criteria_stage<BS, false>(p.t, p.st, p.m, sm, p.xs, p.b.cpu[g], p.b.ram[g], P, p.pc_cap,
-                              nullptr, nullptr, nullptr);
+    load_peers<BS, true>(p.t, p.st, plain_view(p), sm, p.s.P);
+    criteria_stage<BS, false>(p.t, p.st, p.m, sm, p.xs, p.s.cpu, p.s.ram, p.s.P, p.pc_cap);
 }
 
 // ---------------------------------------------------------------- AHP (section V-B)
@@ -90,7 +141,7 @@ __device__ __forceinline__ float saaty2520(float p, float q, float rp, float rq)
 // chunk of ti rows.  Saaty sums are exact integers (x2520); the ratio scale
 // sums floats.  Partials per row chunk, reduced in pass B in fixed order.
 __global__ __launch_bounds__(kAhpBlock) void k_ahp_colsum(Params p) {
-    if (p.b.status[p.r] == 0) return;
+    if (p.b.status[p.s.r] == 0) return;
     __shared__ float sx[kAhpTile], sr[kAhpTile];
     const int N = p.t.N, c = blockIdx.z, ib = blockIdx.y;
     const int j = blockIdx.x * kAhpBlock + threadIdx.x;
@@ -127,7 +178,7 @@ __global__ __launch_bounds__(kAhpBlock) void k_ahp_colsum(Params p) {
 // thread = row i, block y = chunk of tj columns; kAhpAcc interleaved partial
 // sums keep the FP32 error small.  Partials per column chunk.
 __global__ __launch_bounds__(kAhpBlock) void k_ahp_rowsum(Params p) {
-    if (p.b.status[p.r] == 0) return;
+    if (p.b.status[p.s.r] == 0) return;
     __shared__ float sx[kAhpTile], sr[kAhpTile], sinv[kAhpTile];
     const int N = p.t.N, c = blockIdx.z, jb = blockIdx.y;
     const int i = blockIdx.x * kAhpBlock + threadIdx.x;
@@ -191,12 +242,11 @@ __global__ __launch_bounds__(kAhpBlock) void k_ahp_rowsum(Params p) {
 template <int BS>
 __global__ __launch_bounds__(BS) void k_ahp_select(Params p) {
     extern __shared__ __align__(16) char dsm[];
-    if (p.b.status[p.r] == 0) return;
+    if (p.b.status[p.s.r] == 0) return;
     Smem sm = carve(dsm, 0, p.t.nsw);
     const Topo &t = p.t;
     const int N = t.N, nc = p.m.nc;
-    const int g0 = p.b.coff[p.r], g = g0 + p.i, n = p.b.coff[p.r + 1] - g0;
-    const int P = load_peers<BS>(p.st, p.b, sm, g0, g);
+    const ReqView rv = plain_view(p);
     if (threadIdx.x == 0) {
         double colsum[kMaxCrit];
         for (int b = 0; b < nc; ++b) {
@@ -206,14 +256,14 @@ __global__ __launch_bounds__(BS) void k_ahp_select(Params p) {
         for (int a = 0; a < nc; ++a) {
             double s = 0.0;
             for (int b = 0; b < nc; ++b) s += (static_cast<double>(p.m.w[a]) / p.m.w[b]) / colsum[b];
-            sm.q[a] = static_cast<float>(s / nc);
+            reinterpret_cast<float *>(sm.capP)[a] = static_cast<float>(s / nc);   // P1, in a spare slot
         }
-        sm.misc[1] = trace_slot(p.tr, p.inst, p.r, p.i);
+        sm.misc[M_TRACE] = trace_slot(p.tr, p.inst, p.b.rid[p.s.r], p.s.i);
     }
-    __syncthreads();
+    load_peers<BS, false>(t, p.st, rv, sm, p.s.P);
     double p1[kMaxCrit];
 #pragma unroll
-    for (int c = 0; c < kMaxCrit; ++c) p1[c] = c < nc ? sm.q[c] : 0.0;
+    for (int c = 0; c < kMaxCrit; ++c) p1[c] = c < nc ? reinterpret_cast<const float *>(sm.capP)[c] : 0.0;
     const double invN = 1.0 / N;
     auto pg = [&](int u) -> float {
         double s = 0.0;
@@ -226,40 +276,67 @@ __global__ __launch_bounds__(BS) void k_ahp_select(Params p) {
         }
         return static_cast<float>(s);
     };
-    const int slot = sm.misc[1];
+    const int slot = sm.misc[M_TRACE];
     if (slot >= 0)
         for (int u = threadIdx.x; u < N; u += BS) p.tr.scores[(size_t)slot * N + u] = pg(u);
-    select_commit<BS>(t, p.st, p.b, sm, p.xs + (size_t)nc * N, p.r, p.i, n, g, P, p.b.cpu[g], p.b.ram[g],
+    select_commit<BS, 1>(t, p.st, p.b, sm, p.xs + (size_t)nc * N, p.s, rv,
                       [&](int u) { return score_key(pg(u), u); });
 }
 
 // ---------------------------------------------------------------- batched form
-// One persistent workgroup per data-center instance: the instance's state
-// and scratch live in LDS for the whole launch; the workgroup walks its
-// requests in FCFS order and their containers in index order.
+// LDS ints of the request prefetch of the batched form: hosts, cpu, ram
+// (kMaxN each), relative peer offsets (kMaxN + 4), peers and demands
+// (kMaxPairs each).
+__host__ __device__ inline size_t req_lds_ints() { return 4 * (size_t)kMaxN + 4 + 2 * (size_t)kMaxPairs; }
+
+// One persistent workgroup per data-center instance: the instance's state,
+// the per-server scratch and the request being scheduled live in LDS for
+// the whole launch; the workgroup walks its requests in FCFS order and
+// their containers in index order.
 template <int BS>
 __global__ __launch_bounds__(BS) void k_topsis_batched(Params p) {
     extern __shared__ __align__(16) char dsm[];
     const int inst = blockIdx.x;
     const int N = p.t.N;
     Smem sm = carve(dsm, p.pc_cap, p.t.nsw);
-    int *xs = reinterpret_cast<int *>(dsm + smem_fixed_bytes() + sizeof(int) * 2 * p.pc_cap * p.t.nsw);
-    int *ls = xs + (size_t)(p.m.nc + 4) * N;
+    int *xs = lds_after_tables(dsm, p.pc_cap, p.t.nsw);
+    int *ls = xs + (size_t)xs_rows(p.m.nc) * N;
+    int *rq_host = ls + 6 * (size_t)N;
+    int *rq_cpu = rq_host + kMaxN, *rq_ram = rq_cpu + kMaxN, *rq_poff = rq_ram + kMaxN;
+    int *rq_pj = rq_poff + kMaxN + 4, *rq_pbw = rq_pj + kMaxPairs;
     const State gs = state_at(p.state_base, p.state_stride, inst, N);
-    for (int x = threadIdx.x; x < 6 * N; x += BS) ls[x] = gs.cpu[x];
-    __syncthreads();
+    stage_in<BS>(ls, gs.cpu, 6 * N);
     const State st{ls, ls + N, ls + 2 * N, ls + 3 * N, ls + 4 * N, ls + 5 * N};
     const int r0 = p.b.iroff[inst], r1 = p.b.iroff[inst + 1];
     for (int r = r0; r < r1; ++r) {
-        const int n = p.b.coff[r + 1] - p.b.coff[r];
-        for (int i = 0; i < n; ++i) {
-            topsis_step<BS>(p.t, st, p.m, p.b, sm, xs, p.pc_cap, p.tr, inst, r, i);
-            __syncthreads();
-            if (p.b.status[r] == 0) break;
+        const int g0 = p.b.coff[r], n = p.b.coff[r + 1] - g0;
+        const int pb = p.b.poff[g0], npair = p.b.poff[g0 + n] - pb;
+        for (int x = threadIdx.x; x <= n; x += BS) {
+            rq_poff[x] = p.b.poff[g0 + x] - pb;
+            if (x < n) {
+                rq_cpu[x] = p.b.cpu[g0 + x];
+                rq_ram[x] = p.b.ram[g0 + x];
+                rq_host[x] = -1;
+            }
         }
+        for (int x = threadIdx.x; x < npair; x += BS) {
+            rq_pj[x] = p.b.pj[pb + x];
+            rq_pbw[x] = p.b.pbw[pb + x];
+        }
+        __syncthreads();
+        for (int i = 0; i < n; ++i) {
+            const int q0 = rq_poff[i];
+            const StepIn s{r, i, n, g0, g0 + i, pb + q0, rq_poff[i + 1] - q0, rq_cpu[i], rq_ram[i]};
+            const ReqView rv{rq_pj + q0, rq_pbw + q0, rq_host, rq_host};
+            // one server per thread at 1024 threads keeps the loop in registers
+            if (!topsis_step<BS, BS >= 1024 ? 1 : host_group(BS)>(p.t, st, p.m, p.b, sm, xs, p.pc_cap, p.tr, inst,
+                                                                  s, rv))
+                break;
+        }
+        __syncthreads();
     }
     __syncthreads();
-    for (int x = threadIdx.x; x < 6 * N; x += BS) gs.cpu[x] = ls[x];
+    stage_out<BS>(gs.cpu, ls, 6 * N);
 }
 
 // ---------------------------------------------------------------- release
@@ -267,8 +344,8 @@ __global__ __launch_bounds__(BS) void k_topsis_batched(Params p) {
 // demand go back to the state (integer, exact).
 template <int BS>
 __global__ __launch_bounds__(BS) void k_release(Params p) {
-    const int n = p.b.coff[p.r + 1] - p.b.coff[p.r];
-    give_back<BS>(p.t, p.st, p.b, p.r, n);
+    const int n = p.b.coff[p.s.r + 1] - p.b.coff[p.s.r];
+    give_back<BS>(p.t, p.st, p.b, p.s.r, n);
 }
 
 __global__ void k_fill_i32(int *dst, int value, long long n) {

@@ -48,7 +48,7 @@ struct dc_ctx {
     bool poisoned = false;
     int *d_state = nullptr;        // [I][6][N]
     int *d_init = nullptr;         // [I][6][N]
-    int *d_xs = nullptr;           // [I][nc+4][N]
+    int *d_xs = nullptr;           // [I][nc+6][N]
     int *d_colpart = nullptr;      // AHP [nc][nI][N]
     float *d_rowpart = nullptr;    // AHP [nc][nJ][N]
     int ti = 0, tj = 0, nI = 0, nJ = 0;
@@ -56,7 +56,7 @@ struct dc_ctx {
     float *d_tscore = nullptr;
     int plain_bs = 1024, batched_bs = 1024;
     int pc_plain = 1, pc_batched = 1;
-    bool xs_lds = false;
+    bool plain_res = false;        // plain kernel stages state + scratch in LDS
     size_t lds_plain = 0, lds_select = 0;
     std::vector<std::unique_ptr<DevBatch>> batches;
     std::vector<int> queued;       // batches uploaded and waiting to run
@@ -93,7 +93,7 @@ int check_config(const dc_config *c) {
     if (c->method == DC_AHP && c->mode != DC_MODE_PLAIN) return DC_EINVAL;
     const int caps[5] = {c->host_cpu, c->host_ram, c->bw_host_edge, c->bw_edge_agg, c->bw_agg_core};
     for (int v : caps)
-        if (v < 0 || v > (1 << 22)) return DC_EINVAL;   // keeps every value exact in FP32 arithmetic
+        if (v < 0 || v >= (1 << 22)) return DC_EINVAL;   // exact in FP32; fits the 22-bit path keys
     if (c->ncrit < 1 || c->ncrit > DC_MAX_CRIT) return DC_EINVAL;
     double ws = 0.0;
     for (int i = 0; i < c->ncrit; ++i) {
@@ -145,7 +145,7 @@ Params base_params(dc_ctx *ctx, const DevBatch &b, int inst) {
     p.m = ctx->m;
     p.b = b.view;
     p.tr = Trace{ctx->d_tmeta, ctx->d_tscore, ctx->d_tcount, ctx->cfg.trace_stride, ctx->cfg.trace_cap};
-    p.xs = ctx->d_xs + (size_t)inst * (ctx->m.nc + 4) * ctx->N;
+    p.xs = ctx->d_xs + (size_t)inst * xs_rows(ctx->m.nc) * ctx->N;
     p.pc_cap = ctx->pc_plain;
     p.inst = inst;
     p.state_base = ctx->d_state;
@@ -210,7 +210,7 @@ int upload_pending(dc_ctx *ctx) {
     b.Ct = (int)b.cpu.size();
     b.Pt = (int)b.pj.size();
     // device layout: inputs coff, cpu, ram, poff, pj, pbw, iroff; outputs
-    size_t n_in = (size_t)(b.R + 1) + 2 * b.Ct + (b.Ct + 1) + 2 * (size_t)b.Pt + (b.I + 1);
+    size_t n_in = (size_t)(b.R + 1) + 2 * b.Ct + (b.Ct + 1) + 2 * (size_t)b.Pt + (b.I + 1) + b.R;
     n_in += n_in & 1;   // keeps the int64 stamps in the output region 8-byte aligned
     const size_t n_out = (size_t)b.Ct + b.Pt + b.R + b.R + b.Ct + 1 + 4 * (size_t)b.R;
     b.in_ints = n_in;
@@ -225,6 +225,9 @@ int upload_pending(dc_ctx *ctx) {
     const size_t o_pj = o; put(b.pj);
     const size_t o_pbw = o; put(b.pbw);
     const size_t o_iroff = o; put(b.iroff);
+    std::vector<int> rid32(b.R);
+    for (int r = 0; r < b.R; ++r) rid32[r] = (int)(b.ids[r] & 0x7fffffff);
+    const size_t o_rid = o; put(rid32);
     HIPCHK(hipMalloc(&b.dmem, (n_in + n_out) * sizeof(int)));
     HIPCHK(hipMemcpyAsync(b.dmem, img.data(), n_in * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
     int *d = b.dmem;
@@ -236,6 +239,7 @@ int upload_pending(dc_ctx *ctx) {
     b.view.pj = d + o_pj;
     b.view.pbw = d + o_pbw;
     b.view.iroff = d + o_iroff;
+    b.view.rid = d + o_rid;
     b.view.host = out;
     b.view.code = out + b.Ct;
     b.view.failat = out + b.Ct + b.Pt;
@@ -262,7 +266,7 @@ int upload_pending(dc_ctx *ctx) {
 template <int BS>
 void launch_plain_step(dc_ctx *ctx, const Params &p) {
     if (ctx->m.method == DC_TOPSIS) {
-        if (ctx->xs_lds)
+        if (ctx->plain_res)
             hipLaunchKernelGGL((k_topsis_plain<BS, true>), dim3(1), dim3(BS), ctx->lds_plain, ctx->stream, p);
         else
             hipLaunchKernelGGL((k_topsis_plain<BS, false>), dim3(1), dim3(BS), ctx->lds_plain, ctx->stream, p);
@@ -280,10 +284,14 @@ void launch_plain_step(dc_ctx *ctx, const Params &p) {
 int run_plain(dc_ctx *ctx, DevBatch &b) {
     for (int r = 0; r < b.R; ++r) {
         Params p = base_params(ctx, b, b.inst[r]);
-        p.r = r;
-        const int n = b.coff[r + 1] - b.coff[r];
+        const int g0 = b.coff[r], n = b.coff[r + 1] - g0;
         for (int i = 0; i < n; ++i) {
-            p.i = i;
+            const int g = g0 + i;
+            p.s = StepIn{r, i, n, g0, g, b.poff[g], b.poff[g + 1] - b.poff[g], b.cpu[g], b.ram[g]};
+            for (int q = 0; q < p.s.P; ++q) {
+                p.pj[q] = b.pj[p.s.p0 + q];
+                p.pbw[q] = b.pbw[p.s.p0 + q];
+            }
             switch (ctx->plain_bs) {
             case 64: launch_plain_step<64>(ctx, p); break;
             case 256: launch_plain_step<256>(ctx, p); break;
@@ -298,7 +306,8 @@ int run_plain(dc_ctx *ctx, DevBatch &b) {
 }
 
 size_t batched_lds(const dc_ctx *ctx) {
-    return step_lds_bytes(ctx->pc_batched, ctx->t.nsw, (size_t)(ctx->m.nc + 4) * ctx->N, 6 * (size_t)ctx->N);
+    return step_lds_bytes(ctx->pc_batched, ctx->t.nsw, (size_t)xs_rows(ctx->m.nc) * ctx->N,
+                          6 * (size_t)ctx->N + req_lds_ints());
 }
 
 int run_batched(dc_ctx *ctx, DevBatch &b, int bs) {
@@ -394,7 +403,7 @@ int dc_create(const dc_config *cfg, dc_ctx **out) {
     ctx->cfg = *cfg;
     ctx->cfg.host_used = nullptr;
     ctx->cfg.link_used = nullptr;
-    ctx->t = Topo{k, h, h * h, N, k * k / 2};
+    ctx->t = Topo{k, h, h * h, N, k * k / 2, 1.0f / h, 1.0f / (h * h), 1.0f / (k * k / 2)};
     ctx->N = N;
     ctx->I = I;
     ctx->m.method = cfg->method;
@@ -437,22 +446,30 @@ int dc_create(const dc_config *cfg, dc_ctx **out) {
         return DC_EDEVICE;
     }
     const int nc = cfg->ncrit;
-    if (hipMalloc(&c->d_xs, (size_t)I * (nc + 4) * N * sizeof(int)) != hipSuccess) {
+    if (hipMalloc(&c->d_xs, (size_t)I * xs_rows(nc) * N * sizeof(int)) != hipSuccess) {
         dc_destroy(ctx.release());
         return DC_ENOMEM;
     }
     // launch shapes
     c->plain_bs = cfg->block ? cfg->block : (N <= 64 ? 64 : N <= 256 ? 256 : 1024);
     c->batched_bs = cfg->block ? std::max(256, cfg->block) : 1024;
-    const size_t table_budget = 64 * 1024;
-    c->pc_plain = (int)std::max<size_t>(1, std::min<size_t>(kMaxN, table_budget / (8 * (size_t)c->t.nsw)));
-    const size_t xs_bytes = (size_t)(nc + 4) * N * sizeof(int);
-    c->xs_lds = xs_bytes <= 48 * 1024;
-    c->lds_plain = step_lds_bytes(c->pc_plain, c->t.nsw, c->xs_lds ? (size_t)(nc + 4) * N : 0, 0);
+    const size_t lds_max = 160 * 1024;
+    {
+        // plain: state + scratch in LDS when they fit with at least 8 peer tables
+        const size_t res_fixed = step_lds_bytes(0, c->t.nsw, (size_t)xs_rows(nc) * N, 6 * (size_t)N);
+        const size_t per_peer = 8 * (size_t)c->t.nsw;
+        c->plain_res = res_fixed + 8 * per_peer <= lds_max;
+        if (c->plain_res) {
+            c->pc_plain = (int)std::min<size_t>(kMaxN, (lds_max - res_fixed) / per_peer);
+            c->lds_plain = step_lds_bytes(c->pc_plain, c->t.nsw, (size_t)xs_rows(nc) * N, 6 * (size_t)N);
+        } else {
+            c->pc_plain = (int)std::max<size_t>(1, std::min<size_t>(kMaxN, 64 * 1024 / per_peer));
+            c->lds_plain = step_lds_bytes(c->pc_plain, c->t.nsw, 0, 0);
+        }
+    }
     c->lds_select = step_lds_bytes(0, c->t.nsw, 0, 0);
     if (cfg->mode == DC_MODE_BATCHED) {
-        const size_t lds_max = 160 * 1024;
-        const size_t fixed = step_lds_bytes(0, c->t.nsw, (size_t)(nc + 4) * N, 6 * (size_t)N);
+        const size_t fixed = step_lds_bytes(0, c->t.nsw, (size_t)xs_rows(nc) * N, 6 * (size_t)N + req_lds_ints());
         if (fixed + 8 * (size_t)c->t.nsw > lds_max) { dc_destroy(ctx.release()); return DC_EINVAL; }
         c->pc_batched = (int)std::min<size_t>(kMaxN, (lds_max - fixed) / (8 * (size_t)c->t.nsw));
         const size_t lb = batched_lds(c);
@@ -566,7 +583,7 @@ int dc_release(dc_ctx *ctx, int64_t req_id) {
         if (bi == it->second.batch) return DC_ENOENT;   // not scheduled yet
     if ((int)b.status.size() <= r || b.status[r] != 1) return DC_ENOENT;
     Params p = base_params(ctx, b, b.inst[r]);
-    p.r = r;
+    p.s.r = r;
     hipLaunchKernelGGL((k_release<256>), dim3(1), dim3(256), 0, ctx->stream, p);
     HIPCHK(hipGetLastError());
     it->second.released = true;
@@ -673,7 +690,8 @@ int dc_get_trace(dc_ctx *ctx, int32_t cap, int32_t *meta, float *scores, int32_t
 int dc_autotune(dc_ctx *ctx, int32_t *block) {
     if (!ctx) return DC_EINVAL;
     if (ctx->poisoned) return DC_EDEVICE;
-    if (ctx->cfg.mode != DC_MODE_BATCHED) return DC_ESTATE;
+    if (ctx->cfg.mode == DC_MODE_SERVING) return DC_ESTATE;
+    const bool batched = ctx->cfg.mode == DC_MODE_BATCHED;
     int rc = upload_pending(ctx);
     if (rc) return rc;
     if (ctx->queued.empty()) return DC_ESTATE;
@@ -683,13 +701,18 @@ int dc_autotune(dc_ctx *ctx, int32_t *block) {
     HIPCHK(hipMemcpyAsync(saved, ctx->d_state, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
     const int cand[3] = {256, 512, 1024};
     float best_ms = 1e30f;
-    int best = ctx->batched_bs;
+    int best = batched ? ctx->batched_bs : ctx->plain_bs;
+    const int keep_plain = ctx->plain_bs;
     for (int bs : cand) {
+        if (!batched && bs > ctx->N && bs != cand[0]) continue;   // no idle waves beyond the servers
         for (int rep = 0; rep < 2; ++rep) {   // first run warms up
             HIPCHK(hipMemcpyAsync(ctx->d_state, saved, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
             for (int bi : ctx->queued) if ((rc = reset_outputs(ctx, *ctx->batches[bi]))) return rc;
             HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
-            for (int bi : ctx->queued) if ((rc = run_batched(ctx, *ctx->batches[bi], bs))) return rc;
+            ctx->plain_bs = bs;
+            for (int bi : ctx->queued)
+                if ((rc = batched ? run_batched(ctx, *ctx->batches[bi], bs) : run_plain(ctx, *ctx->batches[bi])))
+                    return rc;
             HIPCHK(hipEventRecord(ctx->ev1, ctx->stream));
             HIPCHK(hipEventSynchronize(ctx->ev1));
             float ms = 0.f;
@@ -701,7 +724,8 @@ int dc_autotune(dc_ctx *ctx, int32_t *block) {
     for (int bi : ctx->queued) if ((rc = reset_outputs(ctx, *ctx->batches[bi]))) return rc;
     HIPCHK(hipStreamSynchronize(ctx->stream));
     HIPCHK(hipFree(saved));
-    ctx->batched_bs = best;
+    ctx->plain_bs = keep_plain;
+    if (batched) ctx->batched_bs = best; else ctx->plain_bs = best;
     if (block) *block = best;
     return DC_OK;
 }

@@ -1,8 +1,8 @@
 // Device side of one container step: path stage, criteria, TOPSIS scoring,
 // argmax selection, commit with widest shortest-path routing, and request
 // rollback.  Everything here runs inside one workgroup; the plain, batched
-// and serving kernels differ only in where the data-center state lives
-// (HBM/L2 or LDS) and in how steps are fed.
+// and serving kernels differ only in where the data-center state and the
+// request data live (HBM/L2 or LDS) and in how steps are fed.
 //
 // Paper references (arXiv 1909.07673):
 //   section II-A / Table I  data-center graph, capacities, requests
@@ -19,16 +19,25 @@ namespace dcs {
 
 constexpr int kMaxCrit = 8;
 constexpr int kMaxN = 64;          // containers per request
+constexpr int kMaxPairs = kMaxN * (kMaxN - 1) / 2;
+constexpr int kMaxPods = 64;
 constexpr int kWave = 64;
 constexpr int kBig = 0x7fffffff;
 
 enum { CRIT_CPU = 0, CRIT_RAM = 1, CRIT_ACTIVE = 2, CRIT_PATHBW = 3, CRIT_UPLINK = 4, CRIT_HOPS = 5 };
 
 // Fat-tree sizes.  h = k/2 hosts per edge switch and aggregation switches per
-// pod; hh = h*h hosts per pod; nsw = k*k/2 edge (and aggregation) switches.
+// pod; hh = h*h hosts per pod; nsw = k*k/2 edge (and aggregation) switches;
+// rh, rhh, rnsw their reciprocals in FP32 for exact small-integer division.
 struct Topo {
     int k, h, hh, N, nsw;
+    float rh, rhh, rnsw;
 };
+
+// floor(x / d) for 0 <= x < 2^18 and 1 <= d <= 2048, via the FP32
+// reciprocal r = fl(1/d): (x + 1/2) / d lies at least 1/(2d) from an
+// integer, far more than the two roundings can move it.
+__device__ __forceinline__ int fdiv(int x, float r) { return static_cast<int>((static_cast<float>(x) + 0.5f) * r); }
 
 // Residual state of one data center, structure-of-arrays, N entries each.
 struct State {
@@ -53,7 +62,24 @@ struct Batch {
     int *status;    // [R]  1 accepted (optimistic), 0 rejected
     int *failat;    // [R]  container without a server, -1
     const int *iroff;  // [I+1] first request of each instance (batched form)
+    const int *rid;    // [R]  request id (low 31 bits), for trace records
     long long *tsb, *tse;  // [R] device clock (100 MHz) at the first step's start / the decision
+};
+
+// One container step: where it sits in the batch, and its demand.
+struct StepIn {
+    int r, i, n;       // request (batch index), container index, containers of the request
+    int g0, g;         // global index of the request's container 0 and of this container
+    int p0, P;         // first peer pair of this container and number of placed peers
+    int cpu, ram;      // demand
+};
+
+// Where a step reads its request data: the container's peer list (P
+// entries) and the servers of the request's containers (indexed by
+// container).  Global memory in the plain form, LDS in the batched form.
+struct ReqView {
+    const int *pj, *pbw, *hosts;
+    int *hosts_out;    // LDS copy of hosts to update (batched form), or nullptr
 };
 
 // Constant-rate device clock (100 MHz), read without a memory access.
@@ -66,82 +92,101 @@ struct Trace {
     int stride, cap;
 };
 
-// LDS scratch of a step, carved from dynamic shared memory.
-struct Smem {
-    int *ph, *pbw, *upv;              // [kMaxN] peer server, demand, its uplink residual
-    int *tabT, *tabE;                 // [pc][nsw] per-peer aggregation / edge tables
-    unsigned long long *wkey;         // [32] per-wave argmax partials
-    unsigned long long *ws2;          // [32][kMaxCrit] per-wave sum of squares
-    int *wmx, *wmn;                   // [32][kMaxCrit]
-    float *q, *ap, *am;               // [kMaxCrit]
-    int *misc;                        // [16]
+// Slots of the LDS misc block.
+enum {
+    M_OK = 0, M_TRACE = 1,
+    M_DH0 = 2, M_DH1 = 3, M_DE0 = 4, M_DE1 = 5, M_DP0 = 6, M_DP1 = 7,   // deficits (min, max id)
+    M_ALIVE = 8, M_MISC = 16
 };
 
+constexpr int kMaxWaves = 16;          // 1024-thread workgroups
+// Servers a thread works on together: enough independent chains to hide
+// LDS latency, few enough to stay in registers at 1024 threads.
+__host__ __device__ constexpr int host_group(int bs) { return bs >= 1024 ? 2 : 4; }
+constexpr int kStatFields = 5 * kMaxCrit;  // per criterion: 3 sum-of-squares chunks, max, -min
+
+// LDS scratch of a step, carved from dynamic shared memory.  Every region
+// starts on a 16-byte boundary.
+struct Smem {
+    int4 *pk;                         // [kMaxN] packed peer: server, edge | pod << 16, demand, uplink residual
+    int *wst;                         // [kStatFields][kMaxWaves] per-wave column statistics
+    unsigned *ahi, *alo;              // [2][kMaxWaves] per-wave argmax keys (alternating per retry)
+    int *ph, *pbw;                    // [kMaxN] peer server, demand
+    int *capP;                        // [kMaxPods] summed aggregation-core residual per pod
+    int *misc;                        // [M_MISC]
+    int *capE;                        // [nsw] summed edge-aggregation residual per edge switch
+    int *tabT, *tabE;                 // [pc][nsw] per-peer aggregation / edge tables
+};
+
+__host__ __device__ inline size_t align4(size_t ints) { return (ints + 3) & ~size_t(3); }
+
 __host__ __device__ inline size_t smem_fixed_bytes() {
-    return sizeof(int) * 3 * kMaxN + sizeof(unsigned long long) * 32 +
-           sizeof(unsigned long long) * 32 * kMaxCrit + sizeof(int) * 2 * 32 * kMaxCrit +
-           sizeof(float) * 3 * kMaxCrit + sizeof(int) * 16;
+    return sizeof(int4) * kMaxN + sizeof(int) * (kStatFields * kMaxWaves + 4 * kMaxWaves + 2 * kMaxN + kMaxPods +
+                                                 M_MISC);
+}
+
+// Variable part: capE, then the per-peer tables (rounded to 16 bytes).
+__host__ __device__ inline size_t smem_var_ints(int pc, int nsw) {
+    return align4((size_t)nsw) + 2 * align4((size_t)pc * nsw);
 }
 
 __device__ inline Smem carve(char *base, int pc, int nsw) {
     Smem s;
-    unsigned long long *p64 = reinterpret_cast<unsigned long long *>(base);
-    s.wkey = p64; p64 += 32;
-    s.ws2 = p64; p64 += 32 * kMaxCrit;
-    int *p = reinterpret_cast<int *>(p64);
-    s.wmx = p; p += 32 * kMaxCrit;
-    s.wmn = p; p += 32 * kMaxCrit;
+    s.pk = reinterpret_cast<int4 *>(base);
+    int *p = reinterpret_cast<int *>(base + sizeof(int4) * kMaxN);
+    s.wst = p; p += kStatFields * kMaxWaves;
+    s.ahi = reinterpret_cast<unsigned *>(p); p += 2 * kMaxWaves;
+    s.alo = reinterpret_cast<unsigned *>(p); p += 2 * kMaxWaves;
     s.ph = p; p += kMaxN;
     s.pbw = p; p += kMaxN;
-    s.upv = p; p += kMaxN;
-    s.misc = p; p += 16;
-    float *f = reinterpret_cast<float *>(p);
-    s.q = f; f += kMaxCrit;
-    s.ap = f; f += kMaxCrit;
-    s.am = f; f += kMaxCrit;
-    p = reinterpret_cast<int *>(f);
-    s.tabT = p; p += pc * nsw;
+    s.capP = p; p += kMaxPods;
+    s.misc = p; p += M_MISC;
+    s.capE = p; p += align4(nsw);
+    s.tabT = p; p += align4((size_t)pc * nsw);
     s.tabE = p;
     return s;
 }
 
-// ---------------------------------------------------------------- wave / block reductions
-__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        unsigned long long w = __shfl_xor(v, o, kWave);
-        v = w > v ? w : v;
-    }
-    return v;
-}
-__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
-}
-__device__ __forceinline__ int wave_max_i(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
-    return v;
-}
-__device__ __forceinline__ int wave_min_i(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, kWave));
-    return v;
+// ---------------------------------------------------------------- wave reductions (DPP)
+// Reductions across a 64-lane wave with DPP row shifts and row broadcasts;
+// the result is returned uniformly (read from lane 63).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp(int identity, int v) {
+    return __builtin_amdgcn_update_dpp(identity, v, CTRL, ROWS, 0xf, false);
 }
 
-// Block-wide maximum of a 64-bit key; every thread gets the result.
-template <int BS>
-__device__ __forceinline__ unsigned long long block_max_u64(unsigned long long v, unsigned long long *wbuf) {
-    v = wave_max_u64(v);
-    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    if (lane == 0) wbuf[wid] = v;
-    __syncthreads();
-    unsigned long long r = 0;
-#pragma unroll
-    for (int w = 0; w < BS / kWave; ++w) r = wbuf[w] > r ? wbuf[w] : r;
-    __syncthreads();
-    return r;
+#define DCS_WAVE_REDUCE(v, OP, ID)                        \
+    do {                                                  \
+        v = OP(v, dpp<0x111, 0xf>(ID, v));                \
+        v = OP(v, dpp<0x112, 0xf>(ID, v));                \
+        v = OP(v, dpp<0x114, 0xf>(ID, v));                \
+        v = OP(v, dpp<0x118, 0xf>(ID, v));                \
+        v = OP(v, dpp<0x142, 0xa>(ID, v));                \
+        v = OP(v, dpp<0x143, 0xc>(ID, v));                \
+        v = __builtin_amdgcn_readlane(v, 63);             \
+    } while (0)
+
+__device__ __forceinline__ int op_add(int a, int b) { return a + b; }
+__device__ __forceinline__ int op_max(int a, int b) { return a > b ? a : b; }
+__device__ __forceinline__ int op_min(int a, int b) { return a < b ? a : b; }
+__device__ __forceinline__ int op_umax(int a, int b) { return (unsigned)a > (unsigned)b ? a : b; }
+
+// Reduction within each row of 16 lanes; lane 16*row + 15 holds the result.
+#define DCS_ROW_REDUCE(v, OP, ID)                         \
+    do {                                                  \
+        v = OP(v, dpp<0x111, 0xf>(ID, v));                \
+        v = OP(v, dpp<0x112, 0xf>(ID, v));                \
+        v = OP(v, dpp<0x114, 0xf>(ID, v));                \
+        v = OP(v, dpp<0x118, 0xf>(ID, v));                \
+    } while (0)
+
+__device__ __forceinline__ int wave_sum(int v) { DCS_WAVE_REDUCE(v, op_add, 0); return v; }
+__device__ __forceinline__ int wave_max(int v) { DCS_WAVE_REDUCE(v, op_max, -kBig - 1); return v; }
+__device__ __forceinline__ int wave_min(int v) { DCS_WAVE_REDUCE(v, op_min, kBig); return v; }
+__device__ __forceinline__ unsigned wave_umax(unsigned v) {
+    int x = static_cast<int>(v);
+    DCS_WAVE_REDUCE(x, op_umax, 0);
+    return static_cast<unsigned>(x);
 }
 
 // ---------------------------------------------------------------- topology helpers
@@ -150,46 +195,55 @@ __device__ __forceinline__ unsigned long long block_max_u64(unsigned long long v
 // edge-aggregation links through aggregation index a; with different pods
 // the two aggregation-core links through core (a, j).  c = a (same pod) or
 // a*h + j (different pods).
+// Link x (0..5) of that path, or nullptr when the path is shorter.
+__device__ __forceinline__ int *path_link(const Topo &t, const State &st, int u, int v, int c, int x) {
+    const int eu = fdiv(u, t.rh), ev = fdiv(v, t.rh), pu = fdiv(u, t.rhh), pv = fdiv(v, t.rhh);
+    int a = 0, j = 0;
+    if (pu == pv) a = c; else { a = fdiv(c, t.rh); j = c - a * t.h; }
+    switch (x) {
+    case 0: return st.up + u;
+    case 1: return st.up + v;
+    case 2: return eu != ev ? st.ea + eu * t.h + a : nullptr;
+    case 3: return eu != ev ? st.ea + ev * t.h + a : nullptr;
+    case 4: return pu != pv ? st.ac + (pu * t.h + a) * t.h + j : nullptr;
+    default: return pu != pv ? st.ac + (pv * t.h + a) * t.h + j : nullptr;
+    }
+}
+
 template <bool ATOMIC>
 __device__ __forceinline__ void path_apply(const Topo &t, const State &st, int u, int v, int c, int delta) {
-    const int eu = u / t.h, ev = v / t.h, pu = u / t.hh, pv = v / t.hh;
-    int a = 0, j = 0;
-    if (pu == pv) a = c; else { a = c / t.h; j = c - a * t.h; }
-    int *l[6];
-    int nl = 2;
-    l[0] = st.up + u; l[1] = st.up + v;
-    if (eu != ev) { l[2] = st.ea + eu * t.h + a; l[3] = st.ea + ev * t.h + a; nl = 4; }
-    if (pu != pv) { l[4] = st.ac + (pu * t.h + a) * t.h + j; l[5] = st.ac + (pv * t.h + a) * t.h + j; nl = 6; }
-    for (int x = 0; x < nl; ++x) {
-        if (ATOMIC) atomicAdd(l[x], delta);
-        else *l[x] += delta;
+    for (int x = 0; x < 6; ++x) {
+        int *l = path_link(t, st, u, v, c, x);
+        if (!l) continue;
+        if (ATOMIC) atomicAdd(l, delta);
+        else *l += delta;
     }
 }
 
 // Widest minimum-hop path from u to v under the current residuals; ties go
 // to the lowest aggregation then core index (candidate order).  Evaluated by
-// one wave, candidates spread over lanes.  Returns key = bottleneck << 32 |
-// ~candidate (bottlenecks are non-negative).
-__device__ __forceinline__ unsigned long long widest_wave(const Topo &t, const State &st, int u, int v, int lane) {
-    const int eu = u / t.h, ev = v / t.h, pu = u / t.hh, pv = v / t.hh;
+// one wave, candidates spread over lanes.  Returns the 32-bit key
+// bottleneck << 10 | (1023 - candidate): residuals stay below 2^22 and
+// there are at most 1024 candidates.
+__device__ __forceinline__ unsigned widest_wave(const Topo &t, const State &st, int u, int v, int eu, int pu,
+                                                int ev, int pv, int lane) {
     const int ncand = (eu == ev) ? 1 : (pu == pv ? t.h : t.hh);
     const int base = min(st.up[u], st.up[v]);
-    unsigned long long best = 0;
+    unsigned best = 0;
     for (int c = lane; c < ncand; c += kWave) {
         int b = base;
         if (eu != ev) {
-            const int a = (pu == pv) ? c : c / t.h;
+            const int a = (pu == pv) ? c : fdiv(c, t.rh);
             b = min(b, min(st.ea[eu * t.h + a], st.ea[ev * t.h + a]));
             if (pu != pv) {
                 const int j = c - a * t.h;
                 b = min(b, min(st.ac[(pu * t.h + a) * t.h + j], st.ac[(pv * t.h + a) * t.h + j]));
             }
         }
-        const unsigned long long key = (static_cast<unsigned long long>(static_cast<unsigned>(b)) << 32) |
-                                       static_cast<unsigned>(~c);
+        const unsigned key = (static_cast<unsigned>(b) << 10) | static_cast<unsigned>(1023 - c);
         best = key > best ? key : best;
     }
-    return wave_max_u64(best);
+    return wave_umax(best);
 }
 
 // Commit container (cpu_i, ram_i) on server u with its P placed peers
@@ -197,36 +251,50 @@ __device__ __forceinline__ unsigned long long widest_wave(const Topo &t, const S
 // remote peer on its widest shortest path under the current residuals,
 // failing when a bottleneck is below the demand (Eqs. (4)-(5)).  On failure
 // every change is undone.  Run by one whole wave; lane 0 writes.
+// Lanes 0..5 each update one link of the path (its links are distinct).
+template <bool ATOMIC>
+__device__ __forceinline__ void path_apply_lanes(const Topo &t, const State &st, int u, int v, int c, int delta,
+                                                 int lane) {
+    if (lane < 6) {
+        int *l = path_link(t, st, u, v, c, lane);
+        if (l) {
+            if (ATOMIC) atomicAdd(l, delta);
+            else *l += delta;
+        }
+    }
+}
+
 __device__ __forceinline__ bool commit_wave(const Topo &t, const State &st, int u, int cpu_i, int ram_i, int P,
-                                            const int *ph, const int *pbw, int *code_out, int lane) {
+                                            const Smem &sm, int *code_out, int lane) {
     if (st.cpu[u] < cpu_i || st.ram[u] < ram_i) return false;
-    int routed = 0;
+    const int eu = fdiv(u, t.rh), pu = fdiv(u, t.rhh);
+    int routed = 0, mycode = -1;       // lane p keeps peer p's path choice
     bool ok = true;
     for (int p = 0; p < P; ++p) {
-        const int v = ph[p];
+        const int4 pk = sm.pk[p];
+        const int v = pk.x;
         if (v == u) {
-            if (lane == 0) code_out[p] = -1;
             routed = p + 1;
             continue;
         }
-        const unsigned long long best = widest_wave(t, st, u, v, lane);
-        const int b = static_cast<int>(best >> 32);
-        const int c = static_cast<int>(~static_cast<unsigned>(best & 0xffffffffu));
-        if (b < pbw[p]) { ok = false; break; }
-        if (lane == 0) {
-            path_apply<false>(t, st, u, v, c, -pbw[p]);
-            code_out[p] = c;
-        }
+        const unsigned best = widest_wave(t, st, u, v, eu, pu, pk.y & 0xffff, pk.y >> 16, lane);
+        const int b = static_cast<int>(best >> 10);
+        const int c = 1023 - static_cast<int>(best & 1023u);
+        if (b < pk.z) { ok = false; break; }
+        path_apply_lanes<false>(t, st, u, v, c, -pk.z, lane);
+        mycode = lane == p ? c : mycode;
         __threadfence_block();
         routed = p + 1;
     }
     if (!ok) {
-        if (lane == 0)
-            for (int p = routed - 1; p >= 0; --p)
-                if (ph[p] != u) path_apply<false>(t, st, u, ph[p], code_out[p], pbw[p]);
-        __threadfence_block();
+        for (int p = routed - 1; p >= 0; --p) {
+            const int4 pk = sm.pk[p];
+            if (pk.x != u) path_apply_lanes<false>(t, st, u, pk.x, __builtin_amdgcn_readlane(mycode, p), pk.z, lane);
+            __threadfence_block();
+        }
         return false;
     }
+    if (lane < P) code_out[lane] = mycode;
     if (lane == 0) {
         st.cpu[u] -= cpu_i;
         st.ram[u] -= ram_i;
@@ -278,7 +346,7 @@ __device__ void rollback_request(const Topo &t, const State &st, const Batch &b,
     __syncthreads();
 }
 
-// ---------------------------------------------------------------- path stage + criteria
+// ---------------------------------------------------------------- peers and path tables
 // Peer tables for the peers [pbeg, pbeg+pn) (section V-D routing on a
 // fat-tree, per destination server v in pod pv and edge switch ev):
 //   T[ag] = max_j min(ac(ag, j), ac((pv, a), j))  for aggregation (p, a), p != pv
@@ -286,136 +354,303 @@ __device__ void rollback_request(const Topo &t, const State &st, const Batch &b,
 // so that the widest shortest path from u to v has bottleneck
 // min(up[u], up[v], E[edge(u)]) (or min(up[u], up[v]) on the same edge).
 template <int BS>
-__device__ __forceinline__ void build_tables(const Topo &t, const State &st, const Smem &sm, int pbeg, int pn) {
+__device__ __forceinline__ void table_T(const Topo &t, const State &st, const Smem &sm, int pbeg, int pn) {
     const int tot = pn * t.nsw;
     for (int it = threadIdx.x; it < tot; it += BS) {
-        const int pc = it / t.nsw, ag = it - pc * t.nsw;
-        const int v = sm.ph[pbeg + pc];
-        const int pv = v / t.hh, pa = ag / t.h;
+        const int pc = fdiv(it, t.rnsw), ag = it - pc * t.nsw;
+        const int pv = sm.pk[pbeg + pc].y >> 16, pa = fdiv(ag, t.rh);
         int val = 0;
         if (pa != pv) {
             const int a = ag - pa * t.h;
             const int *x = st.ac + ag * t.h;
             const int *y = st.ac + (pv * t.h + a) * t.h;
-            for (int j = 0; j < t.h; ++j) val = max(val, min(x[j], y[j]));
+            if ((t.h & 3) == 0) {
+                for (int j = 0; j < t.h; j += 4) {
+                    const int4 a4 = *reinterpret_cast<const int4 *>(x + j);
+                    const int4 b4 = *reinterpret_cast<const int4 *>(y + j);
+                    val = max(val, max(max(min(a4.x, b4.x), min(a4.y, b4.y)), max(min(a4.z, b4.z), min(a4.w, b4.w))));
+                }
+            } else {
+                for (int j = 0; j < t.h; ++j) val = max(val, min(x[j], y[j]));
+            }
         }
         sm.tabT[it] = val;
     }
-    __syncthreads();
+}
+
+template <int BS>
+__device__ __forceinline__ void table_E(const Topo &t, const State &st, const Smem &sm, int pbeg, int pn) {
+    const int tot = pn * t.nsw;
     for (int it = threadIdx.x; it < tot; it += BS) {
-        const int pc = it / t.nsw, eg = it - pc * t.nsw;
-        const int v = sm.ph[pbeg + pc];
-        const int ev = v / t.h, pv = v / t.hh, pe = eg / t.h;
+        const int pc = fdiv(it, t.rnsw), eg = it - pc * t.nsw;
+        const int ed = sm.pk[pbeg + pc].y;
+        const int ev = ed & 0xffff, pv = ed >> 16, pe = fdiv(eg, t.rh);
         int val = 0;
         if (eg != ev) {
             const int *x = st.ea + eg * t.h;
             const int *y = st.ea + ev * t.h;
             const int *T = sm.tabT + pc * t.nsw + pe * t.h;
-            for (int a = 0; a < t.h; ++a) {
-                int w = min(x[a], y[a]);
-                if (pe != pv) w = min(w, T[a]);
-                val = max(val, w);
+            const int lim = pe != pv ? 0 : kBig;      // same pod: no aggregation-core leg
+            if ((t.h & 3) == 0) {
+                for (int a = 0; a < t.h; a += 4) {
+                    const int4 a4 = *reinterpret_cast<const int4 *>(x + a);
+                    const int4 b4 = *reinterpret_cast<const int4 *>(y + a);
+                    const int4 t4 = *reinterpret_cast<const int4 *>(T + a);
+                    val = max(val, max(max(min(min(a4.x, b4.x), max(t4.x, lim)), min(min(a4.y, b4.y), max(t4.y, lim))),
+                                       max(min(min(a4.z, b4.z), max(t4.z, lim)), min(min(a4.w, b4.w), max(t4.w, lim)))));
+                }
+            } else {
+                for (int a = 0; a < t.h; ++a) val = max(val, min(min(x[a], y[a]), max(T[a], lim)));
             }
         }
         sm.tabE[it] = val;
     }
+}
+
+// Phase A of a step (no barrier needed before it): the peer list of the
+// container into LDS (server, demand, uplink residual, edge switch, pod),
+// the summed residuals per edge switch and per pod when LIMITS, and the
+// reset of the reduction slots.  Ends with a barrier.
+template <int BS, bool LIMITS>
+__device__ __forceinline__ void load_peers(const Topo &t, const State &st, const ReqView &rv, const Smem &sm,
+                                           int P) {
+    for (int p = threadIdx.x; p < P; p += BS) {
+        const int v = rv.hosts[rv.pj[p]];
+        const int bw = rv.pbw[p];
+        sm.ph[p] = v;
+        sm.pbw[p] = bw;
+        sm.pk[p] = make_int4(v, fdiv(v, t.rh) | (fdiv(v, t.rhh) << 16), bw, st.up[v]);
+    }
+    if (threadIdx.x < 6) sm.misc[M_DH0 + threadIdx.x] = (threadIdx.x & 1) ? -1 : kBig;
+    if (LIMITS && P > 0) {
+        for (int x = threadIdx.x; x < t.nsw; x += BS) {
+            int se = 0;
+            for (int a = 0; a < t.h; ++a) se += st.ea[x * t.h + a];
+            sm.capE[x] = se;
+        }
+        // per pod: one wave sums the pod's h*h aggregation-core residuals
+        const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+        for (int pod = wid; pod < t.k; pod += BS / kWave) {
+            int s = 0;
+            for (int x = lane; x < t.hh; x += kWave) s += st.ac[pod * t.hh + x];
+            s = wave_sum(s);
+            if (lane == 0) sm.capP[pod] = s;
+        }
+    }
     __syncthreads();
 }
 
+// Peer-side deficits: a peer server (edge switch, pod) whose uplink
+// (uplinks) cannot carry the summed demand of the peers it holds can only
+// be reached by a server inside it, so at most one such server (switch,
+// pod) leaves any server feasible.  misc[M_DH0..M_DP1] = (min, max) id of
+// the deficient servers, edge switches, pods; (kBig, -1) when none.  No
+// barrier: the results are read after the next one.
+template <int BS>
+__device__ __forceinline__ void peer_deficits(const Smem &sm, int P) {
+    for (int p = threadIdx.x; p < P; p += BS) {
+        const int4 me = sm.pk[p];
+        const int v = me.x, e = me.y & 0xffff, d = me.y >> 16;
+        int sh = 0, se = 0, sp = 0;
+        for (int q = 0; q < P; ++q) {
+            const int4 o = sm.pk[q];
+            sh += o.x == v ? o.z : 0;
+            se += (o.y & 0xffff) == e ? o.z : 0;
+            sp += (o.y >> 16) == d ? o.z : 0;
+        }
+        if (me.w < sh) { atomicMin(sm.misc + M_DH0, v); atomicMax(sm.misc + M_DH1, v); }
+        if (sm.capE[e] < se) { atomicMin(sm.misc + M_DE0, e); atomicMax(sm.misc + M_DE1, e); }
+        if (sm.capP[d] < sp) { atomicMin(sm.misc + M_DP0, d); atomicMax(sm.misc + M_DP1, d); }
+    }
+}
+
+// ---------------------------------------------------------------- criteria
 // Per-host criteria for one container.  xs rows (N ints each): [0, nc) the
-// criteria values, nc the feasibility flag, nc+1..nc+3 partial accumulators
-// kept across peer chunks.  Accumulates the TOPSIS column statistics
-// (sum of squares, max, min) when STATS.
-template <int BS, bool STATS>
+// criteria values, nc the feasibility flag, nc+1..nc+5 partial accumulators
+// kept across peer chunks.  With STATS the TOPSIS column statistics (exact
+// sum of squares, max, min) are accumulated into the LDS slots; they are
+// complete after the next barrier.
+//
+// Feasibility (Eqs. (4)-(5)): CPU and RAM fit; every remote peer's widest
+// path carries its demand; and a set of conditions every successful commit
+// satisfies, which spare the commit loop from trying servers bound to fail:
+// the server's uplink, its edge switch's and its pod's uplinks each carry
+// the demand of the peers outside them, and the peer-side deficits.
+template <int BS, bool STATS, int G = host_group(BS)>
 __device__ void criteria_stage(const Topo &t, const State &st, const Method &m, const Smem &sm, int *xs,
-                               int cpu_i, int ram_i, int P, int pc_cap, unsigned long long *s2, int *mx, int *mn) {
+                               int cpu_i, int ram_i, int P, int pc_cap) {
     const int N = t.N, nc = m.nc;
     const int nch = P == 0 ? 1 : (P + pc_cap - 1) / pc_cap;
+    unsigned long long s2[kMaxCrit];
+    int mx[kMaxCrit], mn[kMaxCrit];
+#pragma unroll
+    for (int c = 0; c < kMaxCrit; ++c) { s2[c] = 0; mx[c] = -kBig - 1; mn[c] = kBig; }
     for (int ch = 0; ch < nch; ++ch) {
         const int pbeg = ch * pc_cap;
         const int pn = min(P, pbeg + pc_cap) - pbeg;
-        if (pn > 0) build_tables<BS>(t, st, sm, pbeg, pn);
-        for (int u = threadIdx.x; u < N; u += BS) {
-            const int up_u = st.up[u];
-            int pbw_acc, up_acc, hop_acc, feas;
-            if (ch == 0) {
-                pbw_acc = up_u; up_acc = 0; hop_acc = 0;
-                feas = (st.cpu[u] >= cpu_i) & (st.ram[u] >= ram_i);
-            } else {
-                feas = xs[nc * N + u];
-                pbw_acc = xs[(nc + 1) * N + u];
-                up_acc = xs[(nc + 2) * N + u];
-                hop_acc = xs[(nc + 3) * N + u];
-            }
-            const int eu = u / t.h, pu = u / t.hh;
-            for (int pc = 0; pc < pn; ++pc) {
-                const int v = sm.ph[pbeg + pc];
-                if (v == u) continue;                 // co-located peer: no link
-                const int bw = sm.pbw[pbeg + pc];
-                int w = min(up_u, sm.upv[pbeg + pc]);
-                int hop = 2;
-                if (v / t.h != eu) {
-                    w = min(w, sm.tabE[pc * t.nsw + eu]);
-                    hop = (v / t.hh == pu) ? 4 : 6;
-                }
-                pbw_acc = min(pbw_acc, w);
-                up_acc += bw;
-                hop_acc += hop;
-                feas &= (w >= bw);
-            }
-            if (ch + 1 < nch) {
-                xs[nc * N + u] = feas;
-                xs[(nc + 1) * N + u] = pbw_acc;
-                xs[(nc + 2) * N + u] = up_acc;
-                xs[(nc + 3) * N + u] = hop_acc;
-                continue;
-            }
-            feas &= (up_u >= up_acc);
-            xs[nc * N + u] = feas;
+        if (pn > 0) {
+            if (ch == 0) peer_deficits<BS>(sm, P);
+            else __syncthreads();                       // previous chunk done with the tables
+            table_T<BS>(t, st, sm, pbeg, pn);
+            __syncthreads();
+            table_E<BS>(t, st, sm, pbeg, pn);
+            __syncthreads();
+        }
+        const int dh0 = sm.misc[M_DH0], dh1 = sm.misc[M_DH1];
+        const int de0 = sm.misc[M_DE0], de1 = sm.misc[M_DE1];
+        const int dp0 = sm.misc[M_DP0], dp1 = sm.misc[M_DP1];
+        // G servers per thread at a time: one peer record feeds all of
+        // them, and their independent chains hide the LDS latency
+        constexpr int kHostGroup = G;
+        for (int base = threadIdx.x; base < N; base += kHostGroup * BS) {
+            int uu[kHostGroup], up_u[kHostGroup], eu[kHostGroup], pu[kHostGroup];
+            int pbw_acc[kHostGroup], up_acc[kHostGroup], hop_acc[kHostGroup], feas[kHostGroup];
+            int oute[kHostGroup], outp[kHostGroup];
+            bool valid[kHostGroup];
 #pragma unroll
-            for (int c = 0; c < kMaxCrit; ++c) {
-                if (c >= nc) break;
-                int x;
-                switch (m.crit[c]) {
-                case CRIT_CPU: x = st.cpu[u]; break;
-                case CRIT_RAM: x = st.ram[u]; break;
-                case CRIT_ACTIVE: x = st.npl[u] > 0 ? 1 : 0; break;
-                case CRIT_PATHBW: x = pbw_acc; break;
-                case CRIT_UPLINK: x = up_u; break;
-                default: x = hop_acc; break;
+            for (int g = 0; g < kHostGroup; ++g) {
+                const int u = base + g * BS;
+                valid[g] = u < N;
+                const int us = valid[g] ? u : 0;
+                uu[g] = u;
+                up_u[g] = st.up[us];
+                eu[g] = fdiv(us, t.rh);
+                pu[g] = fdiv(us, t.rhh);
+                if (ch == 0) {
+                    pbw_acc[g] = up_u[g]; up_acc[g] = 0; hop_acc[g] = 0; oute[g] = 0; outp[g] = 0;
+                    int f = (st.cpu[us] >= cpu_i) & (st.ram[us] >= ram_i);
+                    f &= (dh1 < 0) | ((dh0 == dh1) & (u == dh0));
+                    f &= (de1 < 0) | ((de0 == de1) & (eu[g] == de0));
+                    f &= (dp1 < 0) | ((dp0 == dp1) & (pu[g] == dp0));
+                    feas[g] = f;
+                } else {
+                    feas[g] = xs[nc * N + us];
+                    pbw_acc[g] = xs[(nc + 1) * N + us];
+                    up_acc[g] = xs[(nc + 2) * N + us];
+                    hop_acc[g] = xs[(nc + 3) * N + us];
+                    oute[g] = xs[(nc + 4) * N + us];
+                    outp[g] = xs[(nc + 5) * N + us];
                 }
-                xs[c * N + u] = x;
-                if (STATS) {
-                    s2[c] += static_cast<unsigned long long>(static_cast<long long>(x) * x);
-                    mx[c] = max(mx[c], x);
-                    mn[c] = min(mn[c], x);
+            }
+            for (int pc = 0; pc < pn; ++pc) {
+                const int4 pk = sm.pk[pbeg + pc];
+                const int v = pk.x, bw = pk.z, ev = pk.y & 0xffff, pv = pk.y >> 16;
+                const int *te = sm.tabE + pc * t.nsw;
+#pragma unroll
+                for (int g = 0; g < kHostGroup; ++g) {
+                    const bool rem = v != uu[g];             // co-located peers use no link
+                    const bool far = ev != eu[g];
+                    const int e = te[eu[g]];
+                    int w = min(up_u[g], pk.w);
+                    w = far ? min(w, e) : w;
+                    const int hop = !rem ? 0 : !far ? 2 : (pv == pu[g] ? 4 : 6);
+                    pbw_acc[g] = rem ? min(pbw_acc[g], w) : pbw_acc[g];
+                    up_acc[g] += rem ? bw : 0;
+                    hop_acc[g] += hop;
+                    feas[g] &= (!rem) | (w >= bw);
+                    oute[g] += (rem & far) ? bw : 0;
+                    outp[g] += (rem & far & (pv != pu[g])) ? bw : 0;
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < kHostGroup; ++g) {
+                if (!valid[g]) continue;
+                const int u = uu[g];
+                if (ch + 1 < nch) {
+                    xs[nc * N + u] = feas[g];
+                    xs[(nc + 1) * N + u] = pbw_acc[g];
+                    xs[(nc + 2) * N + u] = up_acc[g];
+                    xs[(nc + 3) * N + u] = hop_acc[g];
+                    xs[(nc + 4) * N + u] = oute[g];
+                    xs[(nc + 5) * N + u] = outp[g];
+                    continue;
+                }
+                int f = feas[g] & (up_u[g] >= up_acc[g]);
+                if (P > 0) f &= (sm.capE[eu[g]] >= oute[g]) & (sm.capP[pu[g]] >= outp[g]);
+                xs[nc * N + u] = f;
+#pragma unroll
+                for (int c = 0; c < kMaxCrit; ++c) {
+                    if (c >= nc) break;
+                    int x;
+                    switch (m.crit[c]) {
+                    case CRIT_CPU: x = st.cpu[u]; break;
+                    case CRIT_RAM: x = st.ram[u]; break;
+                    case CRIT_ACTIVE: x = st.npl[u] > 0 ? 1 : 0; break;
+                    case CRIT_PATHBW: x = pbw_acc[g]; break;
+                    case CRIT_UPLINK: x = up_u[g]; break;
+                    default: x = hop_acc[g]; break;
+                    }
+                    xs[c * N + u] = x;
+                    if (STATS) {
+                        s2[c] += static_cast<unsigned long long>(static_cast<long long>(x) * x);
+                        mx[c] = max(mx[c], x);
+                        mn[c] = min(mn[c], x);
+                    }
                 }
             }
         }
-        if (ch + 1 < nch) __syncthreads();
+    }
+    if (STATS) {
+        // exact column statistics: the 64-bit sum of squares travels as
+        // three 17-bit chunks whose wave and block sums cannot overflow;
+        // each wave stores its partials in its own slots
+        const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+#pragma unroll
+        for (int c = 0; c < kMaxCrit; ++c) {
+            if (c >= nc) break;
+            const int c0 = wave_sum(static_cast<int>(s2[c] & 0x1ffffu));
+            const int c1 = wave_sum(static_cast<int>((s2[c] >> 17) & 0x1ffffu));
+            const int c2 = wave_sum(static_cast<int>(s2[c] >> 34));
+            const int hi = wave_max(mx[c]), lo = wave_min(mn[c]);
+            if (lane < 5) {
+                const int v = lane == 0 ? c0 : lane == 1 ? c1 : lane == 2 ? c2 : lane == 3 ? hi : -lo;
+                sm.wst[(5 * c + lane) * kMaxWaves + wid] = v;
+            }
+        }
     }
 }
 
-// Loads the peer list of container g into LDS.  Returns P.
+// Block totals of the column statistics from the per-wave slots (after a
+// barrier), computed by every wave on its own: the 16 lanes of a row take
+// one field's wave partials and reduce them with row DPP.  Fields 5c..5c+2
+// sum, 5c+3 and 5c+4 (max and -min) take the maximum.
 template <int BS>
-__device__ __forceinline__ int load_peers(const State &st, const Batch &b, const Smem &sm, int g0, int g) {
-    const int p0 = b.poff[g], P = b.poff[g + 1] - p0;
-    for (int p = threadIdx.x; p < P; p += BS) {
-        const int v = b.host[g0 + b.pj[p0 + p]];
-        sm.ph[p] = v;
-        sm.pbw[p] = b.pbw[p0 + p];
-        sm.upv[p] = st.up[v];
+__device__ __forceinline__ void finish_stats(const Smem &sm, int nc, unsigned long long *s2, int *mx, int *mn) {
+    constexpr int NW = BS / kWave;
+    const int lane = threadIdx.x & (kWave - 1), row = lane >> 4, w = lane & 15;
+    int fin[kStatFields];
+#pragma unroll
+    for (int r = 0; r < kStatFields / 4; ++r) {
+        if (4 * r >= 5 * nc) break;
+        const int f = 4 * r + row;
+        const bool is_sum = (f % 5) < 3;
+        const int id = is_sum ? 0 : -kBig - 1;
+        int v = (w < NW && f < 5 * nc) ? sm.wst[f * kMaxWaves + w] : id;
+        int vs = v, vm = v;
+        DCS_ROW_REDUCE(vs, op_add, 0);
+        DCS_ROW_REDUCE(vm, op_max, -kBig - 1);
+        const int res = is_sum ? vs : vm;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) fin[4 * r + q] = __builtin_amdgcn_readlane(res, 16 * q + 15);
     }
-    __syncthreads();
-    return P;
+#pragma unroll
+    for (int c = 0; c < kMaxCrit; ++c) {
+        if (c >= nc) break;
+        s2[c] = static_cast<unsigned long long>(static_cast<unsigned>(fin[5 * c])) +
+                (static_cast<unsigned long long>(static_cast<unsigned>(fin[5 * c + 1])) << 17) +
+                (static_cast<unsigned long long>(static_cast<unsigned>(fin[5 * c + 2])) << 34);
+        mx[c] = fin[5 * c + 3];
+        mn[c] = -fin[5 * c + 4];
+    }
 }
 
 __device__ __forceinline__ unsigned long long score_key(float s, int u) {
-    return (static_cast<unsigned long long>(__float_as_uint(s)) << 32) | static_cast<unsigned>(~u);
+    return (static_cast<unsigned long long>(__float_as_uint(s) + 1u) << 32) | static_cast<unsigned>(~u);
 }
 
-// Trace slot of this step, or -1.  Called by thread 0 only.
-__device__ __forceinline__ int trace_slot(const Trace &tr, int inst, int r, int i) {
+// Trace slot of this step, or -1.  Called by thread 0 only; rid is the
+// request id recorded in the slot's metadata.
+__device__ __forceinline__ int trace_slot(const Trace &tr, int inst, int rid, int i) {
     if (tr.stride <= 0) return -1;
     const int s = tr.counter[inst];
     tr.counter[inst] = s + 1;
@@ -423,43 +658,65 @@ __device__ __forceinline__ int trace_slot(const Trace &tr, int inst, int r, int 
     const int slot = s / tr.stride;
     if (slot >= tr.cap) return -1;
     tr.meta[4 * slot + 0] = inst;
-    tr.meta[4 * slot + 1] = r;
+    tr.meta[4 * slot + 1] = rid;
     tr.meta[4 * slot + 2] = i;
     tr.meta[4 * slot + 3] = s;
     return slot;
 }
 
-// Select-and-commit loop shared by TOPSIS and AHP: keys come from
-// key_of(u) (0 = infeasible).  Visits servers in decreasing key order by
-// repeated block argmax; a server whose commit fails is masked in the
-// feasibility row and the argmax repeats.  Rolls the request back when no
-// server is left.  Returns true when the container was placed.
-template <int BS, class KeyFn>
+// Select-and-commit loop shared by TOPSIS and AHP: key_of(u) gives the
+// score key of a feasible server (score bits + 1 above ~u, so a feasible
+// server's key is never 0).  Servers are visited in decreasing key order by
+// repeated block argmax (wave max, then one LDS atomic per wave); a server
+// whose commit fails is masked in the feasibility row, only its owner
+// thread rescans its servers, and the argmax repeats.  Rolls the request
+// back when no server is left.  Returns true when the container was placed.
+template <int BS, int G, class KeyFn>
 __device__ bool select_commit(const Topo &t, const State &st, const Batch &b, const Smem &sm, int *feas_row,
-                              int r, int i, int n, int g, int P, int cpu_i, int ram_i, KeyFn key_of) {
+                              const StepIn &s, const ReqView &rv, KeyFn key_of) {
     const int lane = threadIdx.x & (kWave - 1);
-    for (;;) {
+    auto scan = [&]() {
         unsigned long long kb = 0;
-        for (int u = threadIdx.x; u < t.N; u += BS) {
-            if (!feas_row[u]) continue;
-            const unsigned long long k = key_of(u);
-            kb = k > kb ? k : kb;
+        for (int base = threadIdx.x; base < t.N; base += G * BS) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int u = base + g * BS;
+                const int us = u < t.N ? u : 0;
+                const unsigned long long k = (u < t.N && feas_row[us]) ? key_of(us) : 0ull;
+                kb = k > kb ? k : kb;
+            }
         }
-        kb = block_max_u64<BS>(kb, sm.wkey);
-        if (kb == 0) {
-            rollback_request<BS>(t, st, b, r, i);
+        return kb;
+    };
+    constexpr int NW = BS / kWave;
+    const int wid = threadIdx.x / kWave;
+    unsigned long long mine = scan();
+    for (int it = 0;; ++it) {
+        unsigned *shi = sm.ahi + (it & 1) * kMaxWaves, *slo = sm.alo + (it & 1) * kMaxWaves;
+        // wave argmax: largest high word, then among those the largest low
+        // word; one slot per wave, then every wave reduces the slots
+        unsigned hiw = wave_umax(static_cast<unsigned>(mine >> 32));
+        unsigned low = wave_umax(static_cast<unsigned>(mine >> 32) == hiw ? static_cast<unsigned>(mine) : 0u);
+        if (lane == 0) { shi[wid] = hiw; slo[wid] = low; }
+        __syncthreads();
+        const unsigned wh = lane < NW ? shi[lane] : 0u, wl = lane < NW ? slo[lane] : 0u;
+        hiw = wave_umax(wh);
+        low = wave_umax(wh == hiw ? wl : 0u);
+        const unsigned long long kb = (static_cast<unsigned long long>(hiw) << 32) | low;
+        if (hiw == 0) {
+            rollback_request<BS>(t, st, b, s.r, s.i);
             return false;
         }
         const int u = static_cast<int>(~static_cast<unsigned>(kb & 0xffffffffu));
         if (threadIdx.x < kWave) {
-            const int p0 = b.poff[g];
-            const bool ok = commit_wave(t, st, u, cpu_i, ram_i, P, sm.ph, sm.pbw, b.code + p0, lane);
+            const bool ok = commit_wave(t, st, u, s.cpu, s.ram, s.P, sm, b.code + s.p0, lane);
             if (lane == 0) {
-                sm.misc[0] = ok;
+                sm.misc[M_OK] = ok;
                 if (ok) {
-                    b.host[g] = u;
-                    b.score[g] = __uint_as_float(static_cast<unsigned>(kb >> 32));
-                    if (i == n - 1) b.tse[r] = dev_clock();
+                    b.host[s.g] = u;
+                    if (rv.hosts_out) rv.hosts_out[s.i] = u;
+                    b.score[s.g] = __uint_as_float(static_cast<unsigned>(kb >> 32) - 1u);
+                    if (s.i == s.n - 1) b.tse[s.r] = dev_clock();
                 } else {
                     feas_row[u] = 0;
                 }
@@ -467,9 +724,8 @@ __device__ bool select_commit(const Topo &t, const State &st, const Batch &b, co
         }
         __threadfence_block();
         __syncthreads();
-        const int ok = sm.misc[0];
-        __syncthreads();
-        if (ok) return true;
+        if (sm.misc[M_OK]) return true;
+        if (u % BS == static_cast<int>(threadIdx.x)) mine = scan();
     }
 }
 
@@ -478,58 +734,30 @@ __device__ bool select_commit(const Topo &t, const State &st, const Batch &b, co
 // normalisation and weighting fold into q_c = w_c^2 / sum_u x_cu^2, so
 // Ed+- = sqrt(sum_c q_c (x_cu - A+-_c)^2) with A+- the column max / min in
 // raw units (swapped for cost criteria); Rank = Ed- / (Ed+ + Ed-), 0 when
-// both are 0.  Column statistics are exact integer reductions.
-template <int BS>
-__device__ void topsis_step(const Topo &t, const State &st, const Method &m, const Batch &b, const Smem &sm,
-                            int *xs, int pc_cap, const Trace &tr, int inst, int r, int i) {
-    const int g0 = b.coff[r];
-    const int n = b.coff[r + 1] - g0;
-    const int g = g0 + i;
-    if (b.status[r] == 0) return;
-    if (i == 0 && threadIdx.x == 0) b.tsb[r] = dev_clock();
-    const int cpu_i = b.cpu[g], ram_i = b.ram[g];
-    const int P = load_peers<BS>(st, b, sm, g0, g);
+// both are 0.  Column statistics are exact integer reductions.  Returns
+// false when the request was rejected at this container.
+template <int BS, int G = host_group(BS)>
+__device__ bool topsis_step(const Topo &t, const State &st, const Method &m, const Batch &b, const Smem &sm,
+                            int *xs, int pc_cap, const Trace &tr, int inst, const StepIn &s, const ReqView &rv) {
+    if (s.i == 0 && threadIdx.x == 0) b.tsb[s.r] = dev_clock();
+    if (threadIdx.x == 0) sm.misc[M_TRACE] = tr.stride > 0 ? trace_slot(tr, inst, b.rid[s.r], s.i) : -1;
+    load_peers<BS, true>(t, st, rv, sm, s.P);
     const int nc = m.nc, N = t.N;
+    criteria_stage<BS, true, G>(t, st, m, sm, xs, s.cpu, s.ram, s.P, pc_cap);
+    __syncthreads();
 
     unsigned long long s2[kMaxCrit];
     int mx[kMaxCrit], mn[kMaxCrit];
-#pragma unroll
-    for (int c = 0; c < kMaxCrit; ++c) { s2[c] = 0; mx[c] = -kBig; mn[c] = kBig; }
-    criteria_stage<BS, true>(t, st, m, sm, xs, cpu_i, ram_i, P, pc_cap, s2, mx, mn);
-
-    // column statistics: wave then block reduction
-    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-#pragma unroll
-    for (int c = 0; c < kMaxCrit; ++c) {
-        if (c >= nc) break;
-        const unsigned long long a = wave_sum_u64(s2[c]);
-        const int hi = wave_max_i(mx[c]), lo = wave_min_i(mn[c]);
-        if (lane == 0) { sm.ws2[wid * kMaxCrit + c] = a; sm.wmx[wid * kMaxCrit + c] = hi; sm.wmn[wid * kMaxCrit + c] = lo; }
-    }
-    __syncthreads();
-    if (threadIdx.x < nc) {
-        const int c = threadIdx.x;
-        unsigned long long a = 0;
-        int hi = -kBig, lo = kBig;
-        for (int w = 0; w < BS / kWave; ++w) {
-            a += sm.ws2[w * kMaxCrit + c];
-            hi = max(hi, sm.wmx[w * kMaxCrit + c]);
-            lo = min(lo, sm.wmn[w * kMaxCrit + c]);
-        }
-        const double wc = m.w[c];
-        sm.q[c] = a ? static_cast<float>(wc * wc / static_cast<double>(a)) : 0.0f;
-        sm.ap[c] = static_cast<float>(m.cost[c] ? lo : hi);
-        sm.am[c] = static_cast<float>(m.cost[c] ? hi : lo);
-    }
-    if (threadIdx.x == 0) sm.misc[1] = trace_slot(tr, inst, r, i);
-    __syncthreads();
-
+    finish_stats<BS>(sm, nc, s2, mx, mn);
     float q[kMaxCrit], ap[kMaxCrit], am[kMaxCrit];
 #pragma unroll
     for (int c = 0; c < kMaxCrit; ++c) {
-        q[c] = c < nc ? sm.q[c] : 0.f;
-        ap[c] = c < nc ? sm.ap[c] : 0.f;
-        am[c] = c < nc ? sm.am[c] : 0.f;
+        q[c] = ap[c] = am[c] = 0.f;
+        if (c >= nc) continue;
+        const unsigned long long a = s2[c];
+        q[c] = a ? (m.w[c] * m.w[c]) / static_cast<float>(a) : 0.0f;
+        ap[c] = static_cast<float>(m.cost[c] ? mn[c] : mx[c]);
+        am[c] = static_cast<float>(m.cost[c] ? mx[c] : mn[c]);
     }
     auto closeness = [&](int u) -> float {
         float dp2 = 0.f, dm2 = 0.f;
@@ -545,11 +773,11 @@ __device__ void topsis_step(const Topo &t, const State &st, const Method &m, con
         const float den = dp + dm;
         return den > 0.f ? dm / den : 0.f;
     };
-    const int slot = sm.misc[1];
+    const int slot = sm.misc[M_TRACE];
     if (slot >= 0)
         for (int u = threadIdx.x; u < N; u += BS) tr.scores[static_cast<size_t>(slot) * N + u] = closeness(u);
-    select_commit<BS>(t, st, b, sm, xs + nc * N, r, i, n, g, P, cpu_i, ram_i,
-                      [&](int u) { return score_key(closeness(u), u); });
+    return select_commit<BS, G>(t, st, b, sm, xs + nc * N, s, rv,
+                                             [&](int u) { return score_key(closeness(u), u); });
 }
 
 }  // namespace dcs

@@ -41,13 +41,16 @@ def check_scores(gpu, ref, tol=TOL, where=""):
 def lockstep(o, sched, ids, reqs, results, tol=TOL, trace=None, check_paths=False, state_every=False,
              instance=0):
     """Replays `reqs` (submitted to `sched` with ids `ids`, results keyed by
-    id) on oracle `o` in lockstep.  trace: optional dict (request position ->
-    list of (container, gpu score vector)).  Returns statistics."""
+    id) on oracle `o` in lockstep.  trace: optional dict (request id ->
+    list of (container, gpu score vector)).  state_every: compare the
+    integer state after each request (only meaningful when the GPU has
+    scheduled exactly these requests so far, one schedule call each).
+    Returns statistics."""
     st = dict(requests=0, accepted=0, rejected=0, steps=0, near_tie=0, scored_steps=0)
     for pos, (rid, req) in enumerate(zip(ids, reqs)):
         g = results[rid]
         follow = gpu_follow(sched, rid, g)
-        want_dump = trace is not None and pos in trace
+        want_dump = trace is not None and rid in trace
         ref = o.run_request(req, follow=follow, detail=True, dump=want_dump)
         assert ref["status"] == g.status, f"request {pos}: oracle status {ref['status']} vs gpu {g.status}"
         steps = g.n if g.status == 1 else g.failed_at + 1
@@ -66,7 +69,7 @@ def lockstep(o, sched, ids, reqs, results, tol=TOL, trace=None, check_paths=Fals
                 assert abs(float(g.scores[i]) - ref["scores"][i]) <= tol * max(abs(top), 1e-30), (
                     f"request {pos} step {i}: score {g.scores[i]} vs {ref['scores'][i]}")
         if want_dump:
-            for i, vec in trace[pos]:
+            for i, vec in trace[rid]:
                 check_scores(vec, ref["dump"][i], tol, where=f"request {pos} step {i}")
                 st["scored_steps"] += 1
         if check_paths and g.status == 1:
@@ -85,10 +88,10 @@ def lockstep(o, sched, ids, reqs, results, tol=TOL, trace=None, check_paths=Fals
     return st
 
 
-def trace_by_request(sched, ids_in_batch_order):
-    """GPU trace grouped by request position: {pos: [(container, scores)]}."""
+def trace_by_request(sched, ids=None):
+    """GPU trace grouped by request id: {id: [(container, scores)]}."""
     meta, scores = sched.trace()
     out = {}
-    for (inst, r, i, s), vec in zip(meta, scores):
-        out.setdefault(int(r), []).append((int(i), vec))
+    for (inst, rid, i, s), vec in zip(meta, scores):
+        out.setdefault(int(rid), []).append((int(i), vec))
     return out
