@@ -126,7 +126,18 @@ int dc_submit_request(dc_ctx *ctx, int32_t instance, int32_t n, const int32_t *c
  * instance) and block until done; results of the scheduled requests go to
  * out[0..*n_out) in request id order (at most max_results are written; the
  * rest stay available to the next call).  Serving form: non-blocking poll of
- * completed requests. */
+ * completed requests, in completion (= submission) order.
+ *
+ * Serving form (mode DC_MODE_SERVING, one instance): a persistent kernel
+ * keeps the state on the device and takes requests and departures in the
+ * order dc_submit_request / dc_release publish them, while the caller keeps
+ * submitting (continuous batching).  Each live request holds a slot of a
+ * device arena of cfg.mem_budget bytes; dc_submit_request returns
+ * DC_EAGAIN when the arena or the 1024-entry command ring is full (poll
+ * with dc_schedule, release, and retry).  dc_release returns DC_EAGAIN for a
+ * request not yet decided.  dc_get_state returns DC_EAGAIN while commands
+ * are in flight.  The kernel exits after one second without commands and is
+ * relaunched by the next call; dc_destroy stops it. */
 int dc_schedule(dc_ctx *ctx, int32_t max_results, dc_result *out, int32_t *n_out);
 
 /* Departure of an accepted request: gives back its CPU, RAM and path
@@ -170,6 +181,11 @@ int dc_get_trace(dc_ctx *ctx, int32_t cap, int32_t *meta, float *scores, int32_t
  * The state and queue are left unchanged.  DC_ESTATE when nothing is
  * queued or in the serving form. */
 int dc_autotune(dc_ctx *ctx, int32_t *block);
+
+/* Work not yet decided: in the serving form the commands (requests and
+ * departures) published but not completed, otherwise the requests queued
+ * for the next dc_schedule.  Polls completions in the serving form. */
+int dc_pending(dc_ctx *ctx, int64_t *n);
 
 /* Milliseconds the last dc_schedule spent on the device, measured with HIP
  * events around its launches on the context's stream, and the number of

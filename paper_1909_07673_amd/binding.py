@@ -72,6 +72,7 @@ def lib():
         L.dc_get_trace.argtypes = [P, C.c_int32, i32p, C.POINTER(C.c_float), C.POINTER(C.c_int32)]
         L.dc_autotune.argtypes = [P, C.POINTER(C.c_int32)]
         L.dc_last_timing.argtypes = [P, C.POINTER(C.c_float), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.dc_pending.argtypes = [P, C.POINTER(C.c_int64)]
         L.dc_destroy.argtypes = [P]
         L.dc_destroy.restype = None
         L.dc_strerror.argtypes = [C.c_int]
@@ -237,6 +238,35 @@ class Scheduler:
         b = C.c_int32()
         _check(lib().dc_autotune(self._ctx, C.byref(b)), "dc_autotune")
         return b.value
+
+    def pending(self) -> int:
+        n = C.c_int64()
+        _check(lib().dc_pending(self._ctx, C.byref(n)), "dc_pending")
+        return n.value
+
+    def try_submit(self, req, instance: int = 0):
+        """Serving form: returns the request id, or None when admission is
+        refused for now (DC_EAGAIN)."""
+        try:
+            return self.submit(req, instance)
+        except DcError as e:
+            if e.code == DC_EAGAIN:
+                return None
+            raise
+
+    def drain(self, timeout_s: float = 120.0) -> List[Result]:
+        """Serving form: polls until every published command completed."""
+        import time
+        out = []
+        t0 = time.monotonic()
+        while True:
+            out.extend(self.schedule())
+            if self.pending() == 0:
+                out.extend(self.schedule())
+                return out
+            if time.monotonic() - t0 > timeout_s:
+                raise TimeoutError("serving commands did not complete")
+            time.sleep(1e-4)
 
     def last_timing(self):
         ms, la, st = C.c_float(), C.c_int64(), C.c_int64()

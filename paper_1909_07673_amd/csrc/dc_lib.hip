@@ -4,13 +4,17 @@
 // batched (one persistent launch) forms, and collects results.
 #include "../../include/dcsched.h"
 #include "dc_kernels.hpp"
+#include "dc_serve.hpp"
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <chrono>
 #include <deque>
+#include <map>
 #include <memory>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -35,6 +39,67 @@ struct ReqLoc {
     int batch = -1, r = -1;
     bool released = false;
 };
+
+// Serving form: one live request's slot in the device arena.
+struct ServeSlot {
+    size_t off = 0, ints = 0;      // offset and size in the arena (int32 units)
+    int n = 0, P = 0;
+    int status = -1;               // -1 pending, 1 accepted, 0 rejected
+    bool released = false;
+    std::vector<int> hosts;        // attempt record from the completion
+};
+
+// Serving form state: rings in coherent pinned host memory, the device slot
+// arena with a first-fit allocator, and the host's ring positions.
+struct Serve {
+    Cmd *cmds = nullptr;
+    Comp *comps = nullptr;
+    int *ctrl = nullptr;
+    int *staging = nullptr;
+    int *arena = nullptr;
+    size_t arena_ints = 0;
+    std::map<size_t, size_t> free_list;     // offset -> size, int32 units
+    int cap = 1024, stage_ints = 0, bs = 1024, pc = 1;
+    size_t lds = 0;
+    long long idle_ticks = 100000000LL;     // 1 s of device clock
+    int64_t host_pos = 0, comp_pos = 0;     // commands published / completions consumed
+    std::unordered_map<int64_t, ServeSlot> slots;
+    std::unordered_map<int, int64_t> rid_to_id;
+    std::vector<std::pair<int64_t, float>> service_us;
+    hipStream_t aux = nullptr;              // copies while the persistent kernel runs
+    bool launched = false;
+};
+
+bool serve_alloc(Serve &sv, size_t ints, size_t *off) {
+    ints = (ints + 3) & ~size_t(3);
+    for (auto it = sv.free_list.begin(); it != sv.free_list.end(); ++it) {
+        if (it->second >= ints) {
+            *off = it->first;
+            const size_t rest = it->second - ints, roff = it->first + ints;
+            sv.free_list.erase(it);
+            if (rest) sv.free_list[roff] = rest;
+            return true;
+        }
+    }
+    return false;
+}
+
+void serve_free(Serve &sv, size_t off, size_t ints) {
+    ints = (ints + 3) & ~size_t(3);
+    auto it = sv.free_list.emplace(off, ints).first;
+    auto nx = std::next(it);
+    if (nx != sv.free_list.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        sv.free_list.erase(nx);
+    }
+    if (it != sv.free_list.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            sv.free_list.erase(it);
+        }
+    }
+}
 
 }  // namespace
 
@@ -69,6 +134,7 @@ struct dc_ctx {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     float last_ms = 0.f;
     int64_t last_launches = 0, last_steps = 0;
+    std::unique_ptr<Serve> sv;     // serving form only
 };
 
 #define HIPCHK(expr)                                       \
@@ -363,6 +429,188 @@ int collect(dc_ctx *ctx, DevBatch &b) {
     return DC_OK;
 }
 
+// ---------------------------------------------------------------- serving form
+int serve_init(dc_ctx *ctx) {
+    auto sv = std::make_unique<Serve>();
+    const size_t budget = ctx->cfg.mem_budget ? ctx->cfg.mem_budget : (size_t)256 << 20;
+    sv->arena_ints = budget / sizeof(int);
+    sv->stage_ints = slot_layout(kMaxN, kMaxPairs).in_end;
+    const unsigned fl = hipHostMallocCoherent | hipHostMallocMapped;
+    HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&sv->cmds), sizeof(Cmd) * sv->cap, fl));
+    HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&sv->comps), sizeof(Comp) * sv->cap, fl));
+    HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&sv->ctrl), sizeof(int) * 4, fl));
+    HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&sv->staging), sizeof(int) * (size_t)sv->stage_ints * sv->cap, fl));
+    std::memset(sv->cmds, 0, sizeof(Cmd) * sv->cap);
+    std::memset(sv->comps, 0, sizeof(Comp) * sv->cap);
+    std::memset(sv->ctrl, 0, sizeof(int) * 4);
+    HIPCHK(hipMalloc(&sv->arena, sv->arena_ints * sizeof(int)));
+    sv->free_list[0] = sv->arena_ints & ~size_t(3);
+    HIPCHK(hipStreamCreateWithFlags(&sv->aux, hipStreamNonBlocking));
+    sv->bs = ctx->N <= 256 ? 256 : 512;
+    const size_t lds_max = 159 * 1024;   // 160 KiB of LDS, 1 KiB left for static shared memory
+    const size_t base = step_lds_bytes(0, ctx->t.nsw, req_lds_ints(), 0);
+    sv->pc = (int)std::max<size_t>(1, std::min<size_t>(kMaxN, (lds_max - base) / (8 * (size_t)ctx->t.nsw)));
+    sv->lds = step_lds_bytes(sv->pc, ctx->t.nsw, req_lds_ints(), 0);
+    if (sv->lds > lds_max) return DC_EINVAL;
+    if (set_lds(ctx, k_serve<256>, sv->lds) || set_lds(ctx, k_serve<512>, sv->lds)) return DC_EDEVICE;
+    ctx->sv = std::move(sv);
+    return DC_OK;
+}
+
+// (Re)launches the persistent kernel when commands wait and none runs.
+int serve_ensure_running(dc_ctx *ctx) {
+    Serve &sv = *ctx->sv;
+    const int dev_pos = __atomic_load_n(sv.ctrl, __ATOMIC_ACQUIRE);
+    if (dev_pos >= sv.host_pos) return DC_OK;
+    if (sv.launched) {
+        const hipError_t q = hipStreamQuery(ctx->stream);
+        if (q == hipErrorNotReady) return DC_OK;      // still running: it will reach the command
+        HIPCHK(q);
+    }
+    Params p{};
+    p.t = ctx->t;
+    p.st = state_of(ctx, 0);
+    p.m = ctx->m;
+    p.tr = Trace{nullptr, nullptr, nullptr, 0, 0};
+    p.xs = ctx->d_xs;
+    p.pc_cap = sv.pc;
+    ServeArgs a{sv.cmds, sv.comps, sv.ctrl, sv.staging, sv.arena, sv.cap, sv.stage_ints, dev_pos, 0, sv.idle_ticks};
+    __atomic_store_n(sv.ctrl + 1, 0, __ATOMIC_RELEASE);
+    if (sv.bs == 256) hipLaunchKernelGGL((k_serve<256>), dim3(1), dim3(256), sv.lds, ctx->stream, p, a);
+    else hipLaunchKernelGGL((k_serve<512>), dim3(1), dim3(512), sv.lds, ctx->stream, p, a);
+    HIPCHK(hipGetLastError());
+    sv.launched = true;
+    return DC_OK;
+}
+
+// Publishes one command; the caller has checked ring space.
+void serve_publish(Serve &sv, int type, int n, int P, size_t off, int rid) {
+    Cmd &c = sv.cmds[sv.host_pos % sv.cap];
+    c.type = type;
+    c.n = n;
+    c.npair = P;
+    c.slot_off = (int)off;
+    c.rid = rid;
+    __atomic_store_n(&c.seq, (int)(sv.host_pos + 1), __ATOMIC_RELEASE);
+    ++sv.host_pos;
+}
+
+int serve_poll(dc_ctx *ctx) {
+    Serve &sv = *ctx->sv;
+    while (sv.comp_pos < sv.host_pos) {
+        Comp &c = sv.comps[sv.comp_pos % sv.cap];
+        if (__atomic_load_n(&c.seq, __ATOMIC_ACQUIRE) != (int)(sv.comp_pos + 1)) break;
+        auto rit = sv.rid_to_id.find(c.rid);
+        if (rit != sv.rid_to_id.end()) {
+            const int64_t id = rit->second;
+            ServeSlot &sl = sv.slots[id];
+            if (c.type == CMD_SUBMIT) {
+                sl.status = c.status;
+                sl.hosts.assign(c.host, c.host + c.n);
+                dc_result res;
+                std::memset(&res, 0, sizeof res);
+                res.req_id = id;
+                res.instance = 0;
+                res.status = c.status;
+                res.n = c.n;
+                res.failed_at = c.status ? -1 : c.failat;
+                for (int i = 0; i < DC_MAX_CONTAINERS; ++i) res.host[i] = -1;
+                for (int i = 0; i < c.n; ++i) {
+                    res.host[i] = c.status ? c.host[i] : -1;
+                    res.score[i] = c.score[i];
+                }
+                ctx->ready.push_back(res);
+                sv.service_us.emplace_back(id, (float)((c.t_decide - c.t_admit) / 100.0));
+                if (!c.status) serve_free(sv, sl.off, sl.ints);   // rejected: nothing left to release
+            } else {
+                serve_free(sv, sl.off, sl.ints);                   // departure done
+            }
+        }
+        ++sv.comp_pos;
+    }
+    return serve_ensure_running(ctx);
+}
+
+int serve_submit(dc_ctx *ctx, int n, const int *cpu, const int *ram, int m, const int *edges, int64_t *req_id) {
+    Serve &sv = *ctx->sv;
+    int rc = serve_poll(ctx);
+    if (rc) return rc;
+    // peers of container i: edges (i, j), j < i, ascending j
+    std::vector<int> bwm((size_t)n * n, 0);
+    for (int q = 0; q < m; ++q) {
+        bwm[(size_t)edges[3 * q] * n + edges[3 * q + 1]] = edges[3 * q + 2];
+        bwm[(size_t)edges[3 * q + 1] * n + edges[3 * q]] = edges[3 * q + 2];
+    }
+    std::vector<int> poff(1, 0), pj, pbw;
+    for (int i = 0; i < n; ++i) {
+        for (int j = 0; j < i; ++j)
+            if (bwm[(size_t)i * n + j]) { pj.push_back(j); pbw.push_back(bwm[(size_t)i * n + j]); }
+        poff.push_back((int)pj.size());
+    }
+    const int P = (int)pj.size();
+    const SlotLayout L = slot_layout(n, P);
+    if (sv.host_pos - sv.comp_pos >= sv.cap) return DC_EAGAIN;
+    size_t off = 0;
+    if (!serve_alloc(sv, (size_t)L.total, &off)) return DC_EAGAIN;
+    const int64_t id = ctx->next_id++;
+    const int rid = (int)(id & 0x7fffffff);
+    int *stg = sv.staging + (size_t)(sv.host_pos % sv.cap) * sv.stage_ints;
+    stg[L.coff] = 0;
+    stg[L.coff + 1] = n;
+    std::memcpy(stg + L.cpu, cpu, sizeof(int) * n);
+    std::memcpy(stg + L.ram, ram, sizeof(int) * n);
+    std::memcpy(stg + L.poff, poff.data(), sizeof(int) * (n + 1));
+    if (P) {
+        std::memcpy(stg + L.pj, pj.data(), sizeof(int) * P);
+        std::memcpy(stg + L.pbw, pbw.data(), sizeof(int) * P);
+    }
+    stg[L.rid] = rid;
+    ServeSlot sl;
+    sl.off = off;
+    sl.ints = (size_t)L.total;
+    sl.n = n;
+    sl.P = P;
+    sv.slots[id] = sl;
+    sv.rid_to_id[rid] = id;
+    serve_publish(sv, CMD_SUBMIT, n, P, off, rid);
+    if (req_id) *req_id = id;
+    return serve_ensure_running(ctx);
+}
+
+int serve_release(dc_ctx *ctx, int64_t req_id) {
+    Serve &sv = *ctx->sv;
+    int rc = serve_poll(ctx);
+    if (rc) return rc;
+    auto it = sv.slots.find(req_id);
+    if (it == sv.slots.end() || it->second.released) return DC_ENOENT;
+    ServeSlot &sl = it->second;
+    if (sl.status < 0) return DC_EAGAIN;          // not decided yet
+    if (sl.status == 0) return DC_ENOENT;         // rejected: holds nothing
+    if (sv.host_pos - sv.comp_pos >= sv.cap) return DC_EAGAIN;
+    sl.released = true;
+    serve_publish(sv, CMD_RELEASE, sl.n, sl.P, sl.off, (int)(req_id & 0x7fffffff));
+    return serve_ensure_running(ctx);
+}
+
+// Stops the persistent kernel: publishes STOP and waits (bounded) for it.
+int serve_stop(dc_ctx *ctx) {
+    Serve &sv = *ctx->sv;
+    if (!sv.launched) return DC_OK;
+    const auto t0 = std::chrono::steady_clock::now();
+    while (sv.host_pos - sv.comp_pos >= sv.cap) {
+        int rc = serve_poll(ctx);
+        if (rc) return rc;
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(60)) return DC_EDEVICE;
+    }
+    if (hipStreamQuery(ctx->stream) == hipErrorNotReady) serve_publish(sv, CMD_STOP, 0, 0, 0, -1);
+    while (hipStreamQuery(ctx->stream) == hipErrorNotReady) {
+        std::this_thread::sleep_for(std::chrono::microseconds(100));
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(60)) return DC_EDEVICE;
+    }
+    sv.launched = false;
+    return DC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -385,7 +633,6 @@ int dc_create(const dc_config *cfg, dc_ctx **out) {
     *out = nullptr;
     int rc = check_config(cfg);
     if (rc) return rc;
-    if (cfg->mode == DC_MODE_SERVING) return DC_ESTATE;   // served by dc_serve_* (see serving form)
     const int k = cfg->k, h = k / 2, N = k * k * k / 4, I = cfg->n_instances;
     // background load must stay within capacity
     if (cfg->host_used)
@@ -453,7 +700,7 @@ int dc_create(const dc_config *cfg, dc_ctx **out) {
     // launch shapes
     c->plain_bs = cfg->block ? cfg->block : (N <= 64 ? 64 : N <= 256 ? 256 : 1024);
     c->batched_bs = cfg->block ? std::max(256, cfg->block) : 1024;
-    const size_t lds_max = 160 * 1024;
+    const size_t lds_max = 159 * 1024;   // 160 KiB of LDS, 1 KiB left for static shared memory
     {
         // plain: state + scratch in LDS when they fit with at least 8 peer tables
         const size_t res_fixed = step_lds_bytes(0, c->t.nsw, (size_t)xs_rows(nc) * N, 6 * (size_t)N);
@@ -505,6 +752,11 @@ int dc_create(const dc_config *cfg, dc_ctx **out) {
         }
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, c->stream, c->d_tcount, 0, (long long)I);
     }
+    if (cfg->mode == DC_MODE_SERVING) {
+        if (I != 1) { dc_destroy(ctx.release()); return DC_EINVAL; }
+        const int src = serve_init(c);
+        if (src) { dc_destroy(ctx.release()); return src; }
+    }
     if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
         c->poisoned = true;
@@ -530,6 +782,7 @@ int dc_submit_request(dc_ctx *ctx, int32_t instance, int32_t n, const int32_t *c
     }
     for (int i = 0; i < n; ++i)
         if (cpu[i] < 0 || ram[i] < 0 || cpu[i] > (1 << 22) || ram[i] > (1 << 22)) return DC_EINVAL;
+    if (ctx->sv) return serve_submit(ctx, n, cpu, ram, m, edges, req_id);
     ctx->pend_inst.push_back(instance);
     ctx->pend_n.push_back(n);
     ctx->pend_cpu.emplace_back(cpu, cpu + n);
@@ -544,9 +797,9 @@ int dc_submit_request(dc_ctx *ctx, int32_t instance, int32_t n, const int32_t *c
 int dc_schedule(dc_ctx *ctx, int32_t max_results, dc_result *out, int32_t *n_out) {
     if (!ctx || max_results < 0 || (max_results > 0 && !out)) return DC_EINVAL;
     if (ctx->poisoned) return DC_EDEVICE;
-    int rc = upload_pending(ctx);
+    int rc = ctx->sv ? serve_poll(ctx) : upload_pending(ctx);
     if (rc) return rc;
-    if (!ctx->queued.empty()) {
+    if (!ctx->sv && !ctx->queued.empty()) {
         ctx->last_launches = 0;
         ctx->last_steps = 0;
         HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
@@ -575,6 +828,7 @@ int dc_schedule(dc_ctx *ctx, int32_t max_results, dc_result *out, int32_t *n_out
 int dc_release(dc_ctx *ctx, int64_t req_id) {
     if (!ctx) return DC_EINVAL;
     if (ctx->poisoned) return DC_EDEVICE;
+    if (ctx->sv) return serve_release(ctx, req_id);
     auto it = ctx->loc.find(req_id);
     if (it == ctx->loc.end() || it->second.released) return DC_ENOENT;
     DevBatch &b = *ctx->batches[it->second.batch];
@@ -592,6 +846,27 @@ int dc_release(dc_ctx *ctx, int64_t req_id) {
 
 int dc_get_paths(dc_ctx *ctx, int64_t req_id, int32_t cap, int32_t *link_ids, int32_t *n) {
     if (!ctx || cap < 0 || (cap > 0 && !link_ids)) return DC_EINVAL;
+    if (ctx->sv) {
+        auto sit = ctx->sv->slots.find(req_id);
+        if (sit == ctx->sv->slots.end() || sit->second.status != 1 || sit->second.released) return DC_ENOENT;
+        const ServeSlot &sl = sit->second;
+        std::vector<int> slot(sl.ints);
+        HIPCHK(hipMemcpyAsync(slot.data(), ctx->sv->arena + sl.off, sl.ints * sizeof(int), hipMemcpyDeviceToHost,
+                              ctx->sv->aux));
+        HIPCHK(hipStreamSynchronize(ctx->sv->aux));
+        const SlotLayout L = slot_layout(sl.n, sl.P);
+        int q = 0;
+        for (int g = 0; g < sl.n; ++g)
+            for (int x = slot[L.poff + g]; x < slot[L.poff + g + 1]; ++x, ++q) {
+                if (q >= cap) continue;
+                int *dst = link_ids + 6 * (size_t)q;
+                for (int l = 0; l < 6; ++l) dst[l] = -1;
+                const int u = slot[L.host + g], v = slot[L.host + slot[L.pj + x]], c = slot[L.code + x];
+                if (u != v && c >= 0) host_path_links(ctx->t, u, v, c, dst);
+            }
+        if (n) *n = q;
+        return DC_OK;
+    }
     auto it = ctx->loc.find(req_id);
     if (it == ctx->loc.end()) return DC_ENOENT;
     DevBatch &b = *ctx->batches[it->second.batch];
@@ -613,6 +888,14 @@ int dc_get_paths(dc_ctx *ctx, int64_t req_id, int32_t cap, int32_t *link_ids, in
 
 int dc_get_attempt(dc_ctx *ctx, int64_t req_id, int32_t cap, int32_t *hosts, int32_t *n) {
     if (!ctx || cap < 0 || (cap > 0 && !hosts)) return DC_EINVAL;
+    if (ctx->sv) {
+        auto sit = ctx->sv->slots.find(req_id);
+        if (sit == ctx->sv->slots.end() || sit->second.status < 0) return DC_ENOENT;
+        const std::vector<int> &hv = sit->second.hosts;
+        for (int i = 0; i < (int)hv.size() && i < cap; ++i) hosts[i] = hv[i];
+        if (n) *n = (int)hv.size();
+        return DC_OK;
+    }
     auto it = ctx->loc.find(req_id);
     if (it == ctx->loc.end()) return DC_ENOENT;
     DevBatch &b = *ctx->batches[it->second.batch];
@@ -627,6 +910,7 @@ int dc_get_attempt(dc_ctx *ctx, int64_t req_id, int32_t cap, int32_t *hosts, int
 int dc_get_latency(dc_ctx *ctx, int32_t cap, float *service_us, int32_t *n) {
     if (!ctx || cap < 0 || (cap > 0 && !service_us)) return DC_EINVAL;
     std::vector<std::pair<int64_t, float>> v;
+    if (ctx->sv) v = ctx->sv->service_us;
     for (auto &B : ctx->batches) {
         const DevBatch &b = *B;
         for (int r = 0; r < (int)b.tse.size(); ++r)
@@ -642,15 +926,23 @@ int dc_get_latency(dc_ctx *ctx, int32_t cap, float *service_us, int32_t *n) {
 int dc_get_state(dc_ctx *ctx, int32_t instance, int32_t *out) {
     if (!ctx || !out || instance < 0 || instance >= ctx->I) return DC_EINVAL;
     if (ctx->poisoned) return DC_EDEVICE;
+    hipStream_t s = ctx->stream;
+    if (ctx->sv) {
+        int rc = serve_poll(ctx);
+        if (rc) return rc;
+        if (ctx->sv->comp_pos != ctx->sv->host_pos) return DC_EAGAIN;   // commands still in flight
+        s = ctx->sv->aux;
+    }
     HIPCHK(hipMemcpyAsync(out, ctx->d_state + (size_t)instance * 6 * ctx->N, 6 * (size_t)ctx->N * sizeof(int),
-                          hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
     return DC_OK;
 }
 
 int dc_rewind(dc_ctx *ctx) {
     if (!ctx) return DC_EINVAL;
     if (ctx->poisoned) return DC_EDEVICE;
+    if (ctx->sv) return DC_ESTATE;
     int rc = upload_pending(ctx);
     if (rc) return rc;
     HIPCHK(hipMemcpyAsync(ctx->d_state, ctx->d_init, (size_t)ctx->I * 6 * ctx->N * sizeof(int),
@@ -730,6 +1022,21 @@ int dc_autotune(dc_ctx *ctx, int32_t *block) {
     return DC_OK;
 }
 
+int dc_pending(dc_ctx *ctx, int64_t *n) {
+    if (!ctx || !n) return DC_EINVAL;
+    if (ctx->poisoned) return DC_EDEVICE;
+    if (ctx->sv) {
+        int rc = serve_poll(ctx);
+        if (rc) return rc;
+        *n = ctx->sv->host_pos - ctx->sv->comp_pos;
+    } else {
+        int64_t q = (int64_t)ctx->pend_ids.size();
+        for (int bi : ctx->queued) q += ctx->batches[bi]->R;
+        *n = q;
+    }
+    return DC_OK;
+}
+
 int dc_last_timing(dc_ctx *ctx, float *ms, int64_t *launches, int64_t *steps) {
     if (!ctx) return DC_EINVAL;
     if (ms) *ms = ctx->last_ms;
@@ -740,6 +1047,18 @@ int dc_last_timing(dc_ctx *ctx, float *ms, int64_t *launches, int64_t *steps) {
 
 void dc_destroy(dc_ctx *ctx) {
     if (!ctx) return;
+    if (ctx->sv) {
+        if (!ctx->poisoned && serve_stop(ctx) != DC_OK) ctx->poisoned = true;
+        Serve &sv = *ctx->sv;
+        if (!ctx->poisoned) {
+            if (sv.cmds) (void)hipHostFree(sv.cmds);
+            if (sv.comps) (void)hipHostFree(sv.comps);
+            if (sv.ctrl) (void)hipHostFree(sv.ctrl);
+            if (sv.staging) (void)hipHostFree(sv.staging);
+            if (sv.arena) (void)hipFree(sv.arena);
+        }
+        if (sv.aux) (void)hipStreamDestroy(sv.aux);
+    }
     if (!ctx->poisoned && ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     for (auto &b : ctx->batches)
         if (b->dmem) (void)hipFree(b->dmem);
