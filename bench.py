@@ -7,12 +7,12 @@ and every request is scheduled in FCFS order -- per container: path stage,
 criteria, scoring, selection, commit -- with the results copied back.  The
 requests are uploaded to HBM before the timed region.
 
-Default workload: k=16 fat-tree (1024 hosts), 40 Gbps host links, 100 Gbps
-edge-aggregation / aggregation-core links, 0-70 % background load, 2,000
-FCFS requests of 2-32 containers, TOPSIS over (CPU, RAM, active, path
-bandwidth), plain form: one kernel launch per container step.
-
-Prints one JSON line.
+Default workload (one JSON line): k=16 fat-tree (1024 hosts), 40 Gbps host
+links, 100 Gbps edge-aggregation / aggregation-core links, 0-70 %
+background load, 2,000 FCFS requests of 2-32 containers, TOPSIS over (CPU,
+RAM, active, path bandwidth), plain form: one kernel launch per container
+step.  Other workloads (--workload) measure the batched form (256
+instances), the large AHP case and the serving form on a Poisson trace.
 """
 import argparse
 import json
@@ -29,6 +29,9 @@ HBM_PEAK_GBS = 8000.0
 # state arrays (CPU, RAM, placed count, uplink, edge-aggregation and
 # aggregation-core residuals) read once per scored host.
 BYTES_PER_HOST_SCORE = 24
+# FP32 vector issue rate of MI355X without packed math: 256 CUs x 4 SIMDs x
+# 16 lanes x 2.4 GHz lane-instructions per second.
+VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 WORKLOADS = {
     "plain": dict(preset="plain", mode="plain", method="topsis",
@@ -37,24 +40,27 @@ WORKLOADS = {
     "batched": dict(preset="batched", mode="batched", method="topsis",
                     text="256 independent k=16 fat-trees (1024 hosts each), 64-512 requests of 2-48 containers "
                          "per instance, TOPSIS, batched form (one persistent launch)"),
+    "ahp": dict(preset="ahp", mode="plain", method="ahp",
+                text="k=32 fat-tree (8192 hosts), 500 FCFS requests of 8-64 containers, 0-70% background, AHP "
+                     "(Saaty 1-9) on CPU/RAM/uplink/path-bw/hops(cost), four launches per container step"),
+    "serving": dict(preset="serving", mode="serving", method="topsis",
+                    text="k=48 fat-tree (27648 hosts), 0-70% background, Poisson arrivals at 5000 req/s of 2-64 "
+                         "containers, exponential lifetimes (mean 60 s) releasing their resources, TOPSIS, "
+                         "serving form (persistent kernel) against the plain form on the same trace"),
 }
 
 
-def host_scores(results, N):
-    steps = 0
-    for r in results:
-        steps += r.n if r.status == 1 else r.failed_at + 1
-    return steps, steps * N
+def step_count(results):
+    return sum(r.n if r.status == 1 else r.failed_at + 1 for r in results)
 
 
-def cpu_baseline(insts, reqs, budget_s):
+def cpu_baseline(insts, reqs, budget_s, meth):
     """The FP64 oracle, as it stands, on a bounded prefix of the same
     workload (single thread)."""
     import oracle
-    steps = 0
+    steps = n_req = 0
     t0 = time.perf_counter()
-    n_req = 0
-    o = oracle.Oracle(insts[0], oracle.method(kind=oracle.TOPSIS))
+    o = oracle.Oracle(insts[0], meth)
     for req in reqs[0]:
         res = o.run_request(req)
         steps += req.n if res["status"] == 1 else res["failed_at"] + 1
@@ -62,10 +68,192 @@ def cpu_baseline(insts, reqs, budget_s):
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
-    N = insts[0].k ** 3 // 4
+    N = insts[0].n_hosts
     return dict(value=steps * N / dt, unit="host-scores/s", cores=1, kind="oracle",
                 sample=f"first {n_req} requests ({steps} container steps) of the same workload on one host "
                        f"thread, {dt:.1f} s")
+
+
+def percentiles(x):
+    import numpy as np
+    x = np.asarray(x, dtype=np.float64)
+    return {"p50": float(np.percentile(x, 50)), "p99": float(np.percentile(x, 99))} if x.size else None
+
+
+def run_batch(args, wl):
+    """Plain / batched / AHP: rewind + schedule all requests per step."""
+    import numpy as np
+    import torch
+    import oracle
+    import paper_1909_07673_amd as dc
+    from workloads import make_config
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    insts, reqs = make_config(wl["preset"], seed=0)
+    N = insts[0].n_hosts
+    kw = {}
+    if wl["method"] == "ahp":
+        kw = dict(method=dc.DC_AHP, crit=(dc.DC_CRIT_CPU, dc.DC_CRIT_RAM, dc.DC_CRIT_UPLINK, dc.DC_CRIT_PATHBW,
+                                          dc.DC_CRIT_HOPS), cost=(0, 0, 0, 0, 1))
+    mode = dc.DC_MODE_BATCHED if wl["mode"] == "batched" else dc.DC_MODE_PLAIN
+    s = dc.Scheduler(insts, mode=mode, stream=stream, **kw)
+    for i, rl in enumerate(reqs):
+        for r in rl:
+            s.submit(r, instance=i)
+    s.rewind()                      # uploads the requests; they stay resident in HBM
+    tuned = s.autotune() if wl["method"] == "topsis" else None
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        s.rewind()
+        s.schedule()
+    torch.cuda.synchronize()
+    kern_ms, launches, results = 0.0, 0, None
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s.rewind()
+        results = s.schedule()
+        ms, la, _ = s.last_timing()
+        kern_ms += ms
+        launches += la
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    steps = step_count(results)
+    hs = steps * N
+    value = hs * args.steps / wall
+    lat = s.latency_us()
+    avg_launch_s = kern_ms / 1e3 / max(launches, 1)
+    per_step_launches = max(launches // args.steps, 1)
+    out = {
+        "metric": METRIC, "value": value, "unit": "host-scores/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl["text"], "k": insts[0].k, "hosts": N, "instances": len(insts),
+                   "requests": sum(len(r) for r in reqs), "container_steps": steps,
+                   "form": wl["mode"], "method": wl["method"], "block": tuned},
+        "latency_us": dict(percentiles(lat), kind="service (first step start to decision), device clock"),
+    }
+    if wl["method"] == "topsis":
+        kname = "k_topsis_batched" if mode == dc.DC_MODE_BATCHED else "k_topsis_plain"
+        bytes_per_launch = BYTES_PER_HOST_SCORE * hs / per_step_launches
+        achieved = bytes_per_launch / avg_launch_s / 1e9
+        out["roofline"] = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                           "avg_launch_us": avg_launch_s * 1e6, "launches_per_step": per_step_launches,
+                           "bytes_per_launch": bytes_per_launch}
+        meth = oracle.method(kind=oracle.TOPSIS)
+    else:
+        # AHP: the pairwise passes dominate; 2*C*N^2 pair evaluations per
+        # container step, at PAIR_OPS VALU lane-instructions each
+        C = 5
+        pairs = 2.0 * C * N * N * steps
+        out["roofline"] = {"bound": "alu", "kernel": "k_ahp_colsum+k_ahp_rowsum", "unit": "pair-evals/s",
+                           "achieved": pairs * args.steps / (kern_ms / 1e3),
+                           "peak": VALU_LANE_OPS / AHP_PAIR_OPS,
+                           "frac": pairs * args.steps / (kern_ms / 1e3) / (VALU_LANE_OPS / AHP_PAIR_OPS),
+                           "traffic": None, "pair_ops": AHP_PAIR_OPS}
+        meth = oracle.method(kind=oracle.AHP, crit=(oracle.CRIT_CPU, oracle.CRIT_RAM, oracle.CRIT_UPLINK,
+                                                   oracle.CRIT_PATHBW, oracle.CRIT_HOPS), cost=[0, 0, 0, 0, 1])
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(insts, reqs, args.cpu_budget, meth)
+        out["cpu_baseline"]["vs_gpu"] = value / out["cpu_baseline"]["value"]
+    s.close()
+    return out
+
+
+# VALU instructions per Saaty pair evaluation in the AHP passes (counted in
+# the compiled inner loops of k_ahp_colsum / k_ahp_rowsum).
+AHP_PAIR_OPS = 28
+
+
+def replay(s, dc, reqs, arr, dep, serving, horizon_s):
+    """Replays a Poisson trace in real time: request t is submitted at
+    arr[t] (or as soon as admitted), departs at dep[t] if it was accepted.
+    Returns per-request (status, steps, sojourn seconds) and the wall time."""
+    import heapq
+    n = len(reqs)
+    ids = [None] * n
+    done = {}
+    arrival = {}
+    sojourn = {}
+    events = [(arr[t], 0, t) for t in range(n)]
+    heapq.heapify(events)
+    backlog = []            # arrivals waiting for admission (FCFS)
+    t0 = time.perf_counter()
+    id2t = {}
+
+    def absorb(results):
+        now = time.perf_counter() - t0
+        for r in results:
+            t = id2t[r.req_id]
+            done[t] = r
+            sojourn[t] = now - arr[t]
+            if r.status == 1 and dep[t] < horizon_s:
+                heapq.heappush(events, (dep[t], 1, t))
+
+    while events or backlog or len(done) < n:
+        now = time.perf_counter() - t0
+        while events and events[0][0] <= now:
+            when, kind, t = heapq.heappop(events)
+            if kind == 0:
+                backlog.append(t)
+            elif s.release(ids[t]) not in (dc.DC_OK,):
+                heapq.heappush(events, (now + 1e-4, 1, t))
+        while backlog:
+            t = backlog[0]
+            rid = s.try_submit(reqs[t]) if serving else s.submit(reqs[t])
+            if rid is None:
+                break
+            ids[t] = rid
+            id2t[rid] = t
+            backlog.pop(0)
+            if not serving:
+                absorb(s.schedule())
+        if serving:
+            absorb(s.schedule())
+        if not events and not backlog and len(done) == n:
+            break
+        if serving and not backlog and (not events or events[0][0] > now + 2e-4):
+            time.sleep(5e-5)
+    wall = time.perf_counter() - t0
+    return done, sojourn, wall
+
+
+def run_serving(args, wl):
+    import numpy as np
+    import torch
+    import paper_1909_07673_amd as dc
+    from workloads import make_config, make_trace
+
+    torch.cuda.set_device(0)
+    insts, _ = make_config("serving", seed=0, n_req=1)
+    N = insts[0].n_hosts
+    reqs, arr, dep = make_trace(seed=0, duration_s=args.trace_s)
+    forms = {}
+    for name, mode in (("serving", dc.DC_MODE_SERVING), ("plain", dc.DC_MODE_PLAIN)):
+        s = dc.Scheduler(insts, mode=mode)
+        done, soj, wall = replay(s, dc, reqs, arr, dep, mode == dc.DC_MODE_SERVING, args.trace_s)
+        if mode == dc.DC_MODE_SERVING:
+            s.drain()
+        steps = step_count(done.values())
+        lat = s.latency_us()
+        forms[name] = {
+            "host_scores_per_s": steps * N / wall, "wall_s": wall, "container_steps": steps,
+            "accepted": int(sum(r.status for r in done.values())), "requests": len(reqs),
+            "achieved_req_per_s": len(reqs) / wall, "offered_req_per_s": len(reqs) / args.trace_s,
+            "service_us": percentiles(lat), "sojourn_ms": percentiles(np.array(list(soj.values())) * 1e3),
+        }
+        s.close()
+    sv = forms["serving"]
+    return {
+        "metric": METRIC, "value": sv["host_scores_per_s"], "unit": "host-scores/s", "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": sv["wall_s"] * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl["text"], "k": 48, "hosts": N, "trace_s": args.trace_s,
+                   "requests": len(reqs), "form": "serving", "method": "topsis"},
+        "latency_us": dict(sv["service_us"], kind="service (admission to decision), device clock"),
+        "forms": forms,
+    }
 
 
 def main():
@@ -76,82 +264,14 @@ def main():
     ap.add_argument("--workload", default="plain", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--trace-s", type=float, default=2.0, help="serving: seconds of Poisson arrivals")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
               "a data center's container steps are sequential and are not sharded across GPUs", file=sys.stderr)
         sys.exit(2)
-
-    import numpy as np
-    import torch
-    import paper_1909_07673_amd as dc
-    from workloads import make_config
-
     wl = WORKLOADS[args.workload]
-    torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
-    insts, reqs = make_config(wl["preset"], seed=0)
-    N = insts[0].n_hosts
-    mode = dc.DC_MODE_BATCHED if wl["mode"] == "batched" else dc.DC_MODE_PLAIN
-    s = dc.Scheduler(insts, mode=mode, stream=stream)
-    for i, rl in enumerate(reqs):
-        for r in rl:
-            s.submit(r, instance=i)
-    s.rewind()                      # uploads the requests; they stay resident in HBM
-    tuned = s.autotune()            # workgroup size picked by timing the candidates
-    torch.cuda.synchronize()
-
-    for _ in range(args.warmup):
-        s.rewind()
-        s.schedule()
-    torch.cuda.synchronize()
-    kern_ms = 0.0
-    launches = 0
-    results = None
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        s.rewind()
-        results = s.schedule()
-        ms, la, _ = s.last_timing()
-        kern_ms += ms
-        launches += la
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-
-    steps, hs = host_scores(results, N)
-    value = hs * args.steps / wall
-    lat = s.latency_us()
-    avg_launch_s = kern_ms / 1e3 / max(launches, 1)
-    bytes_per_launch = BYTES_PER_HOST_SCORE * hs / max(launches // args.steps, 1)
-    achieved = bytes_per_launch / avg_launch_s / 1e9
-    kname = "k_topsis_batched" if mode == dc.DC_MODE_BATCHED else "k_topsis_plain"
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "host-scores/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": wl["text"], "k": insts[0].k, "hosts": N, "instances": len(insts),
-                   "requests": sum(len(r) for r in reqs), "container_steps": steps,
-                   "form": wl["mode"], "method": wl["method"], "block": tuned},
-        "latency_us": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "kind": "service (first step start to decision), device clock"},
-        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "avg_launch_us": avg_launch_s * 1e6, "launches_per_step": launches // args.steps,
-                     "bytes_per_launch": bytes_per_launch},
-    }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(insts, reqs, args.cpu_budget)
-        out["cpu_baseline"]["vs_gpu"] = value / out["cpu_baseline"]["value"]
-    s.close()
+    out = run_serving(args, wl) if wl["mode"] == "serving" else run_batch(args, wl)
     print(json.dumps(out), flush=True)
 
 

@@ -94,7 +94,10 @@ typedef struct dc_config {
     int32_t block;          /* threads per workgroup, 0 = automatic / autotuned     */
     int32_t trace_stride;   /* record the score vector of every trace_stride-th step (0 = off) */
     int32_t trace_cap;      /* at most this many recorded steps                     */
-    int32_t reserved[5];
+    int32_t grid;           /* TOPSIS plain and serving forms: 0 = automatic (one
+                               cooperative workgroup per pod from k = 32 on),
+                               1 = one workgroup per step, 2 = one workgroup per pod */
+    int32_t reserved[4];
 } dc_config;
 
 typedef struct dc_result {

@@ -1,0 +1,534 @@
+// Cooperative container step for large data centers: one workgroup per pod
+// (k workgroups, launched cooperatively so that all are resident).  Each
+// workgroup builds the path tables for its own pod's aggregation and edge
+// switches, scores its pod's servers, and the column statistics and the
+// argmax are exchanged through global memory between three grid barriers;
+// workgroup 0 commits.  Same arithmetic as the single-workgroup step, so
+// results are bit-identical.  Used by the plain form (one cooperative launch
+// per container step) and the serving form (one persistent cooperative
+// kernel) when k is large.
+#pragma once
+#include "dc_serve.hpp"
+
+namespace dcs {
+
+// Cross-workgroup state, in device memory.
+struct GridCtl {
+    unsigned *count, *gen;        // grid barrier: arrivals, generation
+    int *err;                     // set when a barrier wait timed out
+    int *part;                    // [kStatFields][G] per-workgroup column statistics
+    int *cap;                     // [2][G*h]: summed residuals per edge switch, then [G] per pod
+    unsigned long long *keys;     // [G] per-workgroup best key
+    int *flag;                    // [kGridFlags]: commit result, trace slot, command buffers
+};
+
+// flag[0]: commit result of the current attempt; flag[7]: trace slot of the
+// step; flag[8 + 8 * (pos & 1) ...]: the command at ring position pos,
+// double-buffered so that the leader can publish command pos + 1 while a
+// slower workgroup still reads command pos.
+constexpr int kGridFlags = 24;
+enum { GF_GOT = 0, GF_TYPE, GF_N, GF_NPAIR, GF_SLOT, GF_RID };
+__device__ __forceinline__ int *cmd_flags(const GridCtl &g, int pos) { return g.flag + 8 + 8 * (pos & 1); }
+
+// Grid barrier over gridDim.x co-resident workgroups with agent-scope
+// release / acquire.  A wait longer than `timeout` device ticks sets *err;
+// every barrier returns false once *err is set, so all workgroups leave.
+__device__ __forceinline__ bool grid_sync(const GridCtl &g, int *lds_flag, long long timeout) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int bad = __hip_atomic_load(g.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!bad) {
+            __threadfence();
+            const unsigned gen = __hip_atomic_load(g.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned arrived = __hip_atomic_fetch_add(g.count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (arrived == gridDim.x - 1) {
+                __hip_atomic_store(g.count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(g.gen, gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                const long long t0 = dev_clock();
+                while (__hip_atomic_load(g.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                    if (__hip_atomic_load(g.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { bad = 1; break; }
+                    if (dev_clock() - t0 > timeout) {
+                        __hip_atomic_store(g.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        bad = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+            __threadfence();
+        }
+        *lds_flag = bad;
+    }
+    __syncthreads();
+    return !*lds_flag;
+}
+
+// LDS of the cooperative step (per workgroup): peers, own-pod tables and
+// capacities, per-server scratch of the pod, statistics slots.
+struct GSmem {
+    int4 *pk;                     // [kMaxN] packed peers (as in Smem)
+    int *wst;                     // [kStatFields][kMaxWaves]
+    int *misc;                    // [M_MISC]
+    int *capE;                    // [h] own edge switches
+    int *tabT, *tabE;             // [kMaxN][h]
+    int *xs;                      // [nc+6][hh]
+    int *pcap;                    // [2][kMaxN] peers' edge-switch and pod capacities
+};
+
+__host__ __device__ inline size_t gsmem_bytes(int h, int hh, int nc) {
+    return sizeof(int4) * kMaxN + sizeof(int) * (kStatFields * kMaxWaves + M_MISC + align4(h) +
+                                                 2 * align4((size_t)kMaxN * h) + (size_t)(nc + 6) * hh +
+                                                 2 * kMaxN);
+}
+
+__device__ inline GSmem gcarve(char *base, int h, int hh, int nc) {
+    GSmem s;
+    s.pk = reinterpret_cast<int4 *>(base);
+    int *p = reinterpret_cast<int *>(base + sizeof(int4) * kMaxN);
+    s.wst = p; p += kStatFields * kMaxWaves;
+    s.misc = p; p += M_MISC;
+    s.capE = p; p += align4(h);
+    s.tabT = p; p += align4((size_t)kMaxN * h);
+    s.tabE = p; p += align4((size_t)kMaxN * h);
+    s.xs = p; p += (size_t)(nc + 6) * hh;
+    s.pcap = p;
+    return s;
+}
+
+// Sum of v over the block; the result is valid in every thread after the
+// call (uses misc[M_MISC-1] and one LDS barrier pair).
+template <int BS>
+__device__ __forceinline__ int block_sum(int v, int *slot) {
+    v = wave_sum(v);
+    if (threadIdx.x == 0) *slot = 0;
+    __syncthreads();
+    if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(slot, v);
+    __syncthreads();
+    const int r = *slot;
+    __syncthreads();
+    return r;
+}
+
+// One container step on the pod of this workgroup (w = blockIdx.x).
+// rv.hosts_out, when given, is this workgroup's LDS copy of the request's
+// servers.  Returns false when the request was rejected at this container.
+template <int BS>
+__device__ bool grid_topsis_step(const Topo &t, const State &st, const Method &m, const Batch &b, const GSmem &sm,
+                                 const GridCtl &g, long long timeout, const StepIn &s, const ReqView &rv,
+                                 const Trace &tr) {
+    const int w = blockIdx.x, G = gridDim.x, h = t.h, hh = t.hh, nc = m.nc;
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const int P = s.P, ubase = w * hh;
+    int *xs = sm.xs;
+    if (w == 0 && threadIdx.x == 0) {
+        if (s.i == 0) b.tsb[s.r] = dev_clock();
+        g.flag[7] = tr.stride > 0 ? trace_slot(tr, 0, b.rid[s.r], s.i) : -1;
+    }
+    // ---- A: peers, own capacities
+    for (int p = threadIdx.x; p < P; p += BS) {
+        const int v = rv.hosts[rv.pj[p]];
+        sm.pk[p] = make_int4(v, fdiv(v, t.rh) | (fdiv(v, t.rhh) << 16), rv.pbw[p], st.up[v]);
+    }
+    for (int e = threadIdx.x; e < h; e += BS) {
+        int se = 0;
+        for (int a = 0; a < h; ++a) se += st.ea[(w * h + e) * h + a];
+        sm.capE[e] = se;
+    }
+    int cp = 0;
+    for (int x = threadIdx.x; x < hh; x += BS) cp += st.ac[w * hh + x];
+    const int capP_own = block_sum<BS>(cp, sm.misc + M_MISC - 1);   // ends with barriers
+    // ---- B: path tables for this pod (T: its aggregation switches, E: its edge switches)
+    for (int it = threadIdx.x; it < P * h; it += BS) {
+        const int pc = it / h, a = it - pc * h;
+        const int pv = sm.pk[pc].y >> 16;
+        int val = 0;
+        if (pv != w) {
+            const int *x = st.ac + (w * h + a) * h, *y = st.ac + (pv * h + a) * h;
+            for (int j = 0; j < h; ++j) val = max(val, min(x[j], y[j]));
+        }
+        sm.tabT[pc * h + a] = val;
+    }
+    __syncthreads();
+    for (int it = threadIdx.x; it < P * h; it += BS) {
+        const int pc = it / h, e = it - pc * h;
+        const int ed = sm.pk[pc].y, ev = ed & 0xffff, pv = ed >> 16, eg = w * h + e;
+        int val = 0;
+        if (eg != ev) {
+            const int *x = st.ea + eg * h, *y = st.ea + ev * h, *T = sm.tabT + pc * h;
+            const int lim = pv != w ? 0 : kBig;
+            for (int a = 0; a < h; ++a) val = max(val, min(min(x[a], y[a]), max(T[a], lim)));
+        }
+        sm.tabE[pc * h + e] = val;
+    }
+    __syncthreads();
+    // ---- C: criteria of the pod's servers, partial column statistics
+    unsigned long long s2[kMaxCrit];
+    int mx[kMaxCrit], mn[kMaxCrit];
+#pragma unroll
+    for (int c = 0; c < kMaxCrit; ++c) { s2[c] = 0; mx[c] = -kBig - 1; mn[c] = kBig; }
+    for (int x = threadIdx.x; x < hh; x += BS) {
+        const int u = ubase + x;
+        const int up_u = st.up[u], el = fdiv(x, t.rh), eu = w * h + el;
+        int pbw_acc = up_u, up_acc = 0, hop_acc = 0, oute = 0, outp = 0;
+        int feas = (st.cpu[u] >= s.cpu) & (st.ram[u] >= s.ram);
+        for (int pc = 0; pc < P; ++pc) {
+            const int4 pk = sm.pk[pc];
+            const int v = pk.x, bw = pk.z, ev = pk.y & 0xffff, pv = pk.y >> 16;
+            const bool rem = v != u, far = ev != eu;
+            int wv = min(up_u, pk.w);
+            wv = far ? min(wv, sm.tabE[pc * h + el]) : wv;
+            pbw_acc = rem ? min(pbw_acc, wv) : pbw_acc;
+            up_acc += rem ? bw : 0;
+            hop_acc += !rem ? 0 : !far ? 2 : (pv == w ? 4 : 6);
+            feas &= (!rem) | (wv >= bw);
+            oute += (rem & far) ? bw : 0;
+            outp += (rem & far & (pv != w)) ? bw : 0;
+        }
+        feas &= (up_u >= up_acc);
+        if (P > 0) feas &= (sm.capE[el] >= oute) & (capP_own >= outp);
+        xs[nc * hh + x] = feas;
+#pragma unroll
+        for (int c = 0; c < kMaxCrit; ++c) {
+            if (c >= nc) break;
+            int v;
+            switch (m.crit[c]) {
+            case CRIT_CPU: v = st.cpu[u]; break;
+            case CRIT_RAM: v = st.ram[u]; break;
+            case CRIT_ACTIVE: v = st.npl[u] > 0 ? 1 : 0; break;
+            case CRIT_PATHBW: v = pbw_acc; break;
+            case CRIT_UPLINK: v = up_u; break;
+            default: v = hop_acc; break;
+            }
+            xs[c * hh + x] = v;
+            s2[c] += static_cast<unsigned long long>(static_cast<long long>(v) * v);
+            mx[c] = max(mx[c], v);
+            mn[c] = min(mn[c], v);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxCrit; ++c) {
+        if (c >= nc) break;
+        const int c0 = wave_sum(static_cast<int>(s2[c] & 0x1ffffu));
+        const int c1 = wave_sum(static_cast<int>((s2[c] >> 17) & 0x1ffffu));
+        const int c2 = wave_sum(static_cast<int>(s2[c] >> 34));
+        const int hi = wave_max(mx[c]), lo = wave_min(mn[c]);
+        if (lane < 5) sm.wst[(5 * c + lane) * kMaxWaves + wid] =
+            lane == 0 ? c0 : lane == 1 ? c1 : lane == 2 ? c2 : lane == 3 ? hi : -lo;
+    }
+    __syncthreads();
+    // workgroup partials to global; own capacities for the other pods' checks
+    for (int f = threadIdx.x; f < 5 * nc; f += BS) {
+        int v = (f % 5) < 3 ? 0 : -kBig - 1;
+        for (int x = 0; x < BS / kWave; ++x) {
+            const int pv = sm.wst[f * kMaxWaves + x];
+            v = (f % 5) < 3 ? v + pv : max(v, pv);
+        }
+        g.part[f * G + w] = v;
+    }
+    for (int e = threadIdx.x; e < h; e += BS) g.cap[w * h + e] = sm.capE[e];
+    if (threadIdx.x == 0) g.cap[G * h + w] = capP_own;
+    if (!grid_sync(g, sm.misc + M_OK, timeout)) return false;                  // barrier 1
+    // ---- D: block totals, peer-side deficits, scores, workgroup best
+    unsigned long long S2[kMaxCrit];
+    int MX[kMaxCrit], MN[kMaxCrit];
+#pragma unroll
+    for (int c = 0; c < kMaxCrit; ++c) {
+        S2[c] = 0;
+        MX[c] = MN[c] = 0;
+        if (c >= nc) continue;
+        int a0 = 0, a1 = 0, a2 = 0, hi = -kBig - 1, nlo = -kBig - 1;
+        for (int x = lane; x < G; x += kWave) {
+            a0 += g.part[(5 * c) * G + x];
+            a1 += g.part[(5 * c + 1) * G + x];
+            a2 += g.part[(5 * c + 2) * G + x];
+            hi = max(hi, g.part[(5 * c + 3) * G + x]);
+            nlo = max(nlo, g.part[(5 * c + 4) * G + x]);
+        }
+        a0 = wave_sum(a0);
+        a1 = wave_sum(a1);
+        a2 = wave_sum(a2);
+        S2[c] = static_cast<unsigned long long>(static_cast<unsigned>(a0)) +
+                (static_cast<unsigned long long>(static_cast<unsigned>(a1)) << 17) +
+                (static_cast<unsigned long long>(static_cast<unsigned>(a2)) << 34);
+        MX[c] = wave_max(hi);
+        MN[c] = -wave_max(nlo);
+    }
+    // peer-side deficits (server uplink, edge switch, pod) as in the
+    // single-workgroup step; they only narrow the candidates
+    if (threadIdx.x < 6) sm.misc[M_DH0 + threadIdx.x] = (threadIdx.x & 1) ? -1 : kBig;
+    __syncthreads();
+    for (int p = threadIdx.x; p < P; p += BS) {
+        const int4 me = sm.pk[p];
+        const int v = me.x, e = me.y & 0xffff, d = me.y >> 16;
+        int sh = 0, se = 0, sp = 0;
+        for (int q = 0; q < P; ++q) {
+            const int4 o = sm.pk[q];
+            sh += o.x == v ? o.z : 0;
+            se += (o.y & 0xffff) == e ? o.z : 0;
+            sp += (o.y >> 16) == d ? o.z : 0;
+        }
+        if (me.w < sh) { atomicMin(sm.misc + M_DH0, v); atomicMax(sm.misc + M_DH1, v); }
+        if (g.cap[e] < se) { atomicMin(sm.misc + M_DE0, e); atomicMax(sm.misc + M_DE1, e); }
+        if (g.cap[G * h + d] < sp) { atomicMin(sm.misc + M_DP0, d); atomicMax(sm.misc + M_DP1, d); }
+    }
+    __syncthreads();
+    const int dh0 = sm.misc[M_DH0], dh1 = sm.misc[M_DH1], de0 = sm.misc[M_DE0], de1 = sm.misc[M_DE1];
+    const int dp0 = sm.misc[M_DP0], dp1 = sm.misc[M_DP1];
+    float q[kMaxCrit], ap[kMaxCrit], am[kMaxCrit];
+#pragma unroll
+    for (int c = 0; c < kMaxCrit; ++c) {
+        q[c] = ap[c] = am[c] = 0.f;
+        if (c >= nc) continue;
+        q[c] = S2[c] ? (m.w[c] * m.w[c]) / static_cast<float>(S2[c]) : 0.0f;
+        ap[c] = static_cast<float>(m.cost[c] ? MN[c] : MX[c]);
+        am[c] = static_cast<float>(m.cost[c] ? MX[c] : MN[c]);
+    }
+    auto key_of = [&](int x) -> unsigned long long {
+        const int u = ubase + x;
+        int f = xs[nc * hh + x];
+        f &= (dh1 < 0) | ((dh0 == dh1) & (u == dh0));
+        f &= (de1 < 0) | ((de0 == de1) & (w * h + fdiv(x, t.rh) == de0));
+        f &= (dp1 < 0) | ((dp0 == dp1) & (w == dp0));
+        if (!f) return 0ull;
+        float dp2 = 0.f, dm2 = 0.f;
+#pragma unroll
+        for (int c = 0; c < kMaxCrit; ++c) {
+            if (c >= nc) break;
+            const float v = static_cast<float>(xs[c * hh + x]);
+            const float a = v - ap[c], z = v - am[c];
+            dp2 = fmaf(q[c] * a, a, dp2);
+            dm2 = fmaf(q[c] * z, z, dm2);
+        }
+        const float dpv = sqrtf(dp2), dmv = sqrtf(dm2), den = dpv + dmv;
+        return score_key(den > 0.f ? dmv / den : 0.f, u);
+    };
+    auto wg_best = [&]() {
+        unsigned long long kb = 0;
+        for (int x = threadIdx.x; x < hh; x += BS) {
+            const unsigned long long k = key_of(x);
+            kb = k > kb ? k : kb;
+        }
+        unsigned hiw = wave_umax(static_cast<unsigned>(kb >> 32));
+        unsigned low = wave_umax(static_cast<unsigned>(kb >> 32) == hiw ? static_cast<unsigned>(kb) : 0u);
+        if (lane == 0) {
+            sm.wst[wid] = static_cast<int>(hiw);
+            sm.wst[kMaxWaves + wid] = static_cast<int>(low);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long best = 0;
+            for (int x = 0; x < BS / kWave; ++x) {
+                const unsigned long long k = (static_cast<unsigned long long>(static_cast<unsigned>(sm.wst[x])) << 32) |
+                                             static_cast<unsigned>(sm.wst[kMaxWaves + x]);
+                best = k > best ? k : best;
+            }
+            g.keys[w] = best;
+        }
+    };
+    const int slot = g.flag[7];
+    if (slot >= 0)
+        for (int x = threadIdx.x; x < hh; x += BS) {
+            float dp2 = 0.f, dm2 = 0.f;
+#pragma unroll
+            for (int c = 0; c < kMaxCrit; ++c) {
+                if (c >= nc) break;
+                const float v = static_cast<float>(xs[c * hh + x]);
+                const float a = v - ap[c], z = v - am[c];
+                dp2 = fmaf(q[c] * a, a, dp2);
+                dm2 = fmaf(q[c] * z, z, dm2);
+            }
+            const float dpv = sqrtf(dp2), dmv = sqrtf(dm2), den = dpv + dmv;
+            tr.scores[static_cast<size_t>(slot) * t.N + ubase + x] = den > 0.f ? dmv / den : 0.f;
+        }
+    wg_best();
+    // ---- E: global argmax, commit by workgroup 0, retries
+    for (;;) {
+        if (!grid_sync(g, sm.misc + M_OK, timeout)) return false;             // barrier 2
+        unsigned long long kb = 0;
+        for (int x = lane; x < G; x += kWave) {
+            const unsigned long long k = g.keys[x];
+            kb = k > kb ? k : kb;
+        }
+        {
+            const unsigned hiw = wave_umax(static_cast<unsigned>(kb >> 32));
+            const unsigned low = wave_umax(static_cast<unsigned>(kb >> 32) == hiw ? static_cast<unsigned>(kb) : 0u);
+            kb = (static_cast<unsigned long long>(hiw) << 32) | low;
+        }
+        if (kb == 0) {                                                        // no server left
+            if (w == 0) rollback_request<BS>(t, st, b, s.r, s.i);
+            grid_sync(g, sm.misc + M_OK, timeout);
+            return false;
+        }
+        const int u = static_cast<int>(~static_cast<unsigned>(kb & 0xffffffffu));
+        if (w == 0 && threadIdx.x < kWave) {
+            // commit_wave reads the peer servers from LDS; its routing uses
+            // the global state
+            Smem cs;
+            cs.pk = sm.pk;
+            const bool ok = commit_wave(t, st, u, s.cpu, s.ram, P, cs, b.code + s.p0, lane);
+            if (lane == 0) {
+                __hip_atomic_store(g.flag, ok ? 1 : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (ok) {
+                    b.host[s.g] = u;
+                    b.score[s.g] = __uint_as_float(static_cast<unsigned>(kb >> 32) - 1u);
+                    if (s.i == s.n - 1) b.tse[s.r] = dev_clock();
+                }
+            }
+        }
+        if (!grid_sync(g, sm.misc + M_OK, timeout)) return false;             // barrier 3
+        const int ok = __hip_atomic_load(g.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (ok) {
+            if (rv.hosts_out && threadIdx.x == 0) rv.hosts_out[s.i] = u;
+            __syncthreads();
+            return true;
+        }
+        if (u / hh == w) {                                                    // owner masks it and rescans
+            if (threadIdx.x == 0) xs[nc * hh + (u - ubase)] = 0;
+            __syncthreads();
+            wg_best();
+        }
+    }
+}
+
+}  // namespace dcs
+
+namespace dcs {
+
+// LDS of the request prefetch after the cooperative step's region.
+__device__ __forceinline__ int *grid_req_lds(char *dsm, int h, int hh, int nc) {
+    return reinterpret_cast<int *>(dsm + align4(gsmem_bytes(h, hh, nc) / sizeof(int)) * sizeof(int));
+}
+
+// Plain form, large data centers: one cooperative launch per container step.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_topsis_grid(Params p, GridCtl g, long long timeout) {
+    extern __shared__ __align__(16) char dsm[];
+    if (p.b.status[p.s.r] == 0) return;        // every workgroup leaves: no barrier is reached
+    const GSmem sm = gcarve(dsm, p.t.h, p.t.hh, p.m.nc);
+    grid_topsis_step<BS>(p.t, p.st, p.m, p.b, sm, g, timeout, p.s, plain_view(p), p.tr);
+}
+
+// Serving form, large data centers: the persistent loop of k_serve run by
+// one cooperative workgroup per pod.  Workgroup 0 polls the command ring
+// and publishes each command to the others through a grid barrier; every
+// workgroup keeps its own LDS copy of the request.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_serve_grid(Params p, ServeArgs a, GridCtl g, long long timeout) {
+    extern __shared__ __align__(16) char dsm[];
+    const GSmem sm = gcarve(dsm, p.t.h, p.t.hh, p.m.nc);
+    int *rq_host = grid_req_lds(dsm, p.t.h, p.t.hh, p.m.nc);
+    int *rq_cpu = rq_host + kMaxN, *rq_ram = rq_cpu + kMaxN, *rq_poff = rq_ram + kMaxN;
+    int *rq_pj = rq_poff + kMaxN + 4, *rq_pbw = rq_pj + kMaxPairs;
+    const bool lead = blockIdx.x == 0;
+    int pos = a.start;
+    long long idle0 = dev_clock();
+    for (;;) {
+        if (lead && threadIdx.x == 0) {
+            Cmd *c = a.cmds + (pos % a.cap);
+            int got = 0;
+            for (;;) {        // bounded wait: the workgroups leave after idle_ticks without work
+                if (__hip_atomic_load(&c->seq, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) == pos + 1) {
+                    got = 1;
+                    break;
+                }
+                if (dev_clock() - idle0 > a.idle_ticks) break;
+                __builtin_amdgcn_s_sleep(8);
+            }
+            int *cf = cmd_flags(g, pos);
+            int type = CMD_STOP;
+            if (got) {
+                type = __hip_atomic_load(&c->type, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                cf[GF_N] = __hip_atomic_load(&c->n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                cf[GF_NPAIR] = __hip_atomic_load(&c->npair, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                cf[GF_SLOT] = __hip_atomic_load(&c->slot_off, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                cf[GF_RID] = __hip_atomic_load(&c->rid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+            cf[GF_GOT] = got;
+            cf[GF_TYPE] = type;
+        }
+        if (!grid_sync(g, sm.misc + M_OK, a.idle_ticks + timeout)) break;      // command barrier
+        const int *cf = cmd_flags(g, pos);
+        const int got = cf[GF_GOT], type = cf[GF_TYPE], n = cf[GF_N], P = cf[GF_NPAIR], rid = cf[GF_RID];
+        int *sb = a.arena + cf[GF_SLOT];
+        if (type == CMD_STOP) {
+            if (got) ++pos;
+            break;
+        }
+        const SlotLayout L = slot_layout(n, P);
+        const Batch b = slot_batch(sb, L);
+        const long long t_admit = dev_clock();
+        bool fault = false;
+        if (type == CMD_SUBMIT) {
+            const int *stg = a.staging + (size_t)(pos % a.cap) * a.stage_ints;
+            if (lead)
+                for (int x = threadIdx.x; x < L.in_end; x += BS) sb[x] = stg[x];
+            for (int x = threadIdx.x; x <= n; x += BS) {
+                rq_poff[x] = stg[L.poff + x];
+                if (x < n) {
+                    rq_cpu[x] = stg[L.cpu + x];
+                    rq_ram[x] = stg[L.ram + x];
+                    rq_host[x] = -1;
+                    if (lead) {
+                        sb[L.host + x] = -1;
+                        sb[L.score + x] = 0;
+                    }
+                }
+            }
+            for (int x = threadIdx.x; x < P; x += BS) {
+                rq_pj[x] = stg[L.pj + x];
+                rq_pbw[x] = stg[L.pbw + x];
+                if (lead) sb[L.code + x] = -1;
+            }
+            if (lead && threadIdx.x == 0) {
+                sb[L.failat] = -1;
+                sb[L.status] = 1;
+            }
+            __syncthreads();
+            for (int i = 0; i < n; ++i) {
+                const int q0 = rq_poff[i];
+                const StepIn s{0, i, n, 0, i, q0, rq_poff[i + 1] - q0, rq_cpu[i], rq_ram[i]};
+                const ReqView rv{rq_pj + q0, rq_pbw + q0, rq_host, rq_host};
+                if (!grid_topsis_step<BS>(p.t, p.st, p.m, b, sm, g, timeout, s, rv, p.tr)) {
+                    fault = __hip_atomic_load(g.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+                    break;
+                }
+            }
+        } else if (lead) {
+            give_back<BS>(p.t, p.st, b, 0, n);       // departure of an accepted request
+        }
+        if (fault) break;
+        if (lead) {
+            __syncthreads();
+            Comp *cp = a.comps + (pos % a.cap);
+            if (type == CMD_SUBMIT)
+                for (int x = threadIdx.x; x < n; x += BS) {
+                    cp->host[x] = b.host[x];
+                    cp->score[x] = b.score[x];
+                }
+            if (threadIdx.x == 0) {
+                cp->type = type;
+                cp->rid = rid;
+                cp->n = n;
+                cp->status = type == CMD_SUBMIT ? b.status[0] : 1;
+                cp->failat = type == CMD_SUBMIT ? b.failat[0] : -1;
+                cp->t_admit = t_admit;
+                cp->t_decide = dev_clock();
+            }
+            __threadfence_system();
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                __hip_atomic_store(&cp->seq, pos + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_store(a.ctrl, pos + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+        }
+        ++pos;
+        idle0 = dev_clock();
+    }
+    if (lead && threadIdx.x == 0) {
+        __hip_atomic_store(a.ctrl, pos, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(a.ctrl + 1, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+}  // namespace dcs

@@ -4,7 +4,7 @@
 // batched (one persistent launch) forms, and collects results.
 #include "../../include/dcsched.h"
 #include "dc_kernels.hpp"
-#include "dc_serve.hpp"
+#include "dc_grid.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -135,6 +135,13 @@ struct dc_ctx {
     float last_ms = 0.f;
     int64_t last_launches = 0, last_steps = 0;
     std::unique_ptr<Serve> sv;     // serving form only
+    // cooperative (one workgroup per pod) TOPSIS step
+    bool use_grid = false;
+    GridCtl grid{};
+    int *d_grid = nullptr;         // backing allocation of grid
+    size_t lds_grid = 0;
+    long long grid_timeout = 10000000LL;   // 100 ms of device clock per barrier wait
+    hipError_t launch_err = hipSuccess;    // first failed cooperative launch of a run
 };
 
 #define HIPCHK(expr)                                       \
@@ -170,6 +177,7 @@ int check_config(const dc_config *c) {
     if (std::fabs(ws - 1.0) > 1e-5) return DC_EINVAL;
     if (c->block != 0 && c->block != 64 && c->block != 256 && c->block != 512 && c->block != 1024) return DC_EINVAL;
     if (c->trace_stride < 0 || c->trace_cap < 0) return DC_EINVAL;
+    if (c->grid < 0 || c->grid > 2) return DC_EINVAL;
     return DC_OK;
 }
 
@@ -331,6 +339,17 @@ int upload_pending(dc_ctx *ctx) {
 
 template <int BS>
 void launch_plain_step(dc_ctx *ctx, const Params &p) {
+    if (ctx->use_grid) {
+        Params pp = p;
+        GridCtl g = ctx->grid;
+        long long timeout = ctx->grid_timeout;
+        void *args[] = {&pp, &g, &timeout};
+        const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_topsis_grid<256>),
+                                                        dim3(ctx->t.k), dim3(256), args, ctx->lds_grid, ctx->stream);
+        if (e != hipSuccess && ctx->launch_err == hipSuccess) ctx->launch_err = e;
+        ctx->last_launches += 1;
+        return;
+    }
     if (ctx->m.method == DC_TOPSIS) {
         if (ctx->plain_res)
             hipLaunchKernelGGL((k_topsis_plain<BS, true>), dim3(1), dim3(BS), ctx->lds_plain, ctx->stream, p);
@@ -348,6 +367,7 @@ void launch_plain_step(dc_ctx *ctx, const Params &p) {
 }
 
 int run_plain(dc_ctx *ctx, DevBatch &b) {
+    ctx->launch_err = hipSuccess;
     for (int r = 0; r < b.R; ++r) {
         Params p = base_params(ctx, b, b.inst[r]);
         const int g0 = b.coff[r], n = b.coff[r + 1] - g0;
@@ -366,6 +386,7 @@ int run_plain(dc_ctx *ctx, DevBatch &b) {
             }
         }
         ctx->last_steps += n;
+        HIPCHK(ctx->launch_err);
     }
     HIPCHK(hipGetLastError());
     return DC_OK;
@@ -429,6 +450,47 @@ int collect(dc_ctx *ctx, DevBatch &b) {
     return DC_OK;
 }
 
+// ---------------------------------------------------------------- cooperative step
+int grid_init(dc_ctx *ctx) {
+    const int G = ctx->t.k, h = ctx->t.h;
+    // count, gen, err, pad, flag[kGridFlags], part[kStatFields][G], cap[G*h + G], keys[G] (8-byte aligned)
+    const size_t ints = 4 + kGridFlags + (size_t)kStatFields * G + (size_t)G * h + G + 2 + 2 * (size_t)G;
+    HIPCHK(hipMalloc(&ctx->d_grid, ints * sizeof(int)));
+    hipLaunchKernelGGL(k_fill_i32, dim3(16), dim3(256), 0, ctx->stream, ctx->d_grid, 0, (long long)ints);
+    HIPCHK(hipGetLastError());
+    int *p = ctx->d_grid;
+    GridCtl &g = ctx->grid;
+    g.count = reinterpret_cast<unsigned *>(p);
+    g.gen = reinterpret_cast<unsigned *>(p + 1);
+    g.err = p + 2;
+    g.flag = p + 4;
+    g.part = g.flag + kGridFlags;
+    g.cap = g.part + (size_t)kStatFields * G;
+    int *k = g.cap + (size_t)G * h + G;
+    k += (reinterpret_cast<uintptr_t>(k) & 7) ? 1 : 0;
+    g.keys = reinterpret_cast<unsigned long long *>(k);
+    ctx->lds_grid = gsmem_bytes(h, ctx->t.hh, ctx->m.nc);
+    const size_t serve_lds = align4(ctx->lds_grid / sizeof(int)) * sizeof(int) + req_lds_ints() * sizeof(int);
+    if (serve_lds > 159 * 1024) return DC_EINVAL;
+    if (set_lds(ctx, k_topsis_grid<256>, ctx->lds_grid) || set_lds(ctx, k_serve_grid<256>, serve_lds))
+        return DC_EDEVICE;
+    ctx->use_grid = true;
+    return DC_OK;
+}
+
+// A cooperative step that timed out at a barrier poisons the context.
+int grid_check(dc_ctx *ctx) {
+    if (!ctx->use_grid) return DC_OK;
+    int err = 0;
+    HIPCHK(hipMemcpy(&err, ctx->grid.err, sizeof(int), hipMemcpyDeviceToHost));
+    if (err) {
+        ctx->poisoned = true;
+        std::fprintf(stderr, "libdcsched: a cooperative step timed out at a grid barrier\n");
+        return DC_EDEVICE;
+    }
+    return DC_OK;
+}
+
 // ---------------------------------------------------------------- serving form
 int serve_init(dc_ctx *ctx) {
     auto sv = std::make_unique<Serve>();
@@ -476,8 +538,18 @@ int serve_ensure_running(dc_ctx *ctx) {
     p.pc_cap = sv.pc;
     ServeArgs a{sv.cmds, sv.comps, sv.ctrl, sv.staging, sv.arena, sv.cap, sv.stage_ints, dev_pos, 0, sv.idle_ticks};
     __atomic_store_n(sv.ctrl + 1, 0, __ATOMIC_RELEASE);
-    if (sv.bs == 256) hipLaunchKernelGGL((k_serve<256>), dim3(1), dim3(256), sv.lds, ctx->stream, p, a);
-    else hipLaunchKernelGGL((k_serve<512>), dim3(1), dim3(512), sv.lds, ctx->stream, p, a);
+    if (ctx->use_grid) {
+        GridCtl g = ctx->grid;
+        long long timeout = ctx->grid_timeout;
+        void *args[] = {&p, &a, &g, &timeout};
+        const size_t lds = align4(ctx->lds_grid / sizeof(int)) * sizeof(int) + req_lds_ints() * sizeof(int);
+        HIPCHK(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_serve_grid<256>), dim3(ctx->t.k),
+                                          dim3(256), args, lds, ctx->stream));
+    } else if (sv.bs == 256) {
+        hipLaunchKernelGGL((k_serve<256>), dim3(1), dim3(256), sv.lds, ctx->stream, p, a);
+    } else {
+        hipLaunchKernelGGL((k_serve<512>), dim3(1), dim3(512), sv.lds, ctx->stream, p, a);
+    }
     HIPCHK(hipGetLastError());
     sv.launched = true;
     return DC_OK;
@@ -497,6 +569,10 @@ void serve_publish(Serve &sv, int type, int n, int P, size_t off, int rid) {
 
 int serve_poll(dc_ctx *ctx) {
     Serve &sv = *ctx->sv;
+    if (ctx->use_grid && sv.launched && hipStreamQuery(ctx->stream) == hipSuccess) {
+        int rc = grid_check(ctx);
+        if (rc) return rc;
+    }
     while (sv.comp_pos < sv.host_pos) {
         Comp &c = sv.comps[sv.comp_pos % sv.cap];
         if (__atomic_load_n(&c.seq, __ATOMIC_ACQUIRE) != (int)(sv.comp_pos + 1)) break;
@@ -752,6 +828,11 @@ int dc_create(const dc_config *cfg, dc_ctx **out) {
         }
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, c->stream, c->d_tcount, 0, (long long)I);
     }
+    const bool grid_ok = cfg->method == DC_TOPSIS && cfg->mode != DC_MODE_BATCHED && I == 1;
+    if (grid_ok && (cfg->grid == 2 || (cfg->grid == 0 && k >= 32))) {
+        const int grc = grid_init(c);
+        if (grc) { dc_destroy(ctx.release()); return grc; }
+    }
     if (cfg->mode == DC_MODE_SERVING) {
         if (I != 1) { dc_destroy(ctx.release()); return DC_EINVAL; }
         const int src = serve_init(c);
@@ -809,10 +890,13 @@ int dc_schedule(dc_ctx *ctx, int32_t max_results, dc_result *out, int32_t *n_out
             if (rc) return rc;
         }
         HIPCHK(hipEventRecord(ctx->ev1, ctx->stream));
+        HIPCHK(hipGetLastError());
         for (int bi : ctx->queued) {
             rc = collect(ctx, *ctx->batches[bi]);
             if (rc) return rc;
         }
+        rc = grid_check(ctx);
+        if (rc) return rc;
         HIPCHK(hipEventElapsedTime(&ctx->last_ms, ctx->ev0, ctx->ev1));
         ctx->queued.clear();
     }
@@ -1062,7 +1146,7 @@ void dc_destroy(dc_ctx *ctx) {
     if (!ctx->poisoned && ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     for (auto &b : ctx->batches)
         if (b->dmem) (void)hipFree(b->dmem);
-    int *ptrs[] = {ctx->d_state, ctx->d_init, ctx->d_xs, ctx->d_colpart, ctx->d_tmeta, ctx->d_tcount};
+    int *ptrs[] = {ctx->d_state, ctx->d_init, ctx->d_xs, ctx->d_colpart, ctx->d_tmeta, ctx->d_tcount, ctx->d_grid};
     for (int *p : ptrs)
         if (p) (void)hipFree(p);
     if (ctx->d_rowpart) (void)hipFree(ctx->d_rowpart);

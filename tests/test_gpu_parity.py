@@ -239,3 +239,45 @@ def test_invalid_arguments():
         assert e.value.code == dc.DC_EINVAL
     with pytest.raises(dc.DcError):
         s.submit(bad[0], instance=3)
+
+
+# ---------------------------------------------------------------- cooperative step
+@pytest.mark.parametrize("seed", range(12))
+def test_grid_tiny_lockstep(seed):
+    """One cooperative workgroup per pod (k=4: four workgroups), forced on
+    the small case: every step's score vector against the oracle."""
+    insts, reqs = make_config("tiny", seed=seed)
+    s = dc.Scheduler(insts, grid=2, trace_stride=1, trace_cap=4096)
+    o = O.Oracle(insts[0], _omethod(O.TOPSIS))
+    for req in reqs[0]:
+        rid = s.submit(req)
+        res = {r.req_id: r for r in s.schedule()}
+        st = lockstep(o, s, [rid], [req], res, trace=trace_by_request(s), check_paths=True)
+        assert st["scored_steps"] == st["steps"]
+    s.close()
+
+
+def test_grid_k16_matches_single_workgroup():
+    """k=16 with one workgroup per pod: bit-identical to the single-workgroup
+    step, and in lockstep with the oracle on every step's scores."""
+    insts, reqs = make_config("plain", seed=3, n_req=200)
+    g, gids, gres = _run(insts, reqs, grid=2, trace_stride=1, trace_cap=8192)
+    p, pids, pres = _run(insts, reqs, grid=1)
+    for a, b in zip(gids[0], pids[0]):
+        assert gres[a].status == pres[b].status
+        np.testing.assert_array_equal(gres[a].hosts, pres[b].hosts)
+        np.testing.assert_array_equal(gres[a].scores.view(np.uint32), pres[b].scores.view(np.uint32))
+    np.testing.assert_array_equal(g.state(0), p.state(0))
+    o = O.Oracle(insts[0], _omethod(O.TOPSIS))
+    st = lockstep(o, g, gids[0], reqs[0], gres, trace=trace_by_request(g), check_paths=True)
+    assert st["scored_steps"] == st["steps"]
+
+
+def test_grid_k48_sampled():
+    """k=48 (27,648 hosts, 48 cooperative workgroups, the default there): a
+    prefix in lockstep, score vectors on sampled steps."""
+    insts, reqs = make_config("serving", seed=1, n_req=6)
+    s, ids, res = _run(insts, reqs, trace_stride=7, trace_cap=64)
+    o = O.Oracle(insts[0], _omethod(O.TOPSIS))
+    st = lockstep(o, s, ids[0], reqs[0], res, trace=trace_by_request(s), check_paths=True)
+    assert st["scored_steps"] >= 1

@@ -59,12 +59,13 @@ def _k16():
     return insts, reqs[0]
 
 
-def test_serving_alone_equals_mix_and_oracle():
+@pytest.mark.parametrize("grid", [1, 2])
+def test_serving_alone_equals_mix_and_oracle(grid):
     insts, reqs = _k16()
     cmds = _commands(reqs)
-    mix = dc.Scheduler(insts, mode=dc.DC_MODE_SERVING)
+    mix = dc.Scheduler(insts, mode=dc.DC_MODE_SERVING, grid=grid)
     ids_m, res_m = _replay(mix, reqs, cmds, alone=False)
-    alone = dc.Scheduler(insts, mode=dc.DC_MODE_SERVING)
+    alone = dc.Scheduler(insts, mode=dc.DC_MODE_SERVING, grid=3 - grid)
     ids_a, res_a = _replay(alone, reqs, cmds, alone=True)
     for t in range(len(reqs)):
         a, b = res_m[ids_m[t]], res_a[ids_a[t]]
