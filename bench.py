@@ -54,6 +54,12 @@ def step_count(results):
     return sum(r.n if r.status == 1 else r.failed_at + 1 for r in results)
 
 
+def step_count_array(res):
+    """Container steps in a RESULT_DTYPE record array."""
+    import numpy as np
+    return int(np.where(res["status"] == 1, res["n"], res["failed_at"] + 1).sum())
+
+
 def cpu_baseline(insts, reqs, budget_s, meth):
     """The FP64 oracle, as it stands, on a bounded prefix of the same
     workload (single thread)."""
@@ -97,28 +103,30 @@ def run_batch(args, wl):
         kw = dict(method=dc.DC_AHP, crit=(dc.DC_CRIT_CPU, dc.DC_CRIT_RAM, dc.DC_CRIT_UPLINK, dc.DC_CRIT_PATHBW,
                                           dc.DC_CRIT_HOPS), cost=(0, 0, 0, 0, 1))
     mode = dc.DC_MODE_BATCHED if wl["mode"] == "batched" else dc.DC_MODE_PLAIN
-    s = dc.Scheduler(insts, mode=mode, stream=stream, **kw)
+    s = dc.Scheduler(insts, mode=mode, stream=stream, grid=args.grid, graph=args.graph, **kw)
     for i, rl in enumerate(reqs):
         for r in rl:
             s.submit(r, instance=i)
     s.rewind()                      # uploads the requests; they stay resident in HBM
     tuned = s.autotune() if wl["method"] == "topsis" else None
     torch.cuda.synchronize()
+    buf = np.zeros(s.pending(), dc.RESULT_DTYPE)
     for _ in range(args.warmup):
         s.rewind()
-        s.schedule()
+        s.schedule_array(buf)
     torch.cuda.synchronize()
     kern_ms, launches, results = 0.0, 0, None
     t0 = time.perf_counter()
     for _ in range(args.steps):
         s.rewind()
-        results = s.schedule()
+        results = s.schedule_array(buf)
         ms, la, _ = s.last_timing()
         kern_ms += ms
         launches += la
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    steps = step_count(results)
+    assert len(results) == len(buf), "every queued request is decided in a step"
+    steps = step_count_array(results)
     hs = steps * N
     value = hs * args.steps / wall
     lat = s.latency_us()
@@ -130,11 +138,13 @@ def run_batch(args, wl):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": wl["text"], "k": insts[0].k, "hosts": N, "instances": len(insts),
                    "requests": sum(len(r) for r in reqs), "container_steps": steps,
-                   "form": wl["mode"], "method": wl["method"], "block": tuned},
+                   "form": wl["mode"], "method": wl["method"], "block": tuned, "grid": args.grid,
+                   "graph": args.graph},
         "latency_us": dict(percentiles(lat), kind="service (first step start to decision), device clock"),
     }
     if wl["method"] == "topsis":
-        kname = "k_topsis_batched" if mode == dc.DC_MODE_BATCHED else "k_topsis_plain"
+        kname = ("k_topsis_batched" if mode == dc.DC_MODE_BATCHED else
+                 "k_topsis_grid" if args.grid == 2 or (args.grid == 0 and insts[0].k >= 32) else "k_topsis_plain")
         bytes_per_launch = BYTES_PER_HOST_SCORE * hs / per_step_launches
         achieved = bytes_per_launch / avg_launch_s / 1e9
         out["roofline"] = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
@@ -230,8 +240,12 @@ def run_serving(args, wl):
     N = insts[0].n_hosts
     reqs, arr, dep = make_trace(seed=0, duration_s=args.trace_s)
     forms = {}
-    for name, mode in (("serving", dc.DC_MODE_SERVING), ("plain", dc.DC_MODE_PLAIN)):
-        s = dc.Scheduler(insts, mode=mode)
+    # grid 0: one cooperative workgroup per pod (the default at this size);
+    # grid 1: the single-workgroup step, for comparison
+    variants = (("serving", dc.DC_MODE_SERVING, 0), ("plain", dc.DC_MODE_PLAIN, 0),
+                ("serving_1wg", dc.DC_MODE_SERVING, 1), ("plain_1wg", dc.DC_MODE_PLAIN, 1))
+    for name, mode, grid in variants:
+        s = dc.Scheduler(insts, mode=mode, grid=grid)
         done, soj, wall = replay(s, dc, reqs, arr, dep, mode == dc.DC_MODE_SERVING, args.trace_s)
         if mode == dc.DC_MODE_SERVING:
             s.drain()
@@ -265,6 +279,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--trace-s", type=float, default=2.0, help="serving: seconds of Poisson arrivals")
+    ap.add_argument("--grid", type=int, default=0, choices=(0, 1, 2),
+                    help="TOPSIS step: 0 automatic, 1 one workgroup, 2 one cooperative workgroup per pod")
+    ap.add_argument("--graph", type=int, default=0, choices=(0, 1, 2),
+                    help="batched form: 0 automatic (graph), 1 direct launch, 2 HIP graph")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "

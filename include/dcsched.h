@@ -97,7 +97,10 @@ typedef struct dc_config {
     int32_t grid;           /* TOPSIS plain and serving forms: 0 = automatic (one
                                cooperative workgroup per pod from k = 32 on),
                                1 = one workgroup per step, 2 = one workgroup per pod */
-    int32_t reserved[4];
+    int32_t graph;          /* batched form: 0 = automatic (on), 1 = launch directly,
+                               2 = capture each queued batch's launch in a HIP graph
+                               once per workgroup size and replay it afterwards   */
+    int32_t reserved[3];
 } dc_config;
 
 typedef struct dc_result {

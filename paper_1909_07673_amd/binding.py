@@ -32,13 +32,21 @@ class dc_config(C.Structure):
                 ("weight", C.c_float * 8),
                 ("host_used", C.c_void_p), ("link_used", C.c_void_p), ("stream", C.c_void_p),
                 ("mem_budget", C.c_size_t), ("block", C.c_int32), ("trace_stride", C.c_int32),
-                ("trace_cap", C.c_int32), ("grid", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("trace_cap", C.c_int32), ("grid", C.c_int32), ("graph", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
 
 
 class dc_result(C.Structure):
     _fields_ = [("req_id", C.c_int64), ("instance", C.c_int32), ("status", C.c_int32),
                 ("n", C.c_int32), ("failed_at", C.c_int32),
                 ("host", C.c_int32 * DC_MAX_CONTAINERS), ("score", C.c_float * DC_MAX_CONTAINERS)]
+
+
+# dc_result as a NumPy record (same layout), for bulk result transfer.
+RESULT_DTYPE = np.dtype([("req_id", np.int64), ("instance", np.int32), ("status", np.int32),
+                         ("n", np.int32), ("failed_at", np.int32),
+                         ("host", np.int32, DC_MAX_CONTAINERS), ("score", np.float32, DC_MAX_CONTAINERS)], align=True)
+assert RESULT_DTYPE.itemsize == C.sizeof(dc_result)
 
 
 class DcError(RuntimeError):
@@ -124,7 +132,7 @@ class Scheduler:
                  crit: Iterable[int] = DEFAULT_CRIT, cost: Optional[Iterable[int]] = None,
                  weight: Optional[Iterable[float]] = None, ahp_scale: int = DC_AHP_SAATY9,
                  stream=None, block: int = 0, trace_stride: int = 0, trace_cap: int = 0,
-                 mem_budget: int = 0, grid: int = 0):
+                 mem_budget: int = 0, grid: int = 0, graph: int = 0):
         inst0 = instances[0]
         crit = list(crit)
         cost = list(cost) if cost is not None else [0] * len(crit)
@@ -150,6 +158,7 @@ class Scheduler:
         cfg.stream = h if h else None
         cfg.block, cfg.trace_stride, cfg.trace_cap, cfg.mem_budget = block, trace_stride, trace_cap, mem_budget
         cfg.grid = grid
+        cfg.graph = graph
         self.N, self.I, self.k = N, len(instances), inst0.k
         self.cfg = cfg
         self._ctx = C.c_void_p()
@@ -192,6 +201,17 @@ class Scheduler:
             remaining -= n.value
             if n.value < 4096 or remaining <= 0:
                 return out
+
+    def schedule_array(self, out: Optional[np.ndarray] = None) -> np.ndarray:
+        """dc_schedule into a record array of RESULT_DTYPE (no per-result
+        Python objects): returns the filled prefix of `out`, which is
+        allocated for every queued request when not given."""
+        if out is None:
+            out = np.zeros(max(self.pending(), 1), RESULT_DTYPE)
+        n = C.c_int32()
+        _check(lib().dc_schedule(self._ctx, len(out), out.ctypes.data_as(C.POINTER(dc_result)), C.byref(n)),
+               "dc_schedule")
+        return out[: n.value]
 
     def release(self, req_id: int) -> int:
         return lib().dc_release(self._ctx, req_id)

@@ -33,6 +33,11 @@ struct DevBatch {
     std::vector<int> host, code, status, failat;
     std::vector<float> score;
     std::vector<long long> tsb, tse;
+    hipGraphExec_t gexec = nullptr;    // batched form: captured launch of this batch
+    int gbs = 0;                       // workgroup size it was captured with
+    ~DevBatch() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+    }
 };
 
 struct ReqLoc {
@@ -142,6 +147,7 @@ struct dc_ctx {
     size_t lds_grid = 0;
     long long grid_timeout = 10000000LL;   // 100 ms of device clock per barrier wait
     hipError_t launch_err = hipSuccess;    // first failed cooperative launch of a run
+    hipStream_t cap_stream = nullptr;      // graph capture (batched form)
 };
 
 #define HIPCHK(expr)                                       \
@@ -178,6 +184,7 @@ int check_config(const dc_config *c) {
     if (c->block != 0 && c->block != 64 && c->block != 256 && c->block != 512 && c->block != 1024) return DC_EINVAL;
     if (c->trace_stride < 0 || c->trace_cap < 0) return DC_EINVAL;
     if (c->grid < 0 || c->grid > 2) return DC_EINVAL;
+    if (c->graph < 0 || c->graph > 2) return DC_EINVAL;
     return DC_OK;
 }
 
@@ -397,14 +404,48 @@ size_t batched_lds(const dc_ctx *ctx) {
                           6 * (size_t)ctx->N + req_lds_ints());
 }
 
-int run_batched(dc_ctx *ctx, DevBatch &b, int bs) {
+void launch_batched(dc_ctx *ctx, DevBatch &b, int bs, hipStream_t stream) {
     Params p = base_params(ctx, b, 0);
     p.pc_cap = ctx->pc_batched;
     const size_t lds = batched_lds(ctx);
     switch (bs) {
-    case 256: hipLaunchKernelGGL((k_topsis_batched<256>), dim3(ctx->I), dim3(256), lds, ctx->stream, p); break;
-    case 512: hipLaunchKernelGGL((k_topsis_batched<512>), dim3(ctx->I), dim3(512), lds, ctx->stream, p); break;
-    default: hipLaunchKernelGGL((k_topsis_batched<1024>), dim3(ctx->I), dim3(1024), lds, ctx->stream, p); break;
+    case 256: hipLaunchKernelGGL((k_topsis_batched<256>), dim3(ctx->I), dim3(256), lds, stream, p); break;
+    case 512: hipLaunchKernelGGL((k_topsis_batched<512>), dim3(ctx->I), dim3(512), lds, stream, p); break;
+    default: hipLaunchKernelGGL((k_topsis_batched<1024>), dim3(ctx->I), dim3(1024), lds, stream, p); break;
+    }
+}
+
+// Captures the batch's launch into a graph on a private stream (capture is
+// not allowed on the legacy default stream a caller may have handed in).
+int capture_batched(dc_ctx *ctx, DevBatch &b, int bs) {
+    if (b.gexec) {
+        HIPCHK(hipGraphExecDestroy(b.gexec));
+        b.gexec = nullptr;
+    }
+    if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    launch_batched(ctx, b, bs, ctx->cap_stream);
+    const hipError_t le = hipGetLastError();
+    const hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &g);
+    HIPCHK(le);
+    HIPCHK(ce);
+    const hipError_t ie = hipGraphInstantiate(&b.gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHK(ie);
+    b.gbs = bs;
+    return DC_OK;
+}
+
+int run_batched(dc_ctx *ctx, DevBatch &b, int bs) {
+    if (ctx->cfg.graph == 1) {
+        launch_batched(ctx, b, bs, ctx->stream);
+    } else {
+        if (!b.gexec || b.gbs != bs) {
+            const int rc = capture_batched(ctx, b, bs);
+            if (rc) return rc;
+        }
+        HIPCHK(hipGraphLaunch(b.gexec, ctx->stream));
     }
     HIPCHK(hipGetLastError());
     ctx->last_launches += 1;
@@ -1086,9 +1127,14 @@ int dc_autotune(dc_ctx *ctx, int32_t *block) {
             for (int bi : ctx->queued) if ((rc = reset_outputs(ctx, *ctx->batches[bi]))) return rc;
             HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
             ctx->plain_bs = bs;
-            for (int bi : ctx->queued)
-                if ((rc = batched ? run_batched(ctx, *ctx->batches[bi], bs) : run_plain(ctx, *ctx->batches[bi])))
+            for (int bi : ctx->queued) {
+                if (batched) {
+                    launch_batched(ctx, *ctx->batches[bi], bs, ctx->stream);   // timed eagerly
+                    HIPCHK(hipGetLastError());
+                } else if ((rc = run_plain(ctx, *ctx->batches[bi]))) {
                     return rc;
+                }
+            }
             HIPCHK(hipEventRecord(ctx->ev1, ctx->stream));
             HIPCHK(hipEventSynchronize(ctx->ev1));
             float ms = 0.f;
@@ -1154,6 +1200,7 @@ void dc_destroy(dc_ctx *ctx) {
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
 }
 
