@@ -43,6 +43,10 @@ WORKLOADS = {
     "ahp": dict(preset="ahp", mode="plain", method="ahp",
                 text="k=32 fat-tree (8192 hosts), 500 FCFS requests of 8-64 containers, 0-70% background, AHP "
                      "(Saaty 1-9) on CPU/RAM/uplink/path-bw/hops(cost), four launches per container step"),
+    "tiles": dict(preset=None, mode="tiles", method="topsis",
+                  text="TOPSIS scoring + selection alone (dc_topsis_tiles) over 32,768 materialised 4 x 1024 "
+                       "integer decision matrices (512 MiB, the batched shape: 256 instances x 128 steps), "
+                       "best server and score per matrix"),
     "serving": dict(preset="serving", mode="serving", method="topsis",
                     text="k=48 fat-tree (27648 hosts), 0-70% background, Poisson arrivals at 5000 req/s of 2-64 "
                          "containers, exponential lifetimes (mean 60 s) releasing their resources, TOPSIS, "
@@ -176,6 +180,69 @@ def run_batch(args, wl):
 AHP_PAIR_OPS = 28
 
 
+TILE_T, TILE_C, TILE_N = 32768, 4, 1024
+
+
+def run_tiles(args, wl):
+    """Kernel roofline of TOPSIS scoring: one launch scores every server of
+    every matrix and selects the best; the matrices are resident in HBM and
+    larger than the 256 MiB last-level cache, so each launch streams them."""
+    import numpy as np
+    import torch
+    import paper_1909_07673_amd as dc
+    from workloads import make_tiles
+
+    torch.cuda.set_device(0)
+    T, C, N = TILE_T, TILE_C, TILE_N
+    xh, _ = make_tiles(seed=2024, T=T, N=N, C=C)
+    x = torch.from_numpy(xh).cuda()
+    w = [1.0 / C] * C
+    stream = torch.cuda.current_stream()
+    for _ in range(max(args.warmup, 1)):
+        dc.topsis_tiles(x, w, stream=stream)
+    torch.cuda.synchronize()
+    if args.copy_ref:
+        # a plain device copy of the same bytes, for scaling HBM counters
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del y
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        best, bscore, _ = dc.topsis_tiles(x, w, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_s = e0.elapsed_time(e1) / 1e3 / args.steps
+    hs = T * N
+    bytes_per_launch = 4 * C * N * T + 8 * T          # criteria read once, best + score written
+    achieved = bytes_per_launch / launch_s / 1e9
+    out = {
+        "metric": METRIC, "value": hs * args.steps / wall, "unit": "host-scores/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl["text"], "matrices": T, "criteria": C, "hosts": N, "form": "tiles",
+                   "method": "topsis"},
+        "roofline": {"bound": "hbm", "kernel": "k_topsis_tiles_reg<4,1>", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_us": launch_s * 1e6, "bytes_per_launch": bytes_per_launch},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        t1 = time.perf_counter()
+        done = 0
+        while time.perf_counter() - t1 < args.cpu_budget and done < T:
+            oracle.topsis(xh[done].astype(np.float64), w)
+            done += 1
+        el = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": done * N / el, "unit": "host-scores/s", "cores": 1, "kind": "oracle",
+                               "sample": f"first {done} of the {T} matrices, FP64 oracle TOPSIS, one thread"}
+        out["cpu_baseline"]["vs_gpu"] = out["value"] / out["cpu_baseline"]["value"]
+    return out
+
+
 def replay(s, dc, reqs, arr, dep, serving, horizon_s):
     """Replays a Poisson trace in real time: request t is submitted at
     arr[t] (or as soon as admitted), departs at dep[t] if it was accepted.
@@ -281,6 +348,8 @@ def main():
     ap.add_argument("--trace-s", type=float, default=2.0, help="serving: seconds of Poisson arrivals")
     ap.add_argument("--grid", type=int, default=0, choices=(0, 1, 2),
                     help="TOPSIS step: 0 automatic, 1 one workgroup, 2 one cooperative workgroup per pod")
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="tiles: also run one plain copy of the matrices (reference for HBM byte counters)")
     ap.add_argument("--graph", type=int, default=0, choices=(0, 1, 2),
                     help="batched form: 0 automatic (graph), 1 direct launch, 2 HIP graph")
     args = ap.parse_args()
@@ -289,7 +358,12 @@ def main():
               "a data center's container steps are sequential and are not sharded across GPUs", file=sys.stderr)
         sys.exit(2)
     wl = WORKLOADS[args.workload]
-    out = run_serving(args, wl) if wl["mode"] == "serving" else run_batch(args, wl)
+    if wl["mode"] == "serving":
+        out = run_serving(args, wl)
+    elif wl["mode"] == "tiles":
+        out = run_tiles(args, wl)
+    else:
+        out = run_batch(args, wl)
     print(json.dumps(out), flush=True)
 
 

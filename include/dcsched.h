@@ -198,6 +198,31 @@ int dc_pending(dc_ctx *ctx, int64_t *n);
  * scheduling kernel launches it made. */
 int dc_last_timing(dc_ctx *ctx, float *ms, int64_t *launches, int64_t *steps);
 
+/* TOPSIS scoring and selection (section V-C) on its own, over T decision
+ * matrices already in device memory; needs no context.
+ *   x          device, [T][C][N] int32, criterion-major, 0 <= value < 2^22
+ *              (integer criteria as the container step builds them).
+ *   feasible   device, [T][N] uint8 (nonzero = feasible), or NULL (all).
+ *   cost       host, [C], 1 = smaller is better, or NULL (all benefit).
+ *   weight     host, [C], each > 0 and finite.
+ *   scores     device, [T][N] float closeness, or NULL (not written).
+ *   best       device, [T] int32: the feasible server of highest closeness,
+ *              lowest index on ties; -1 when no server is feasible.
+ *   best_score device, [T] float closeness of best (0 when -1), or NULL.
+ *   stream     hipStream_t to launch on, NULL = the default stream.
+ * Per tile: column L2 norms from exact integer sums of squares, ideal and
+ * anti-ideal as column maximum / minimum (swapped for a cost criterion),
+ * closeness d-/(d+ + d-) (0 when both distances are 0) in FP32 with the
+ * arithmetic of the container step, so its scores are identical to the
+ * step's for the same criteria.  Asynchronous on the stream; the caller
+ * keeps the buffers alive until it completes.  DC_EINVAL for T < 0 or
+ * T >= 2^31, C outside 1..DC_MAX_CRIT, N outside 1..2^20, a null x, best or
+ * weight, or a weight that is not positive; DC_EDEVICE when the launch
+ * fails.  16-byte aligned x and scores and N % 4 == 0 take the fast path. */
+int dc_topsis_tiles(int64_t T, int32_t C, int32_t N, const int32_t *x, const uint8_t *feasible,
+                    const int32_t *cost, const float *weight, float *scores, int32_t *best, float *best_score,
+                    void *stream);
+
 void dc_destroy(dc_ctx *ctx);
 const char *dc_strerror(int code);
 

@@ -81,6 +81,7 @@ def lib():
         L.dc_autotune.argtypes = [P, C.POINTER(C.c_int32)]
         L.dc_last_timing.argtypes = [P, C.POINTER(C.c_float), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.dc_pending.argtypes = [P, C.POINTER(C.c_int64)]
+        L.dc_topsis_tiles.argtypes = [C.c_int64, C.c_int32, C.c_int32, P, P, i32p, C.POINTER(C.c_float), P, P, P, P]
         L.dc_destroy.argtypes = [P]
         L.dc_destroy.restype = None
         L.dc_strerror.argtypes = [C.c_int]
@@ -293,3 +294,33 @@ class Scheduler:
         ms, la, st = C.c_float(), C.c_int64(), C.c_int64()
         _check(lib().dc_last_timing(self._ctx, C.byref(ms), C.byref(la), C.byref(st)), "dc_last_timing")
         return ms.value, la.value, st.value
+
+
+def topsis_tiles(x, weight, cost=None, feasible=None, scores: bool = False, stream=None):
+    """dc_topsis_tiles on device tensors: x int32 [T][C][N] (contiguous, on
+    the GPU), feasible uint8 [T][N] or None.  Returns (best int32 [T],
+    best_score float32 [T], scores float32 [T][N] or None), launched on
+    `stream` (default: torch's current stream of x's device)."""
+    import torch
+    if x.dtype != torch.int32 or x.dim() != 3 or not x.is_cuda:
+        raise ValueError("x must be an int32 [T][C][N] device tensor")
+    x = x.contiguous()
+    T, Cn, N = x.shape
+    dev = x.device
+    best = torch.empty(T, dtype=torch.int32, device=dev)
+    bscore = torch.empty(T, dtype=torch.float32, device=dev)
+    sc = torch.empty((T, N), dtype=torch.float32, device=dev) if scores else None
+    fp = None
+    if feasible is not None:
+        if feasible.dtype != torch.uint8 or tuple(feasible.shape) != (T, N) or feasible.device != dev:
+            raise ValueError("feasible must be a uint8 [T][N] tensor on x's device")
+        feasible = feasible.contiguous()
+        fp = feasible.data_ptr()
+    w = (C.c_float * Cn)(*[float(v) for v in weight])
+    cv = (C.c_int32 * Cn)(*[int(v) for v in (cost if cost is not None else [0] * Cn)])
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    _check(lib().dc_topsis_tiles(T, Cn, N, x.data_ptr(), fp, cv, w, sc.data_ptr() if sc is not None else None,
+                                 best.data_ptr(), bscore.data_ptr(), _stream_handle(stream)),
+           "dc_topsis_tiles")
+    return best, bscore, sc

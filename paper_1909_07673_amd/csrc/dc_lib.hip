@@ -5,6 +5,7 @@
 #include "../../include/dcsched.h"
 #include "dc_kernels.hpp"
 #include "dc_grid.hpp"
+#include "dc_tiles.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -1164,6 +1165,50 @@ int dc_pending(dc_ctx *ctx, int64_t *n) {
         for (int bi : ctx->queued) q += ctx->batches[bi]->R;
         *n = q;
     }
+    return DC_OK;
+}
+
+int dc_topsis_tiles(int64_t T, int32_t C, int32_t N, const int32_t *x, const uint8_t *feasible,
+                    const int32_t *cost, const float *weight, float *scores, int32_t *best, float *best_score,
+                    void *stream) {
+    if (T < 0 || T > 0x7fffffffLL || C < 1 || C > DC_MAX_CRIT || N < 1 || N > (1 << 20)) return DC_EINVAL;
+    if (T == 0) return DC_OK;
+    if (!x || !best || !weight) return DC_EINVAL;
+    TileArgs a{};
+    a.x = x;
+    a.feas = feasible;
+    a.scores = scores;
+    a.best = best;
+    a.best_score = best_score;
+    a.C = C;
+    a.N = N;
+    for (int c = 0; c < C; ++c) {
+        if (!(weight[c] > 0.f) || !std::isfinite(weight[c])) return DC_EINVAL;
+        a.w[c] = weight[c];
+        a.cost[c] = cost ? (cost[c] != 0) : 0;
+    }
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    auto al = [](const void *p, uintptr_t m) { return (reinterpret_cast<uintptr_t>(p) & (m - 1)) == 0; };
+    const bool vec = N % 4 == 0 && al(x, 16) && (!scores || al(scores, 16)) && (!feasible || al(feasible, 4));
+    const int it = (N + 4 * kTileBlock - 1) / (4 * kTileBlock);
+    const dim3 grid(static_cast<unsigned>(T)), block(kTileBlock);
+    if (vec && it <= 4) {
+        const int IT = it <= 1 ? 1 : it <= 2 ? 2 : 4;
+#define DCS_TILES_C(CC)                                                                                  \
+    case CC:                                                                                             \
+        if (IT == 1) hipLaunchKernelGGL((k_topsis_tiles_reg<CC, 1>), grid, block, 0, st, a);             \
+        else if (IT == 2) hipLaunchKernelGGL((k_topsis_tiles_reg<CC, 2>), grid, block, 0, st, a);        \
+        else hipLaunchKernelGGL((k_topsis_tiles_reg<CC, 4>), grid, block, 0, st, a);                     \
+        break;
+        switch (C) {
+            DCS_TILES_C(1) DCS_TILES_C(2) DCS_TILES_C(3) DCS_TILES_C(4)
+            DCS_TILES_C(5) DCS_TILES_C(6) DCS_TILES_C(7) DCS_TILES_C(8)
+        }
+#undef DCS_TILES_C
+    } else {
+        hipLaunchKernelGGL(k_topsis_tiles_gen, grid, block, 0, st, a);
+    }
+    if (hipGetLastError() != hipSuccess) return DC_EDEVICE;
     return DC_OK;
 }
 

@@ -232,3 +232,24 @@ def make_trace(seed: int, duration_s: float, rate_per_s: float = 5000.0,
     dep[dep >= duration_s] = np.inf
     reqs = make_requests(arr.shape[0], rng, n_lo, n_hi)
     return reqs, arr, dep
+
+
+# Value ranges of decision-matrix columns for standalone scoring: residual
+# CPU cores, residual RAM GB, placed-container flag, path bandwidth (Mbps),
+# summed hop count, then wider columns for extra criteria.
+TILE_RANGES = ((0, 32), (0, 256), (0, 1), (0, 40000), (0, 384), (0, 100000), (0, 10), (0, (1 << 22) - 1))
+
+
+def make_tiles(seed: int, T: int, N: int, C: int = 4, feasible_p: Optional[float] = None):
+    """T integer decision matrices, criterion-major int32 [T][C][N], with the
+    column ranges above, and (when feasible_p is given) a uint8 [T][N]
+    feasibility mask drawn Bernoulli(feasible_p)."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
+    x = np.empty((T, C, N), np.int32)
+    for c in range(C):
+        lo, hi = TILE_RANGES[c % len(TILE_RANGES)]
+        x[:, c, :] = rng.integers(lo, hi + 1, size=(T, N), dtype=np.int32)
+    feas = None
+    if feasible_p is not None:
+        feas = (rng.random((T, N)) < feasible_p).astype(np.uint8)
+    return x, feas
