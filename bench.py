@@ -107,12 +107,12 @@ def run_batch(args, wl):
         kw = dict(method=dc.DC_AHP, crit=(dc.DC_CRIT_CPU, dc.DC_CRIT_RAM, dc.DC_CRIT_UPLINK, dc.DC_CRIT_PATHBW,
                                           dc.DC_CRIT_HOPS), cost=(0, 0, 0, 0, 1))
     mode = dc.DC_MODE_BATCHED if wl["mode"] == "batched" else dc.DC_MODE_PLAIN
-    s = dc.Scheduler(insts, mode=mode, stream=stream, grid=args.grid, graph=args.graph, **kw)
+    s = dc.Scheduler(insts, mode=mode, stream=stream, grid=args.grid, graph=args.graph, block=args.block, **kw)
     for i, rl in enumerate(reqs):
         for r in rl:
             s.submit(r, instance=i)
     s.rewind()                      # uploads the requests; they stay resident in HBM
-    tuned = s.autotune() if wl["method"] == "topsis" else None
+    tuned = s.autotune() if wl["method"] == "topsis" and not args.block else (args.block or None)
     torch.cuda.synchronize()
     buf = np.zeros(s.pending(), dc.RESULT_DTYPE)
     for _ in range(args.warmup):
@@ -131,6 +131,9 @@ def run_batch(args, wl):
     wall = time.perf_counter() - t0
     assert len(results) == len(buf), "every queued request is decided in a step"
     steps = step_count_array(results)
+    per_inst = np.bincount(results["instance"], weights=np.where(results["status"] == 1, results["n"],
+                                                                  results["failed_at"] + 1),
+                           minlength=len(insts))
     hs = steps * N
     value = hs * args.steps / wall
     lat = s.latency_us()
@@ -143,7 +146,8 @@ def run_batch(args, wl):
         "config": {"workload": wl["text"], "k": insts[0].k, "hosts": N, "instances": len(insts),
                    "requests": sum(len(r) for r in reqs), "container_steps": steps,
                    "form": wl["mode"], "method": wl["method"], "block": tuned, "grid": args.grid,
-                   "graph": args.graph},
+                   "graph": args.graph,
+                   "steps_per_instance": {"mean": float(per_inst.mean()), "max": int(per_inst.max())}},
         "latency_us": dict(percentiles(lat), kind="service (first step start to decision), device clock"),
     }
     if wl["method"] == "topsis":
@@ -156,6 +160,10 @@ def run_batch(args, wl):
                            "avg_launch_us": avg_launch_s * 1e6, "launches_per_step": per_step_launches,
                            "bytes_per_launch": bytes_per_launch}
         meth = oracle.method(kind=oracle.TOPSIS)
+        if not args.no_scoring_kernel:
+            # the scoring stage alone, streaming resident matrices (HBM-bound)
+            out["scoring_kernel_roofline"] = dict(
+                tile_timing(20, 2)[3], workload=WORKLOADS["tiles"]["text"])
     else:
         # AHP: the pairwise passes dominate; 2*C*N^2 pair evaluations per
         # container step, at PAIR_OPS VALU lane-instructions each
@@ -182,26 +190,53 @@ AHP_PAIR_OPS = 28
 
 TILE_T, TILE_C, TILE_N = 32768, 4, 1024
 
+# HBM traffic of the scoring kernel per launch at the shape above, from two
+# rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of
+# `bench.py --workload tiles --copy-ref`, each scaled by what the same
+# counter reads for the run's plain 512 MiB device copy.  Valid only for the
+# kernel sources the counters were taken on (their SHA-256 below); reported
+# as null once those sources change.
+TILE_TRAFFIC = {
+    "sources": ("paper_1909_07673_amd/csrc/dc_tiles.hpp", "paper_1909_07673_amd/csrc/dc_step.hpp"),
+    "sha256": "f5c5e44fac14ac35d3272cbbb96a922e30c515b574c4df9a5827d8fc4afc3082",
+    "fetch_kib": 262216.56, "fetch_copy_kib": 262162.25,     # copy reads 524288 KiB
+    "write_kib": 517.41, "write_copy_kib": 524288.0,         # copy writes 524288 KiB
+}
 
-def run_tiles(args, wl):
-    """Kernel roofline of TOPSIS scoring: one launch scores every server of
-    every matrix and selects the best; the matrices are resident in HBM and
-    larger than the 256 MiB last-level cache, so each launch streams them."""
-    import numpy as np
+
+def tile_traffic():
+    """Scaled HBM bytes per launch of the scoring kernel, or None when its
+    sources differ from those the counters were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in TILE_TRAFFIC["sources"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != TILE_TRAFFIC["sha256"]:
+        return None
+    t = TILE_TRAFFIC
+    fetch = t["fetch_kib"] * (524288.0 / t["fetch_copy_kib"])
+    write = t["write_kib"] * (524288.0 / t["write_copy_kib"])
+    return (fetch + write) * 1024.0
+
+
+def tile_timing(steps, warmup, copy_ref=False):
+    """Times dc_topsis_tiles over TILE_T resident matrices: returns (host
+    matrices, average launch seconds from HIP events on the launch stream,
+    wall seconds of the timed launches, roofline dict)."""
     import torch
     import paper_1909_07673_amd as dc
     from workloads import make_tiles
 
-    torch.cuda.set_device(0)
     T, C, N = TILE_T, TILE_C, TILE_N
     xh, _ = make_tiles(seed=2024, T=T, N=N, C=C)
     x = torch.from_numpy(xh).cuda()
     w = [1.0 / C] * C
     stream = torch.cuda.current_stream()
-    for _ in range(max(args.warmup, 1)):
+    for _ in range(max(warmup, 1)):
         dc.topsis_tiles(x, w, stream=stream)
     torch.cuda.synchronize()
-    if args.copy_ref:
+    if copy_ref:
         # a plain device copy of the same bytes, for scaling HBM counters
         y = torch.empty_like(x)
         y.copy_(x)
@@ -210,24 +245,40 @@ def run_tiles(args, wl):
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record(stream)
-    for _ in range(args.steps):
-        best, bscore, _ = dc.topsis_tiles(x, w, stream=stream)
+    for _ in range(steps):
+        dc.topsis_tiles(x, w, stream=stream)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    launch_s = e0.elapsed_time(e1) / 1e3 / args.steps
-    hs = T * N
+    launch_s = e0.elapsed_time(e1) / 1e3 / steps
     bytes_per_launch = 4 * C * N * T + 8 * T          # criteria read once, best + score written
     achieved = bytes_per_launch / launch_s / 1e9
+    roof = {"bound": "hbm", "kernel": "k_topsis_tiles_wave<4,4>", "achieved": achieved,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": tile_traffic(),
+            "avg_launch_us": launch_s * 1e6, "bytes_per_launch": bytes_per_launch}
+    del x
+    return xh, launch_s, wall, roof
+
+
+def run_tiles(args, wl):
+    """Kernel roofline of TOPSIS scoring: one launch scores every server of
+    every matrix and selects the best; the matrices are resident in HBM and
+    larger than the 256 MiB last-level cache, so each launch streams them."""
+    import numpy as np
+    import torch
+
+    torch.cuda.set_device(0)
+    T, C, N = TILE_T, TILE_C, TILE_N
+    w = [1.0 / C] * C
+    xh, launch_s, wall, roof = tile_timing(args.steps, args.warmup, args.copy_ref)
+    hs = T * N
     out = {
         "metric": METRIC, "value": hs * args.steps / wall, "unit": "host-scores/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": wl["text"], "matrices": T, "criteria": C, "hosts": N, "form": "tiles",
                    "method": "topsis"},
-        "roofline": {"bound": "hbm", "kernel": "k_topsis_tiles_reg<4,1>", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "avg_launch_us": launch_s * 1e6, "bytes_per_launch": bytes_per_launch},
+        "roofline": roof,
     }
     if not args.no_cpu_baseline:
         import oracle
@@ -348,6 +399,10 @@ def main():
     ap.add_argument("--trace-s", type=float, default=2.0, help="serving: seconds of Poisson arrivals")
     ap.add_argument("--grid", type=int, default=0, choices=(0, 1, 2),
                     help="TOPSIS step: 0 automatic, 1 one workgroup, 2 one cooperative workgroup per pod")
+    ap.add_argument("--block", type=int, default=0, choices=(0, 256, 512, 1024),
+                    help="plain/batched TOPSIS: workgroup size (0 = autotuned)")
+    ap.add_argument("--no-scoring-kernel", action="store_true",
+                    help="plain/batched: skip the separate roofline of the scoring stage alone")
     ap.add_argument("--copy-ref", action="store_true",
                     help="tiles: also run one plain copy of the matrices (reference for HBM byte counters)")
     ap.add_argument("--graph", type=int, default=0, choices=(0, 1, 2),

@@ -291,17 +291,7 @@ __device__ bool grid_topsis_step(const Topo &t, const State &st, const Method &m
         f &= (de1 < 0) | ((de0 == de1) & (w * h + fdiv(x, t.rh) == de0));
         f &= (dp1 < 0) | ((dp0 == dp1) & (w == dp0));
         if (!f) return 0ull;
-        float dp2 = 0.f, dm2 = 0.f;
-#pragma unroll
-        for (int c = 0; c < kMaxCrit; ++c) {
-            if (c >= nc) break;
-            const float v = static_cast<float>(xs[c * hh + x]);
-            const float a = v - ap[c], z = v - am[c];
-            dp2 = fmaf(q[c] * a, a, dp2);
-            dm2 = fmaf(q[c] * z, z, dm2);
-        }
-        const float dpv = sqrtf(dp2), dmv = sqrtf(dm2), den = dpv + dmv;
-        return score_key(den > 0.f ? dmv / den : 0.f, u);
+        return score_key(topsis_close(nc, [&](int c) { return xs[c * hh + x]; }, q, ap, am), u);
     };
     auto wg_best = [&]() {
         unsigned long long kb = 0;
@@ -328,19 +318,9 @@ __device__ bool grid_topsis_step(const Topo &t, const State &st, const Method &m
     };
     const int slot = g.flag[7];
     if (slot >= 0)
-        for (int x = threadIdx.x; x < hh; x += BS) {
-            float dp2 = 0.f, dm2 = 0.f;
-#pragma unroll
-            for (int c = 0; c < kMaxCrit; ++c) {
-                if (c >= nc) break;
-                const float v = static_cast<float>(xs[c * hh + x]);
-                const float a = v - ap[c], z = v - am[c];
-                dp2 = fmaf(q[c] * a, a, dp2);
-                dm2 = fmaf(q[c] * z, z, dm2);
-            }
-            const float dpv = sqrtf(dp2), dmv = sqrtf(dm2), den = dpv + dmv;
-            tr.scores[static_cast<size_t>(slot) * t.N + ubase + x] = den > 0.f ? dmv / den : 0.f;
-        }
+        for (int x = threadIdx.x; x < hh; x += BS)
+            tr.scores[static_cast<size_t>(slot) * t.N + ubase + x] =
+                topsis_close(nc, [&](int c) { return xs[c * hh + x]; }, q, ap, am);
     wg_best();
     // ---- E: global argmax, commit by workgroup 0, retries
     for (;;) {

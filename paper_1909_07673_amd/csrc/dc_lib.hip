@@ -1190,21 +1190,52 @@ int dc_topsis_tiles(int64_t T, int32_t C, int32_t N, const int32_t *x, const uin
     const hipStream_t st = static_cast<hipStream_t>(stream);
     auto al = [](const void *p, uintptr_t m) { return (reinterpret_cast<uintptr_t>(p) & (m - 1)) == 0; };
     const bool vec = N % 4 == 0 && al(x, 16) && (!scores || al(scores, 16)) && (!feasible || al(feasible, 4));
-    const int it = (N + 4 * kTileBlock - 1) / (4 * kTileBlock);
+    // four-server groups per lane when one wavefront holds the tile
+    const int V = (N + 4 * kWave - 1) / (4 * kWave);
+    const int Vp = V <= 1 ? 1 : V <= 2 ? 2 : V <= 4 ? 4 : V <= 8 ? 8 : 16;   // 16: two passes
     const dim3 grid(static_cast<unsigned>(T)), block(kTileBlock);
-    if (vec && it <= 4) {
-        const int IT = it <= 1 ? 1 : it <= 2 ? 2 : 4;
-#define DCS_TILES_C(CC)                                                                                  \
-    case CC:                                                                                             \
-        if (IT == 1) hipLaunchKernelGGL((k_topsis_tiles_reg<CC, 1>), grid, block, 0, st, a);             \
-        else if (IT == 2) hipLaunchKernelGGL((k_topsis_tiles_reg<CC, 2>), grid, block, 0, st, a);        \
-        else hipLaunchKernelGGL((k_topsis_tiles_reg<CC, 4>), grid, block, 0, st, a);                     \
-        break;
-        switch (C) {
-            DCS_TILES_C(1) DCS_TILES_C(2) DCS_TILES_C(3) DCS_TILES_C(4)
-            DCS_TILES_C(5) DCS_TILES_C(6) DCS_TILES_C(7) DCS_TILES_C(8)
+    if (vec && Vp <= 8 && C * Vp <= 16) {
+        // persistent grid: as many workgroups as fit on the device at once,
+        // never more than needed for one wavefront per tile
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return DC_EDEVICE;
+        auto pgrid = [&](const void *k) {
+            int per = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, kTileBlock, 0) != hipSuccess || per < 1) per = 1;
+            const long long need = (T + kTileWaves - 1) / kTileWaves;
+            return dim3(static_cast<unsigned>(std::min<long long>(need, (long long)per * cus)));
+        };
+#define DCS_TILES_LAUNCH(CC, VV)                                                                         \
+    hipLaunchKernelGGL((k_topsis_tiles_wave<CC, VV>),                                                    \
+                       pgrid(reinterpret_cast<const void *>(k_topsis_tiles_wave<CC, VV>)), block, 0, st, a, (long long)T)
+        switch (C * 100 + Vp) {
+        case 101: DCS_TILES_LAUNCH(1, 1); break;
+        case 102: DCS_TILES_LAUNCH(1, 2); break;
+        case 104: DCS_TILES_LAUNCH(1, 4); break;
+        case 108: DCS_TILES_LAUNCH(1, 8); break;
+        case 201: DCS_TILES_LAUNCH(2, 1); break;
+        case 202: DCS_TILES_LAUNCH(2, 2); break;
+        case 204: DCS_TILES_LAUNCH(2, 4); break;
+        case 208: DCS_TILES_LAUNCH(2, 8); break;
+        case 301: DCS_TILES_LAUNCH(3, 1); break;
+        case 302: DCS_TILES_LAUNCH(3, 2); break;
+        case 304: DCS_TILES_LAUNCH(3, 4); break;
+        case 401: DCS_TILES_LAUNCH(4, 1); break;
+        case 402: DCS_TILES_LAUNCH(4, 2); break;
+        case 404: DCS_TILES_LAUNCH(4, 4); break;
+        case 501: DCS_TILES_LAUNCH(5, 1); break;
+        case 502: DCS_TILES_LAUNCH(5, 2); break;
+        case 601: DCS_TILES_LAUNCH(6, 1); break;
+        case 602: DCS_TILES_LAUNCH(6, 2); break;
+        case 701: DCS_TILES_LAUNCH(7, 1); break;
+        case 702: DCS_TILES_LAUNCH(7, 2); break;
+        case 801: DCS_TILES_LAUNCH(8, 1); break;
+        case 802: DCS_TILES_LAUNCH(8, 2); break;
+        default: return DC_EINVAL;          // unreachable: Vp <= 8, C * Vp <= 16
         }
-#undef DCS_TILES_C
+#undef DCS_TILES_LAUNCH
     } else {
         hipLaunchKernelGGL(k_topsis_tiles_gen, grid, block, 0, st, a);
     }

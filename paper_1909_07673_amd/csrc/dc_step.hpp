@@ -644,6 +644,28 @@ __device__ __forceinline__ void finish_stats(const Smem &sm, int nc, unsigned lo
     }
 }
 
+// TOPSIS closeness of one server from its integer criteria get(c), c < nc
+// (section V-C): Ed+- = sqrt(sum_c q_c (x_c - A+-_c)^2) with q_c = w_c^2 /
+// sum_u x_cu^2, Rank = Ed- / (Ed+ + Ed-), 0 when both are 0.  Differences of
+// integers below 2^22 are exact in FP32; the square roots and the quotient
+// use the hardware square root and reciprocal (1 ulp).  Every form scores
+// through this function, so equal criteria and statistics give equal bits.
+template <class Get>
+__device__ __forceinline__ float topsis_close(int nc, Get get, const float *q, const float *ap, const float *am) {
+    float dp2 = 0.f, dm2 = 0.f;
+#pragma unroll
+    for (int c = 0; c < kMaxCrit; ++c) {
+        if (c >= nc) break;
+        const float x = static_cast<float>(get(c));
+        const float a = x - ap[c], z = x - am[c];
+        dp2 = fmaf(q[c] * a, a, dp2);
+        dm2 = fmaf(q[c] * z, z, dm2);
+    }
+    const float dp = __builtin_amdgcn_sqrtf(dp2), dm = __builtin_amdgcn_sqrtf(dm2);
+    const float den = dp + dm;
+    return den > 0.f ? fminf(dm * __builtin_amdgcn_rcpf(den), 1.0f) : 0.f;
+}
+
 __device__ __forceinline__ unsigned long long score_key(float s, int u) {
     return (static_cast<unsigned long long>(__float_as_uint(s) + 1u) << 32) | static_cast<unsigned>(~u);
 }
@@ -760,18 +782,7 @@ __device__ bool topsis_step(const Topo &t, const State &st, const Method &m, con
         am[c] = static_cast<float>(m.cost[c] ? mx[c] : mn[c]);
     }
     auto closeness = [&](int u) -> float {
-        float dp2 = 0.f, dm2 = 0.f;
-#pragma unroll
-        for (int c = 0; c < kMaxCrit; ++c) {
-            if (c >= nc) break;
-            const float x = static_cast<float>(xs[c * N + u]);
-            const float a = x - ap[c], z = x - am[c];
-            dp2 = fmaf(q[c] * a, a, dp2);
-            dm2 = fmaf(q[c] * z, z, dm2);
-        }
-        const float dp = sqrtf(dp2), dm = sqrtf(dm2);
-        const float den = dp + dm;
-        return den > 0.f ? dm / den : 0.f;
+        return topsis_close(nc, [&](int c) { return xs[c * N + u]; }, q, ap, am);
     };
     const int slot = sm.misc[M_TRACE];
     if (slot >= 0)

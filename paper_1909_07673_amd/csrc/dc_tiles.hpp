@@ -92,82 +92,103 @@ __device__ __forceinline__ void tile_select(const TileArgs &a, long long t, unsi
 }
 
 __device__ __forceinline__ float tile_close(int nc, const int *v, const float *q, const float *ap, const float *am) {
-    float dp2 = 0.f, dm2 = 0.f;
-#pragma unroll
-    for (int c = 0; c < kMaxCrit; ++c) {
-        if (c >= nc) break;
-        const float f = static_cast<float>(v[c]);
-        const float a = f - ap[c], z = f - am[c];
-        dp2 = fmaf(q[c] * a, a, dp2);
-        dm2 = fmaf(q[c] * z, z, dm2);
-    }
-    const float dp = sqrtf(dp2), dm = sqrtf(dm2), den = dp + dm;
-    return den > 0.f ? dm / den : 0.f;
+    return topsis_close(nc, [&](int c) { return v[c]; }, q, ap, am);
 }
 
-// One workgroup per tile, N % 4 == 0 and N <= 4 * kTileBlock * IT: each
-// thread loads its 4-server groups of every criterion once (16-byte loads,
-// coalesced along the servers) and keeps them in registers for both passes,
-// so the tile crosses HBM exactly once.
-template <int C, int IT>
-__global__ __launch_bounds__(kTileBlock) void k_topsis_tiles_reg(TileArgs a) {
-    __shared__ int wst[5 * C * kTileWaves];
-    __shared__ unsigned long long wkey[kTileWaves];
-    const long long t = blockIdx.x;
+// N % 4 == 0 and N <= 256 * V: one wavefront per tile, four per workgroup,
+// walking tiles with a grid stride.  Lane l holds the 4-server groups
+// l, l + 64, ..., l + 64 (V - 1) of every criterion in registers (16-byte
+// loads, coalesced along the servers), so a tile crosses HBM exactly once;
+// all reductions are wave DPP reductions, with no LDS and no barrier.
+typedef int dcs_v4i __attribute__((ext_vector_type(4)));
+
+template <int C, int V>
+__global__ __launch_bounds__(kTileBlock) void k_topsis_tiles_wave(TileArgs a, long long T) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const long long W = static_cast<long long>(gridDim.x) * kTileWaves;
     const int N = a.N;
-    const int *x = a.x + static_cast<size_t>(t) * C * N;
-    int4 v[C][IT];
+    const size_t tile = static_cast<size_t>(C) * N;
+    for (long long t = static_cast<long long>(blockIdx.x) * kTileWaves + threadIdx.x / kWave; t < T; t += W) {
+        const int *x = a.x + t * tile;
+        int4 v[C][V];
 #pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        const int g = 4 * (it * kTileBlock + static_cast<int>(threadIdx.x));
+        for (int q = 0; q < V; ++q) {
+            const int g = 4 * (q * kWave + lane);
 #pragma unroll
-        for (int c = 0; c < C; ++c)
-            v[c][it] = g < N ? *reinterpret_cast<const int4 *>(x + static_cast<size_t>(c) * N + g) : make_int4(0, 0, 0, 0);
-    }
-    unsigned long long s2[kMaxCrit];
-    int mx[kMaxCrit], mn[kMaxCrit];
-#pragma unroll
-    for (int c = 0; c < kMaxCrit; ++c) { s2[c] = 0; mx[c] = -kBig - 1; mn[c] = kBig; }
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        if (4 * (it * kTileBlock + static_cast<int>(threadIdx.x)) >= N) break;
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const int4 e = v[c][it];
-            s2[c] += static_cast<unsigned long long>(static_cast<long long>(e.x) * e.x) +
-                     static_cast<unsigned long long>(static_cast<long long>(e.y) * e.y) +
-                     static_cast<unsigned long long>(static_cast<long long>(e.z) * e.z) +
-                     static_cast<unsigned long long>(static_cast<long long>(e.w) * e.w);
-            mx[c] = max(mx[c], max(max(e.x, e.y), max(e.z, e.w)));
-            mn[c] = min(mn[c], min(min(e.x, e.y), min(e.z, e.w)));
-        }
-    }
-    tile_stats(C, s2, mx, mn, wst);
-    float q[kMaxCrit], ap[kMaxCrit], am[kMaxCrit];
-    tile_factors(a, s2, mx, mn, q, ap, am);
-    unsigned long long kb = 0;
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        const int g = 4 * (it * kTileBlock + static_cast<int>(threadIdx.x));
-        if (g >= N) break;
-        unsigned fm = 0x01010101u;
-        if (a.feas) fm = *reinterpret_cast<const unsigned *>(a.feas + static_cast<size_t>(t) * N + g);
-        float sc[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            int vv[C];
-#pragma unroll
-            for (int c = 0; c < C; ++c) vv[c] = j == 0 ? v[c][it].x : j == 1 ? v[c][it].y : j == 2 ? v[c][it].z : v[c][it].w;
-            sc[j] = tile_close(C, vv, q, ap, am);
-            if ((fm >> (8 * j)) & 0xffu) {
-                const unsigned long long k = score_key(sc[j], g + j);
-                kb = k > kb ? k : kb;
+            for (int c = 0; c < C; ++c) {
+                int4 e = make_int4(0, 0, 0, 0);
+                if (g < N) {
+                    const dcs_v4i r = __builtin_nontemporal_load(
+                        reinterpret_cast<const dcs_v4i *>(x + static_cast<size_t>(c) * N + g));
+                    e = make_int4(r.x, r.y, r.z, r.w);
+                }
+                v[c][q] = e;
             }
         }
-        if (a.scores)
-            *reinterpret_cast<float4 *>(a.scores + static_cast<size_t>(t) * N + g) = make_float4(sc[0], sc[1], sc[2], sc[3]);
+        // exact column statistics: per-lane 64-bit sums of squares (values
+        // below 2^22, at most 4V <= 32 of them, so below 2^49), reduced as a
+        // low 26-bit chunk (64 lanes sum below 2^32) and the rest
+        unsigned long long s2[kMaxCrit];
+        int mx[kMaxCrit], mn[kMaxCrit];
+#pragma unroll
+        for (int c = 0; c < kMaxCrit; ++c) { s2[c] = 0; mx[c] = -kBig - 1; mn[c] = kBig; }
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+            if (4 * (q * kWave + lane) >= N) break;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int4 e = v[c][q];
+                const unsigned ex = e.x, ey = e.y, ez = e.z, ew = e.w;
+                s2[c] += static_cast<unsigned long long>(ex) * ex;
+                s2[c] += static_cast<unsigned long long>(ey) * ey;
+                s2[c] += static_cast<unsigned long long>(ez) * ez;
+                s2[c] += static_cast<unsigned long long>(ew) * ew;
+                mx[c] = max(mx[c], max(max(e.x, e.y), max(e.z, e.w)));
+                mn[c] = min(mn[c], min(min(e.x, e.y), min(e.z, e.w)));
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const unsigned lo = static_cast<unsigned>(wave_sum(static_cast<int>(s2[c] & 0x3ffffffu)));
+            const unsigned hi = static_cast<unsigned>(wave_sum(static_cast<int>(s2[c] >> 26)));
+            s2[c] = static_cast<unsigned long long>(lo) + (static_cast<unsigned long long>(hi) << 26);
+            mx[c] = wave_max(mx[c]);
+            mn[c] = wave_min(mn[c]);
+        }
+        float q[kMaxCrit], ap[kMaxCrit], am[kMaxCrit];
+        tile_factors(a, s2, mx, mn, q, ap, am);
+        unsigned long long kb = 0;
+#pragma unroll
+        for (int qq = 0; qq < V; ++qq) {
+            const int g = 4 * (qq * kWave + lane);
+            if (g >= N) break;
+            unsigned fm = 0x01010101u;
+            if (a.feas) fm = *reinterpret_cast<const unsigned *>(a.feas + static_cast<size_t>(t) * N + g);
+            float sc[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                int vv[C];
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    vv[c] = j == 0 ? v[c][qq].x : j == 1 ? v[c][qq].y : j == 2 ? v[c][qq].z : v[c][qq].w;
+                sc[j] = tile_close(C, vv, q, ap, am);
+                if ((fm >> (8 * j)) & 0xffu) {
+                    const unsigned long long k = score_key(sc[j], g + j);
+                    kb = k > kb ? k : kb;
+                }
+            }
+            if (a.scores)
+                *reinterpret_cast<float4 *>(a.scores + static_cast<size_t>(t) * N + g) =
+                    make_float4(sc[0], sc[1], sc[2], sc[3]);
+        }
+        const unsigned hiw = wave_umax(static_cast<unsigned>(kb >> 32));
+        const unsigned low = wave_umax(static_cast<unsigned>(kb >> 32) == hiw ? static_cast<unsigned>(kb) : 0u);
+        if (lane == 0) {
+            const unsigned long long best = (static_cast<unsigned long long>(hiw) << 32) | low;
+            a.best[t] = best ? static_cast<int>(~low) : -1;
+            if (a.best_score) a.best_score[t] = best ? __uint_as_float(hiw - 1u) : 0.f;
+        }
     }
-    tile_select(a, t, kb, wkey);
 }
 
 // Any shape: one workgroup per tile, two passes over the tile in global

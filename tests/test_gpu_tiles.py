@@ -56,10 +56,16 @@ def _run(x, feas, w, cost, scores=True):
 
 
 SHAPES = [
-    # T, C, N, feasible_p, cost     (paths: 4-server groups in registers, or two passes)
-    (9, 4, 1024, None, None),          # registers, one group per thread
-    (5, 5, 2048, 0.6, [0, 0, 0, 0, 1]),
-    (3, 4, 4096, 0.3, None),           # registers, four groups per thread
+    # T, C, N, feasible_p, cost     (paths: one wavefront per tile with the
+    # tile in registers, or one workgroup per tile with two passes)
+    (9, 4, 1024, None, None),          # wavefront, four groups per lane
+    (13, 2, 2048, 0.5, [1, 0]),        # wavefront, eight groups per lane
+    (5, 1, 2048, 0.9, None),           # wavefront, eight groups per lane, one criterion
+    (4, 1, 4096, 0.9, None),           # two passes (beyond one wavefront's registers)
+    (7, 3, 1000, 0.5, [0, 1, 0]),      # wavefront, ragged last group
+    (6, 5, 512, 0.6, [0, 0, 0, 0, 1]), # wavefront, five criteria
+    (5, 5, 2048, 0.6, [0, 0, 0, 0, 1]),  # two passes
+    (3, 4, 4096, 0.3, None),           # two passes
     (4, 8, 3000, 0.5, [0, 1, 0, 0, 1, 0, 0, 0]),   # ragged last group
     (3, 3, 54, 0.7, None),             # k=6: N % 4 != 0, two passes
     (2, 4, 27648, 0.8, None),          # k=48: two passes
@@ -102,9 +108,9 @@ def test_tiles_edge_cases():
 
 
 def test_tiles_paths_identical():
-    """The register path and the two-pass path (forced by a misaligned view
+    """The wavefront path and the two-pass path (forced by a misaligned view
     of the same data) give bit-identical results; scores are optional."""
-    T, C, N = 7, 4, 2048
+    T, C, N = 7, 4, 1024
     x, feas = make_tiles(seed=5, T=T, N=N, C=C, feasible_p=0.4)
     w = [0.25] * 4
     b1, s1, sc1 = _run(x, feas, w, None)
