@@ -29,9 +29,11 @@ HBM_PEAK_GBS = 8000.0
 # state arrays (CPU, RAM, placed count, uplink, edge-aggregation and
 # aggregation-core residuals) read once per scored host.
 BYTES_PER_HOST_SCORE = 24
-# FP32 vector issue rate of MI355X without packed math: 256 CUs x 4 SIMDs x
-# 16 lanes x 2.4 GHz lane-instructions per second.
-VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
+# FP32 vector peak of MI355X, 157.3 TFLOP/s (256 CUs x 2.4 GHz x 128 FMA
+# lanes per clock), as VALU lane-instructions per second: one lane-FMA per
+# issue slot.  The Saaty passes are mostly compares and selects, which do not
+# pack, so this peak is generous to them.
+VALU_LANE_OPS = 157.3e12 / 2
 
 WORKLOADS = {
     "plain": dict(preset="plain", mode="plain", method="topsis",
@@ -42,7 +44,7 @@ WORKLOADS = {
                          "per instance, TOPSIS, batched form (one persistent launch)"),
     "ahp": dict(preset="ahp", mode="plain", method="ahp",
                 text="k=32 fat-tree (8192 hosts), 500 FCFS requests of 8-64 containers, 0-70% background, AHP "
-                     "(Saaty 1-9) on CPU/RAM/uplink/path-bw/hops(cost), four launches per container step"),
+                     "(Saaty 1-9) on CPU/RAM/uplink/path-bw/hops(cost), five launches per container step"),
     "tiles": dict(preset=None, mode="tiles", method="topsis",
                   text="TOPSIS scoring + selection alone (dc_topsis_tiles) over 32,768 materialised 4 x 1024 "
                        "integer decision matrices (512 MiB, the batched shape: 256 instances x 128 steps), "
@@ -183,8 +185,8 @@ def run_batch(args, wl):
     return out
 
 
-# VALU instructions per Saaty pair evaluation in the AHP passes (counted in
-# the compiled inner loops of k_ahp_colsum / k_ahp_rowsum).
+# VALU instructions per Saaty pair evaluation in the AHP passes, counted in
+# the compiled inner loops (27 in k_ahp_colsum, 27-29 in k_ahp_rowsum).
 AHP_PAIR_OPS = 28
 
 
@@ -327,6 +329,8 @@ def replay(s, dc, reqs, arr, dep, serving, horizon_s):
                 backlog.append(t)
             elif s.release(ids[t]) not in (dc.DC_OK,):
                 heapq.heappush(events, (now + 1e-4, 1, t))
+        # the plain form takes the whole backlog in one blocking schedule
+        # call; the serving form admits what fits and keeps polling
         while backlog:
             t = backlog[0]
             rid = s.try_submit(reqs[t]) if serving else s.submit(reqs[t])
@@ -335,13 +339,10 @@ def replay(s, dc, reqs, arr, dep, serving, horizon_s):
             ids[t] = rid
             id2t[rid] = t
             backlog.pop(0)
-            if not serving:
-                absorb(s.schedule())
-        if serving:
-            absorb(s.schedule())
+        absorb(s.schedule())
         if not events and not backlog and len(done) == n:
             break
-        if serving and not backlog and (not events or events[0][0] > now + 2e-4):
+        if not backlog and (not events or events[0][0] > now + 2e-4):
             time.sleep(5e-5)
     wall = time.perf_counter() - t0
     return done, sojourn, wall

@@ -236,9 +236,56 @@ __global__ __launch_bounds__(kAhpBlock) void k_ahp_rowsum(Params p) {
     if (i < N) p.rowpart[((size_t)c * p.nJ + jb) * N + i] = s;
 }
 
-// AHP step, last stage: global priority PG[u] = sum_c P1[c] * L2_c[u], with
-// P1 the local rank of the criteria-level ratio matrix W[a]/W[b] (equal to
-// W when the weights sum to 1), then selection and commit.
+// Local rank of the criteria-level ratio matrix W[a] / W[b] (column sums,
+// then row means of the normalised matrix); equal to W when the weights sum
+// to 1.  Kept as FP32 values, widened to FP64 for the sums that use them.
+__device__ __forceinline__ void ahp_p1(const Method &m, double *p1) {
+    const int nc = m.nc;
+    double colsum[kMaxCrit];
+    for (int b = 0; b < kMaxCrit; ++b) {
+        colsum[b] = 1.0;
+        if (b >= nc) continue;
+        colsum[b] = 0.0;
+        for (int a = 0; a < nc; ++a) colsum[b] += static_cast<double>(m.w[a]) / m.w[b];
+    }
+    for (int a = 0; a < kMaxCrit; ++a) {
+        p1[a] = 0.0;
+        if (a >= nc) continue;
+        double s = 0.0;
+        for (int b = 0; b < nc; ++b) s += (static_cast<double>(m.w[a]) / m.w[b]) / colsum[b];
+        p1[a] = static_cast<double>(static_cast<float>(s / nc));
+    }
+}
+
+// AHP step, stage 4: global priority of every server, PG[u] = sum_c P1[c] *
+// L2_c[u], summing the row partials of pass B in fixed order.  Written as
+// FP32 into xs row nc + 1 (free once the criteria stage is done), and into
+// the trace when this step is recorded.
+__global__ __launch_bounds__(kAhpBlock) void k_ahp_pg(Params p) {
+    if (p.b.status[p.s.r] == 0) return;
+    const int N = p.t.N, nc = p.m.nc;
+    const int u = blockIdx.x * kAhpBlock + threadIdx.x;
+    if (u >= N) return;
+    double p1[kMaxCrit];
+    ahp_p1(p.m, p1);
+    const double invN = 1.0 / N;
+    double s = 0.0;
+    for (int c = 0; c < nc; ++c) {
+        double l = 0.0;
+        for (int jb = 0; jb < p.nJ; ++jb) l += p.rowpart[((size_t)c * p.nJ + jb) * N + u];
+        s += p1[c] * (l * invN);
+    }
+    const float v = static_cast<float>(s);
+    reinterpret_cast<float *>(p.xs + (size_t)(nc + 1) * N)[u] = v;
+    if (p.tr.stride > 0) {
+        // the slot k_ahp_select claims for this step (it advances the counter)
+        const int cnt = p.tr.counter[p.inst];
+        if (cnt % p.tr.stride == 0 && cnt / p.tr.stride < p.tr.cap)
+            p.tr.scores[static_cast<size_t>(cnt / p.tr.stride) * N + u] = v;
+    }
+}
+
+// AHP step, last stage: selection and commit on the global priorities.
 template <int BS>
 __global__ __launch_bounds__(BS) void k_ahp_select(Params p) {
     extern __shared__ __align__(16) char dsm[];
@@ -247,40 +294,11 @@ __global__ __launch_bounds__(BS) void k_ahp_select(Params p) {
     const Topo &t = p.t;
     const int N = t.N, nc = p.m.nc;
     const ReqView rv = plain_view(p);
-    if (threadIdx.x == 0) {
-        double colsum[kMaxCrit];
-        for (int b = 0; b < nc; ++b) {
-            colsum[b] = 0.0;
-            for (int a = 0; a < nc; ++a) colsum[b] += static_cast<double>(p.m.w[a]) / p.m.w[b];
-        }
-        for (int a = 0; a < nc; ++a) {
-            double s = 0.0;
-            for (int b = 0; b < nc; ++b) s += (static_cast<double>(p.m.w[a]) / p.m.w[b]) / colsum[b];
-            reinterpret_cast<float *>(sm.capP)[a] = static_cast<float>(s / nc);   // P1, in a spare slot
-        }
-        sm.misc[M_TRACE] = trace_slot(p.tr, p.inst, p.b.rid[p.s.r], p.s.i);
-    }
+    if (threadIdx.x == 0) trace_slot(p.tr, p.inst, p.b.rid[p.s.r], p.s.i);   // scores written by k_ahp_pg
     load_peers<BS, false>(t, p.st, rv, sm, p.s.P);
-    double p1[kMaxCrit];
-#pragma unroll
-    for (int c = 0; c < kMaxCrit; ++c) p1[c] = c < nc ? reinterpret_cast<const float *>(sm.capP)[c] : 0.0;
-    const double invN = 1.0 / N;
-    auto pg = [&](int u) -> float {
-        double s = 0.0;
-#pragma unroll
-        for (int c = 0; c < kMaxCrit; ++c) {
-            if (c >= nc) break;
-            double l = 0.0;
-            for (int jb = 0; jb < p.nJ; ++jb) l += p.rowpart[((size_t)c * p.nJ + jb) * N + u];
-            s += p1[c] * (l * invN);
-        }
-        return static_cast<float>(s);
-    };
-    const int slot = sm.misc[M_TRACE];
-    if (slot >= 0)
-        for (int u = threadIdx.x; u < N; u += BS) p.tr.scores[(size_t)slot * N + u] = pg(u);
+    const float *pg = reinterpret_cast<const float *>(p.xs + (size_t)(nc + 1) * N);
     select_commit<BS, 1>(t, p.st, p.b, sm, p.xs + (size_t)nc * N, p.s, rv,
-                      [&](int u) { return score_key(pg(u), u); });
+                      [&](int u) { return score_key(pg[u], u); });
 }
 
 // ---------------------------------------------------------------- batched form

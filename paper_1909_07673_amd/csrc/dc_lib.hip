@@ -369,8 +369,9 @@ void launch_plain_step(dc_ctx *ctx, const Params &p) {
         hipLaunchKernelGGL((k_criteria_plain<BS>), dim3(1), dim3(BS), ctx->lds_plain, ctx->stream, p);
         hipLaunchKernelGGL(k_ahp_colsum, dim3(bx, ctx->nI, ctx->m.nc), dim3(kAhpBlock), 0, ctx->stream, p);
         hipLaunchKernelGGL(k_ahp_rowsum, dim3(bx, ctx->nJ, ctx->m.nc), dim3(kAhpBlock), 0, ctx->stream, p);
+        hipLaunchKernelGGL(k_ahp_pg, dim3(bx), dim3(kAhpBlock), 0, ctx->stream, p);
         hipLaunchKernelGGL((k_ahp_select<BS>), dim3(1), dim3(BS), ctx->lds_select, ctx->stream, p);
-        ctx->last_launches += 4;
+        ctx->last_launches += 5;
     }
 }
 
