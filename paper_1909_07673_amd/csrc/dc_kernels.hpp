@@ -97,7 +97,7 @@ __global__ __launch_bounds__(BS) void k_topsis_plain(Params p) {
     stage_in<BS>(ls, p.st.cpu, 6 * N);        // the six arrays are contiguous
     // (the barrier at the end of load_peers orders these writes before any read)
     const State st{ls, ls + N, ls + 2 * N, ls + 3 * N, ls + 4 * N, ls + 5 * N};
-    topsis_step<BS>(p.t, st, p.m, p.b, sm, xs, p.pc_cap, p.tr, p.inst, p.s, rv);
+    topsis_step<BS, host_group(BS), true>(p.t, st, p.m, p.b, sm, xs, p.pc_cap, p.tr, p.inst, p.s, rv);
     __syncthreads();
     stage_out<BS>(p.st.cpu, ls, 6 * N);
 }
@@ -347,7 +347,7 @@ __global__ __launch_bounds__(BS) void k_topsis_batched(Params p) {
             const StepIn s{r, i, n, g0, g0 + i, pb + q0, rq_poff[i + 1] - q0, rq_cpu[i], rq_ram[i]};
             const ReqView rv{rq_pj + q0, rq_pbw + q0, rq_host, rq_host};
             // one server per thread at 1024 threads keeps the loop in registers
-            if (!topsis_step<BS, BS >= 1024 ? 1 : host_group(BS)>(p.t, st, p.m, p.b, sm, xs, p.pc_cap, p.tr, inst,
+            if (!topsis_step<BS, BS >= 1024 ? 1 : host_group(BS), true>(p.t, st, p.m, p.b, sm, xs, p.pc_cap, p.tr, inst,
                                                                   s, rv))
                 break;
         }

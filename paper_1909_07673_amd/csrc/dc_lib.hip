@@ -12,7 +12,6 @@
 #include <cstdio>
 #include <cstring>
 #include <chrono>
-#include <deque>
 #include <map>
 #include <memory>
 #include <thread>
@@ -31,13 +30,15 @@ struct DevBatch {
     Batch view{};
     std::vector<int64_t> ids;      // request id per batch request
     std::vector<int> inst, coff, poff, pj, pbw, cpu, ram, iroff;
-    std::vector<int> host, code, status, failat;
+    std::vector<int> host, status, failat;
     std::vector<float> score;
     std::vector<long long> tsb, tse;
     hipGraphExec_t gexec = nullptr;    // batched form: captured launch of this batch
     int gbs = 0;                       // workgroup size it was captured with
+    int *pinned = nullptr;             // pinned host copy of the outputs, route codes left out
     ~DevBatch() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (pinned) (void)hipHostFree(pinned);
     }
 };
 
@@ -136,7 +137,8 @@ struct dc_ctx {
     std::vector<int64_t> pend_ids;
     std::unordered_map<int64_t, ReqLoc> loc;
     int64_t next_id = 0;
-    std::deque<dc_result> ready;
+    std::vector<dc_result> ready;  // decided results not yet handed out, from ready_head on
+    size_t ready_head = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     float last_ms = 0.f;
     int64_t last_launches = 0, last_steps = 0;
@@ -455,40 +457,52 @@ int run_batched(dc_ctx *ctx, DevBatch &b, int bs) {
     return DC_OK;
 }
 
+// Copies the outputs back through a pinned buffer: the servers, then
+// everything after the route codes (failed_at, status, scores, timestamps).
+// The route codes stay on the device; dc_get_paths fetches the few it needs.
 int collect(dc_ctx *ctx, DevBatch &b) {
-    std::vector<int> out(b.out_ints);
-    HIPCHK(hipMemcpyAsync(out.data(), b.dmem + b.in_ints, b.out_ints * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    const int *dout = b.dmem + b.in_ints;
+    const size_t tail0 = (size_t)b.Ct + b.Pt, tail = b.out_ints - tail0;
+    if (!b.pinned) HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&b.pinned), (b.Ct + tail) * sizeof(int), 0));
+    int *out = b.pinned;
+    HIPCHK(hipMemcpyAsync(out, dout, (size_t)b.Ct * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(out + b.Ct, dout + tail0, tail * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
-    b.host.assign(out.begin(), out.begin() + b.Ct);
-    b.code.assign(out.begin() + b.Ct, out.begin() + b.Ct + b.Pt);
-    b.failat.assign(out.begin() + b.Ct + b.Pt, out.begin() + b.Ct + b.Pt + b.R);
-    b.status.assign(out.begin() + b.Ct + b.Pt + b.R, out.begin() + b.Ct + b.Pt + 2 * b.R);
+    const int *t0 = out + b.Ct;                        // output offset tail0 maps here
+    b.host.assign(out, out + b.Ct);
+    b.failat.assign(t0, t0 + b.R);
+    b.status.assign(t0 + b.R, t0 + 2 * b.R);
     b.score.resize(b.Ct);
-    std::memcpy(b.score.data(), out.data() + b.Ct + b.Pt + 2 * b.R, sizeof(float) * b.Ct);
+    std::memcpy(b.score.data(), t0 + 2 * b.R, sizeof(float) * b.Ct);
     b.tsb.resize(b.R);
     b.tse.resize(b.R);
     const long long *ts = reinterpret_cast<const long long *>(b.view.tsb);
-    const size_t o_ts = (size_t)(reinterpret_cast<const int *>(ts) - (b.dmem + b.in_ints));
-    std::memcpy(b.tsb.data(), out.data() + o_ts, sizeof(long long) * b.R);
-    std::memcpy(b.tse.data(), out.data() + o_ts + 2 * (size_t)b.R, sizeof(long long) * b.R);
+    const size_t o_ts = (size_t)(reinterpret_cast<const int *>(ts) - dout) - tail0;
+    std::memcpy(b.tsb.data(), t0 + o_ts, sizeof(long long) * b.R);
+    std::memcpy(b.tse.data(), t0 + o_ts + 2 * (size_t)b.R, sizeof(long long) * b.R);
     // results in request id order
     std::vector<int> order(b.R);
     for (int r = 0; r < b.R; ++r) order[r] = r;
     std::sort(order.begin(), order.end(), [&](int a, int c) { return b.ids[a] < b.ids[c]; });
-    for (int r : order) {
-        dc_result res;
-        std::memset(&res, 0, sizeof res);
+    const size_t at = ctx->ready.size();
+    ctx->ready.resize(at + order.size());
+    for (size_t k = 0; k < order.size(); ++k) {
+        const int r = order[k];
+        dc_result &res = ctx->ready[at + k];
         res.req_id = b.ids[r];
         res.instance = b.inst[r];
         res.status = b.status[r];
         res.n = b.coff[r + 1] - b.coff[r];
         res.failed_at = b.status[r] ? -1 : b.failat[r];
-        for (int i = 0; i < DC_MAX_CONTAINERS; ++i) res.host[i] = -1;
-        for (int i = 0; i < res.n; ++i) {
-            res.host[i] = b.host[b.coff[r] + i];
-            res.score[i] = b.score[b.coff[r] + i];
-        }
-        ctx->ready.push_back(res);
+        // a rejected request places nothing (its attempt stays readable
+        // through dc_get_attempt)
+        if (res.status)
+            std::memcpy(res.host, b.host.data() + b.coff[r], sizeof(int32_t) * res.n);
+        else
+            std::fill(res.host, res.host + res.n, -1);
+        std::memcpy(res.score, b.score.data() + b.coff[r], sizeof(float) * res.n);
+        std::fill(res.host + res.n, res.host + DC_MAX_CONTAINERS, -1);
+        std::fill(res.score + res.n, res.score + DC_MAX_CONTAINERS, 0.f);
     }
     return DC_OK;
 }
@@ -944,9 +958,13 @@ int dc_schedule(dc_ctx *ctx, int32_t max_results, dc_result *out, int32_t *n_out
         ctx->queued.clear();
     }
     int k = 0;
-    while (k < max_results && !ctx->ready.empty()) {
-        out[k++] = ctx->ready.front();
-        ctx->ready.pop_front();
+    const size_t avail = ctx->ready.size() - ctx->ready_head;
+    k = (int)std::min<size_t>((size_t)max_results, avail);
+    if (k > 0) std::memcpy(out, ctx->ready.data() + ctx->ready_head, sizeof(dc_result) * (size_t)k);
+    ctx->ready_head += (size_t)k;
+    if (ctx->ready_head == ctx->ready.size()) {
+        ctx->ready.clear();
+        ctx->ready_head = 0;
     }
     if (n_out) *n_out = k;
     return DC_OK;
@@ -1000,14 +1018,20 @@ int dc_get_paths(dc_ctx *ctx, int64_t req_id, int32_t cap, int32_t *link_ids, in
     const int r = it->second.r;
     if ((int)b.status.size() <= r || b.status[r] != 1) return DC_ENOENT;
     const int g0 = b.coff[r], g1 = b.coff[r + 1];
+    const int x0 = b.poff[g0], nx = b.poff[g1] - x0;
+    std::vector<int> code(std::max(nx, 1));
+    if (nx > 0) {
+        HIPCHK(hipMemcpyAsync(code.data(), b.view.code + x0, nx * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
     int q = 0;
     for (int g = g0; g < g1; ++g)
         for (int x = b.poff[g]; x < b.poff[g + 1]; ++x, ++q) {
             if (q >= cap) continue;
             int *dst = link_ids + 6 * (size_t)q;
             for (int l = 0; l < 6; ++l) dst[l] = -1;
-            const int u = b.host[g], v = b.host[g0 + b.pj[x]];
-            if (u != v && b.code[x] >= 0) host_path_links(ctx->t, u, v, b.code[x], dst);
+            const int u = b.host[g], v = b.host[g0 + b.pj[x]], c = code[x - x0];
+            if (u != v && c >= 0) host_path_links(ctx->t, u, v, c, dst);
         }
     if (n) *n = q;
     return DC_OK;
@@ -1084,6 +1108,8 @@ int dc_rewind(dc_ctx *ctx) {
         for (int64_t id : ctx->batches[bi]->ids) ctx->loc[id].released = false;
     }
     ctx->ready.clear();
+    ctx->ready_head = 0;
+    ctx->ready_head = 0;
     return DC_OK;
 }
 

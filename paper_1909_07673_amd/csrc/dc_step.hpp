@@ -666,6 +666,55 @@ __device__ __forceinline__ float topsis_close(int nc, Get get, const float *q, c
     return den > 0.f ? fminf(dm * __builtin_amdgcn_rcpf(den), 1.0f) : 0.f;
 }
 
+// Column statistics when the criteria rows sit in LDS: wave c reduces
+// column c over all servers (exact 64-bit sum of squares as three 17-bit
+// chunks, maximum, minimum) and its lane 0 turns them into the scoring
+// factors q_c = w_c^2 / sum x^2, A+_c and A-_c, kept as floats in the wst
+// slots; every thread reads them after the barrier.  Same values as the
+// per-wave path of criteria_stage + finish_stats, with 5 wave reductions per
+// criterion instead of 5 per criterion in every wave.
+template <int BS>
+__device__ __forceinline__ void column_factors_lds(const Smem &sm, const Method &m, const int *xs, int N, float *q,
+                                                   float *ap, float *am) {
+    constexpr int NW = BS / kWave;
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    float *f = reinterpret_cast<float *>(sm.wst);
+    for (int c = wid; c < m.nc; c += NW) {
+        const int *col = xs + static_cast<size_t>(c) * N;
+        unsigned long long s2 = 0;
+        int hi = -kBig - 1, lo = kBig;
+#pragma unroll 8
+        for (int u = lane; u < N; u += kWave) {
+            const int x = col[u];
+            s2 += static_cast<unsigned long long>(static_cast<unsigned>(x)) * static_cast<unsigned>(x);
+            hi = max(hi, x);
+            lo = min(lo, x);
+        }
+        const unsigned c0 = static_cast<unsigned>(wave_sum(static_cast<int>(s2 & 0x1ffffu)));
+        const unsigned c1 = static_cast<unsigned>(wave_sum(static_cast<int>((s2 >> 17) & 0x1ffffu)));
+        const unsigned c2 = static_cast<unsigned>(wave_sum(static_cast<int>(s2 >> 34)));
+        hi = wave_max(hi);
+        lo = wave_min(lo);
+        if (lane == 0) {
+            const unsigned long long a = static_cast<unsigned long long>(c0) +
+                                         (static_cast<unsigned long long>(c1) << 17) +
+                                         (static_cast<unsigned long long>(c2) << 34);
+            f[c] = a ? (m.w[c] * m.w[c]) / static_cast<float>(a) : 0.0f;
+            f[kMaxCrit + c] = static_cast<float>(m.cost[c] ? lo : hi);
+            f[2 * kMaxCrit + c] = static_cast<float>(m.cost[c] ? hi : lo);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < kMaxCrit; ++c) {
+        q[c] = ap[c] = am[c] = 0.f;
+        if (c >= m.nc) continue;
+        q[c] = f[c];
+        ap[c] = f[kMaxCrit + c];
+        am[c] = f[2 * kMaxCrit + c];
+    }
+}
+
 __device__ __forceinline__ unsigned long long score_key(float s, int u) {
     return (static_cast<unsigned long long>(__float_as_uint(s) + 1u) << 32) | static_cast<unsigned>(~u);
 }
@@ -758,28 +807,34 @@ __device__ bool select_commit(const Topo &t, const State &st, const Batch &b, co
 // raw units (swapped for cost criteria); Rank = Ed- / (Ed+ + Ed-), 0 when
 // both are 0.  Column statistics are exact integer reductions.  Returns
 // false when the request was rejected at this container.
-template <int BS, int G = host_group(BS)>
+// XS_LDS: the criteria rows xs are in LDS, so the column statistics are
+// taken from them afterwards by one wave per criterion.
+template <int BS, int G = host_group(BS), bool XS_LDS = false>
 __device__ bool topsis_step(const Topo &t, const State &st, const Method &m, const Batch &b, const Smem &sm,
                             int *xs, int pc_cap, const Trace &tr, int inst, const StepIn &s, const ReqView &rv) {
     if (s.i == 0 && threadIdx.x == 0) b.tsb[s.r] = dev_clock();
     if (threadIdx.x == 0) sm.misc[M_TRACE] = tr.stride > 0 ? trace_slot(tr, inst, b.rid[s.r], s.i) : -1;
     load_peers<BS, true>(t, st, rv, sm, s.P);
     const int nc = m.nc, N = t.N;
-    criteria_stage<BS, true, G>(t, st, m, sm, xs, s.cpu, s.ram, s.P, pc_cap);
+    criteria_stage<BS, !XS_LDS, G>(t, st, m, sm, xs, s.cpu, s.ram, s.P, pc_cap);
     __syncthreads();
 
-    unsigned long long s2[kMaxCrit];
-    int mx[kMaxCrit], mn[kMaxCrit];
-    finish_stats<BS>(sm, nc, s2, mx, mn);
     float q[kMaxCrit], ap[kMaxCrit], am[kMaxCrit];
+    if (XS_LDS) {
+        column_factors_lds<BS>(sm, m, xs, N, q, ap, am);
+    } else {
+        unsigned long long s2[kMaxCrit];
+        int mx[kMaxCrit], mn[kMaxCrit];
+        finish_stats<BS>(sm, nc, s2, mx, mn);
 #pragma unroll
-    for (int c = 0; c < kMaxCrit; ++c) {
-        q[c] = ap[c] = am[c] = 0.f;
-        if (c >= nc) continue;
-        const unsigned long long a = s2[c];
-        q[c] = a ? (m.w[c] * m.w[c]) / static_cast<float>(a) : 0.0f;
-        ap[c] = static_cast<float>(m.cost[c] ? mn[c] : mx[c]);
-        am[c] = static_cast<float>(m.cost[c] ? mx[c] : mn[c]);
+        for (int c = 0; c < kMaxCrit; ++c) {
+            q[c] = ap[c] = am[c] = 0.f;
+            if (c >= nc) continue;
+            const unsigned long long a = s2[c];
+            q[c] = a ? (m.w[c] * m.w[c]) / static_cast<float>(a) : 0.0f;
+            ap[c] = static_cast<float>(m.cost[c] ? mn[c] : mx[c]);
+            am[c] = static_cast<float>(m.cost[c] ? mx[c] : mn[c]);
+        }
     }
     auto closeness = [&](int u) -> float {
         return topsis_close(nc, [&](int c) { return xs[c * N + u]; }, q, ap, am);

@@ -328,3 +328,27 @@ def test_batched_graph_replays_match_direct_launches():
         np.testing.assert_array_equal(sa, sb)
     for a, sa in direct[1:]:
         assert a.tobytes() == direct[0][0].tobytes()
+
+
+@pytest.mark.parametrize("mode", [dc.DC_MODE_PLAIN, dc.DC_MODE_BATCHED, dc.DC_MODE_SERVING])
+def test_rejected_results_place_nothing(mode):
+    """A rejected request's result holds -1 for every container and names
+    the first container with no server; its attempt stays readable; an
+    accepted one holds a server for every container."""
+    insts, reqs = make_config("plain", seed=8, n_req=300)
+    s = dc.Scheduler(insts, mode=mode)
+    ids = [s.submit(r) for r in reqs[0]]
+    res = {r.req_id: r for r in (s.drain() if mode == dc.DC_MODE_SERVING else s.schedule())}
+    assert len(res) == len(ids)
+    rejected = 0
+    for rid in ids:
+        r = res[rid]
+        if r.status:
+            assert r.failed_at == -1 and np.all(r.hosts >= 0)
+        else:
+            rejected += 1
+            assert 0 <= r.failed_at < r.n and np.all(r.hosts == -1)
+            att = s.attempt(rid)
+            assert np.all(att[: r.failed_at] >= 0) and np.all(att[r.failed_at:] == -1)
+    assert rejected > 0
+    s.close()
