@@ -100,7 +100,10 @@ typedef struct dc_config {
     int32_t graph;          /* batched form: 0 = automatic (on), 1 = launch directly,
                                2 = capture each queued batch's launch in a HIP graph
                                once per workgroup size and replay it afterwards   */
-    int32_t reserved[3];
+    int32_t grid_timeout_us; /* cooperative step: longest wait at one grid barrier
+                               before the step gives up and the context reports
+                               DC_EDEVICE (0 = 100000 us)                         */
+    int32_t reserved[2];
 } dc_config;
 
 typedef struct dc_result {

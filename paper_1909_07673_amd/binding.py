@@ -33,7 +33,7 @@ class dc_config(C.Structure):
                 ("host_used", C.c_void_p), ("link_used", C.c_void_p), ("stream", C.c_void_p),
                 ("mem_budget", C.c_size_t), ("block", C.c_int32), ("trace_stride", C.c_int32),
                 ("trace_cap", C.c_int32), ("grid", C.c_int32), ("graph", C.c_int32),
-                ("reserved", C.c_int32 * 3)]
+                ("grid_timeout_us", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 class dc_result(C.Structure):
@@ -133,7 +133,7 @@ class Scheduler:
                  crit: Iterable[int] = DEFAULT_CRIT, cost: Optional[Iterable[int]] = None,
                  weight: Optional[Iterable[float]] = None, ahp_scale: int = DC_AHP_SAATY9,
                  stream=None, block: int = 0, trace_stride: int = 0, trace_cap: int = 0,
-                 mem_budget: int = 0, grid: int = 0, graph: int = 0):
+                 mem_budget: int = 0, grid: int = 0, graph: int = 0, grid_timeout_us: int = 0):
         inst0 = instances[0]
         crit = list(crit)
         cost = list(cost) if cost is not None else [0] * len(crit)
@@ -160,6 +160,7 @@ class Scheduler:
         cfg.block, cfg.trace_stride, cfg.trace_cap, cfg.mem_budget = block, trace_stride, trace_cap, mem_budget
         cfg.grid = grid
         cfg.graph = graph
+        cfg.grid_timeout_us = grid_timeout_us
         self.N, self.I, self.k = N, len(instances), inst0.k
         self.cfg = cfg
         self._ctx = C.c_void_p()

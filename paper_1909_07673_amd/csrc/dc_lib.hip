@@ -188,6 +188,7 @@ int check_config(const dc_config *c) {
     if (c->trace_stride < 0 || c->trace_cap < 0) return DC_EINVAL;
     if (c->grid < 0 || c->grid > 2) return DC_EINVAL;
     if (c->graph < 0 || c->graph > 2) return DC_EINVAL;
+    if (c->grid_timeout_us < 0) return DC_EINVAL;
     return DC_OK;
 }
 
@@ -354,8 +355,8 @@ void launch_plain_step(dc_ctx *ctx, const Params &p) {
         GridCtl g = ctx->grid;
         long long timeout = ctx->grid_timeout;
         void *args[] = {&pp, &g, &timeout};
-        const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_topsis_grid<256>),
-                                                        dim3(ctx->t.k), dim3(256), args, ctx->lds_grid, ctx->stream);
+        const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_topsis_grid<kGridBlock>),
+                                                        dim3(ctx->t.k), dim3(kGridBlock), args, ctx->lds_grid, ctx->stream);
         if (e != hipSuccess && ctx->launch_err == hipSuccess) ctx->launch_err = e;
         ctx->last_launches += 1;
         return;
@@ -529,7 +530,7 @@ int grid_init(dc_ctx *ctx) {
     ctx->lds_grid = gsmem_bytes(h, ctx->t.hh, ctx->m.nc);
     const size_t serve_lds = align4(ctx->lds_grid / sizeof(int)) * sizeof(int) + req_lds_ints() * sizeof(int);
     if (serve_lds > 159 * 1024) return DC_EINVAL;
-    if (set_lds(ctx, k_topsis_grid<256>, ctx->lds_grid) || set_lds(ctx, k_serve_grid<256>, serve_lds))
+    if (set_lds(ctx, k_topsis_grid<kGridBlock>, ctx->lds_grid) || set_lds(ctx, k_serve_grid<kGridBlock>, serve_lds))
         return DC_EDEVICE;
     ctx->use_grid = true;
     return DC_OK;
@@ -600,8 +601,8 @@ int serve_ensure_running(dc_ctx *ctx) {
         long long timeout = ctx->grid_timeout;
         void *args[] = {&p, &a, &g, &timeout};
         const size_t lds = align4(ctx->lds_grid / sizeof(int)) * sizeof(int) + req_lds_ints() * sizeof(int);
-        HIPCHK(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_serve_grid<256>), dim3(ctx->t.k),
-                                          dim3(256), args, lds, ctx->stream));
+        HIPCHK(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_serve_grid<kGridBlock>), dim3(ctx->t.k),
+                                          dim3(kGridBlock), args, lds, ctx->stream));
     } else if (sv.bs == 256) {
         hipLaunchKernelGGL((k_serve<256>), dim3(1), dim3(256), sv.lds, ctx->stream, p, a);
     } else {
@@ -887,6 +888,7 @@ int dc_create(const dc_config *cfg, dc_ctx **out) {
     }
     const bool grid_ok = cfg->method == DC_TOPSIS && cfg->mode != DC_MODE_BATCHED && I == 1;
     if (grid_ok && (cfg->grid == 2 || (cfg->grid == 0 && k >= 32))) {
+        if (cfg->grid_timeout_us > 0) c->grid_timeout = 100LL * cfg->grid_timeout_us;   // 100 MHz clock
         const int grc = grid_init(c);
         if (grc) { dc_destroy(ctx.release()); return grc; }
     }
@@ -1280,10 +1282,15 @@ int dc_last_timing(dc_ctx *ctx, float *ms, int64_t *launches, int64_t *steps) {
 
 void dc_destroy(dc_ctx *ctx) {
     if (!ctx) return;
+    if (ctx->sv && !ctx->poisoned && serve_stop(ctx) != DC_OK) ctx->poisoned = true;
+    // every kernel of this library ends on its own (bounded waits, idle exit),
+    // so waiting for the streams is safe even on a poisoned context; memory is
+    // freed only once nothing can still use it
+    bool quiet = !ctx->stream || hipStreamSynchronize(ctx->stream) == hipSuccess;
+    if (ctx->sv && ctx->sv->aux) quiet = hipStreamSynchronize(ctx->sv->aux) == hipSuccess && quiet;
     if (ctx->sv) {
-        if (!ctx->poisoned && serve_stop(ctx) != DC_OK) ctx->poisoned = true;
         Serve &sv = *ctx->sv;
-        if (!ctx->poisoned) {
+        if (quiet) {
             if (sv.cmds) (void)hipHostFree(sv.cmds);
             if (sv.comps) (void)hipHostFree(sv.comps);
             if (sv.ctrl) (void)hipHostFree(sv.ctrl);
@@ -1292,14 +1299,18 @@ void dc_destroy(dc_ctx *ctx) {
         }
         if (sv.aux) (void)hipStreamDestroy(sv.aux);
     }
-    if (!ctx->poisoned && ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    for (auto &b : ctx->batches)
-        if (b->dmem) (void)hipFree(b->dmem);
-    int *ptrs[] = {ctx->d_state, ctx->d_init, ctx->d_xs, ctx->d_colpart, ctx->d_tmeta, ctx->d_tcount, ctx->d_grid};
-    for (int *p : ptrs)
-        if (p) (void)hipFree(p);
-    if (ctx->d_rowpart) (void)hipFree(ctx->d_rowpart);
-    if (ctx->d_tscore) (void)hipFree(ctx->d_tscore);
+    if (quiet) {
+        for (auto &b : ctx->batches)
+            if (b->dmem) (void)hipFree(b->dmem);
+        int *ptrs[] = {ctx->d_state, ctx->d_init, ctx->d_xs, ctx->d_colpart, ctx->d_tmeta, ctx->d_tcount, ctx->d_grid};
+        for (int *p : ptrs)
+            if (p) (void)hipFree(p);
+        if (ctx->d_rowpart) (void)hipFree(ctx->d_rowpart);
+        if (ctx->d_tscore) (void)hipFree(ctx->d_tscore);
+    } else {
+        std::fprintf(stderr, "libdcsched: the device did not finish this context's work; its memory is left allocated\n");
+        for (auto &b : ctx->batches) b->pinned = nullptr;   // left allocated too
+    }
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);

@@ -352,3 +352,33 @@ def test_rejected_results_place_nothing(mode):
             assert np.all(att[: r.failed_at] >= 0) and np.all(att[r.failed_at:] == -1)
     assert rejected > 0
     s.close()
+
+
+@pytest.mark.parametrize("mode", [dc.DC_MODE_PLAIN, dc.DC_MODE_SERVING])
+def test_grid_barrier_timeout_is_reported(mode):
+    """The cooperative step's barrier waits are bounded: with the limit forced
+    down to 1 us from the host, the barriers give up, every workgroup leaves
+    normally, and the context reports DC_EDEVICE from then on.  A fresh
+    context on the same device then schedules the same requests correctly."""
+    insts, reqs = make_config("serving", seed=4, n_req=8)
+    s = dc.Scheduler(insts, mode=mode, grid=2, grid_timeout_us=1)
+    with pytest.raises(dc.DcError) as e:
+        if mode == dc.DC_MODE_SERVING:
+            for r in reqs[0]:
+                s.submit(r)
+            s.drain(timeout_s=30.0)
+        else:
+            for r in reqs[0]:
+                s.submit(r)
+            s.schedule()
+    assert e.value.code == dc.DC_EDEVICE
+    with pytest.raises(dc.DcError):
+        s.submit(reqs[0][0])
+    s.close()
+    a, ids, res = _run(insts, reqs, grid=2)
+    b, ids2, res2 = _run(insts, reqs, grid=1)
+    for x, y in zip(ids[0], ids2[0]):
+        assert res[x].status == res2[y].status
+        np.testing.assert_array_equal(res[x].hosts, res2[y].hosts)
+    a.close()
+    b.close()
