@@ -45,6 +45,10 @@ WORKLOADS = {
     "ahp": dict(preset="ahp", mode="plain", method="ahp",
                 text="k=32 fat-tree (8192 hosts), 500 FCFS requests of 8-64 containers, 0-70% background, AHP "
                      "(Saaty 1-9) on CPU/RAM/uplink/path-bw/hops(cost), five launches per container step"),
+    "pods": dict(preset="pods", mode="plain", method="topsis",
+                 text="k=16 fat-tree (1024 hosts), 2000 FCFS requests of 2-32 containers with up to half of each "
+                      "request's containers in pods of 2-4 (one placement per pod), 0-70% background, TOPSIS, "
+                      "plain form (one launch per pod step)"),
     "tiles": dict(preset=None, mode="tiles", method="topsis",
                   text="TOPSIS scoring + selection alone (dc_topsis_tiles) over 32,768 materialised 4 x 1024 "
                        "integer decision matrices (512 MiB, the batched shape: 256 instances x 128 steps), "
@@ -60,10 +64,27 @@ def step_count(results):
     return sum(r.n if r.status == 1 else r.failed_at + 1 for r in results)
 
 
-def step_count_array(res):
-    """Container steps in a RESULT_DTYPE record array."""
+def _pod_steps(req, status, failed_at):
+    """Steps a request took: one per pod (a container without a pod is a pod
+    of its own), in the order of each pod's first container."""
+    pod = getattr(req, "pod", None)
+    if pod is None:
+        return req.n if status == 1 else failed_at + 1
+    seen, unit = {}, []
+    for i, p in enumerate(pod):
+        key = ("p", int(p)) if p >= 0 else ("c", i)
+        seen.setdefault(key, len(seen))
+        unit.append(seen[key])
+    return len(seen) if status == 1 else unit[failed_at] + 1
+
+
+def step_count_array(res, reqs=None):
+    """Scoring steps in a RESULT_DTYPE record array (one per container, or
+    one per pod when the requests, in result order, carry pods)."""
     import numpy as np
-    return int(np.where(res["status"] == 1, res["n"], res["failed_at"] + 1).sum())
+    if reqs is None:
+        return int(np.where(res["status"] == 1, res["n"], res["failed_at"] + 1).sum())
+    return sum(_pod_steps(q, int(r["status"]), int(r["failed_at"])) for q, r in zip(reqs, res))
 
 
 def cpu_baseline(insts, reqs, budget_s, meth):
@@ -75,14 +96,14 @@ def cpu_baseline(insts, reqs, budget_s, meth):
     o = oracle.Oracle(insts[0], meth)
     for req in reqs[0]:
         res = o.run_request(req)
-        steps += req.n if res["status"] == 1 else res["failed_at"] + 1
+        steps += _pod_steps(req, res["status"], res["failed_at"])
         n_req += 1
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
     N = insts[0].n_hosts
     return dict(value=steps * N / dt, unit="host-scores/s", cores=1, kind="oracle",
-                sample=f"first {n_req} requests ({steps} container steps) of the same workload on one host "
+                sample=f"first {n_req} requests ({steps} scoring steps) of the same workload on one host "
                        f"thread, {dt:.1f} s")
 
 
@@ -132,10 +153,12 @@ def run_batch(args, wl):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     assert len(results) == len(buf), "every queued request is decided in a step"
-    steps = step_count_array(results)
-    per_inst = np.bincount(results["instance"], weights=np.where(results["status"] == 1, results["n"],
-                                                                  results["failed_at"] + 1),
-                           minlength=len(insts))
+    flat = [q for rl in reqs for q in rl]       # submission order = result (request id) order
+    with_pods = any(getattr(q, "pod", None) is not None for q in flat)
+    steps = step_count_array(results, flat if with_pods else None)
+    per_inst = np.bincount(results["instance"], weights=[
+        _pod_steps(q, int(r["status"]), int(r["failed_at"])) for q, r in zip(flat, results)],
+        minlength=len(insts))
     hs = steps * N
     value = hs * args.steps / wall
     lat = s.latency_us()

@@ -111,7 +111,8 @@ typedef struct dc_result {
     int32_t instance;
     int32_t status;         /* 1 accepted, 0 rejected                               */
     int32_t n;              /* containers                                           */
-    int32_t failed_at;      /* first container with no server (rejected), else -1   */
+    int32_t failed_at;      /* rejected: first container of the first pod with no
+                               server; accepted: -1                                 */
     int32_t host[DC_MAX_CONTAINERS];  /* M_c; -1 when rejected                     */
     float score[DC_MAX_CONTAINERS];   /* score of the chosen server                */
 } dc_result;
@@ -125,8 +126,16 @@ int dc_create(const dc_config *cfg, dc_ctx **out);
 /* Queue one tenant request for data center `instance` (section II-A).
  * cpu[n], ram[n]: container demands (>= 0).  edges[m][3]: (i, j, bw) with
  * i != j, 0 <= i, j < n, bw > 0, each unordered pair at most once.
- * pod: reserved, must be NULL.  The request id is returned in *req_id; ids
- * grow in submission order, which is the FCFS order.  n must be 1..64. */
+ * pod: NULL, or pod[n] with pod[i] >= 0 naming container i's pod (equal
+ * ids: same pod) and pod[i] < 0 for a container without one.  Containers of
+ * a pod share one server (Eq. (8)): the pod is placed as one unit asking for
+ * the summed CPU and RAM of its containers, pods in the order of their first
+ * container; traffic inside a pod uses no link, and the links between two
+ * pods are routed together, with their summed demand, on one widest path
+ * between the two servers.  Without pods every container is its own pod.
+ * Summed demands must stay within 2^22 (DC_EINVAL otherwise).  The request
+ * id is returned in *req_id; ids grow in submission order, which is the
+ * FCFS order.  n must be 1..64. */
 int dc_submit_request(dc_ctx *ctx, int32_t instance, int32_t n, const int32_t *cpu,
                       const int32_t *ram, int32_t m, const int32_t *edges,
                       const int32_t *pod, int64_t *req_id);
@@ -154,14 +163,16 @@ int dc_schedule(dc_ctx *ctx, int32_t max_results, dc_result *out, int32_t *n_out
 int dc_release(dc_ctx *ctx, int64_t req_id);
 
 /* Links of an accepted request's routed pairs (M_ec): 6 link ids per
- * container pair, in container order then peer order, -1 padded (a
- * co-located pair uses no link).  Link id = level*N + index. *n receives
- * the number of pairs; at most cap pairs are written. */
+ * routed pod pair (a container pair without pods), in the order the pods
+ * were placed, then ascending earlier pod, -1 padded (a co-located pair
+ * uses no link).  Link id = level*N + index. *n receives the number of
+ * pairs; at most cap pairs are written. */
 int dc_get_paths(dc_ctx *ctx, int64_t req_id, int32_t cap, int32_t *link_ids, int32_t *n);
 
 /* Servers chosen for each container of a scheduled request, including,
- * for a rejected request, the servers its containers before failed_at held
- * before the rollback (-1 from failed_at on).  Meant for lockstep checks.
+ * for a rejected request, the servers its pods placed before the failing
+ * one held before the rollback (-1 for the others).  Meant for lockstep
+ * checks.
  * *n receives the container count; at most cap entries are written. */
 int dc_get_attempt(dc_ctx *ctx, int64_t req_id, int32_t cap, int32_t *hosts, int32_t *n);
 

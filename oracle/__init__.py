@@ -79,6 +79,9 @@ def lib():
                                      f64p, i32p, f64p]
         L.or_run_request.argtypes = [P, C.POINTER(Method), C.c_int, i32p, i32p, C.c_int, P, P,
                                      P, P, P, P, P, P, P, P]
+        L.or_run_request_pods.argtypes = [P, C.POINTER(Method), C.c_int, i32p, i32p, C.c_int, P, P, P,
+                                          P, P, P, P, P, P, P, P]
+        L.or_units.argtypes = [C.c_int, P, i32p, i32p]
         L.or_release.argtypes = [P, C.c_int64]
         L.or_get_paths.argtypes = [P, C.c_int64, C.c_int, i32p, i64p]
         L.or_get_hosts.argtypes = [P, C.c_int64, i32p]
@@ -111,6 +114,17 @@ def ahp(X, w, cost=None, scale=SAATY9, return_levels=False):
     lib().or_ahp(N, Cn, X, np.ascontiguousarray(w, dtype=np.float64), c, scale, out,
                  _ptr(p1), _ptr(p2))
     return (out, p1, p2) if return_levels else out
+
+
+def units(n, pod=None):
+    """Pods of a request as the oracle numbers them: (unit[i] = pod of
+    container i, first[g] = smallest container of pod g); without pods every
+    container is its own pod."""
+    unit = np.zeros(n, dtype=np.int32)
+    first = np.zeros(n, dtype=np.int32)
+    p = None if pod is None else np.ascontiguousarray(pod, dtype=np.int32)
+    nu = lib().or_units(n, _ptr(p), unit, first)
+    return unit, first[:nu].copy()
 
 
 def saaty(p, q) -> float:
@@ -175,27 +189,39 @@ class Oracle:
 
     def run_request(self, req, follow=None, detail=False, dump=False):
         """Schedule one request.  Returns a dict with status (1 accepted,
-        0 rejected, <0 error), hosts, scores, failed_at, rec_id and, with
-        detail=True, the per-step own choice / top score / top-two gap."""
+        0 rejected, <0 error), hosts, scores (per container), failed_at,
+        rec_id and, with detail=True, the per-step own choice / top score /
+        top-two gap / chosen score (ref_host, ref_top, ref_gap,
+        step_scores).  A step places one pod (one container without pods);
+        follow and the per-step outputs are indexed by step."""
         n = req.n
         cpu = np.ascontiguousarray(req.cpu, dtype=np.int32)
         ram = np.ascontiguousarray(req.ram, dtype=np.int32)
         edges = np.ascontiguousarray(req.edges, dtype=np.int32).reshape(-1)
+        pod = getattr(req, "pod", None)
+        pod = None if pod is None else np.ascontiguousarray(pod, dtype=np.int32)
+        nu = len(units(n, pod)[1])
         fol = None if follow is None else np.ascontiguousarray(follow, dtype=np.int32)
         host = np.full(n, -1, dtype=np.int32)
         score = np.zeros(n)
-        rh = np.full(n, -1, dtype=np.int32) if detail else None
-        rt = np.zeros(n) if detail else None
-        rg = np.zeros(n) if detail else None
-        dmp = np.zeros((n, self.N)) if dump else None
+        rh = np.full(nu, -1, dtype=np.int32) if detail else None
+        rt = np.zeros(nu) if detail else None
+        rg = np.zeros(nu) if detail else None
+        dmp = np.zeros((nu, self.N)) if dump else None
         fa = np.zeros(1, dtype=np.int32)
         rid = np.zeros(1, dtype=np.int64)
-        st = lib().or_run_request(self.h, C.byref(self.m), n, cpu, ram, req.m, _ptr(edges), _ptr(fol),
-                                  _ptr(host), _ptr(score), _ptr(rh), _ptr(rt), _ptr(rg), _ptr(dmp),
-                                  _ptr(fa), _ptr(rid))
+        if pod is None:
+            st = lib().or_run_request(self.h, C.byref(self.m), n, cpu, ram, req.m, _ptr(edges), _ptr(fol),
+                                      _ptr(host), _ptr(score), _ptr(rh), _ptr(rt), _ptr(rg), _ptr(dmp),
+                                      _ptr(fa), _ptr(rid))
+        else:
+            st = lib().or_run_request_pods(self.h, C.byref(self.m), n, cpu, ram, req.m, _ptr(edges), _ptr(pod),
+                                           _ptr(fol), _ptr(host), _ptr(score), _ptr(rh), _ptr(rt), _ptr(rg),
+                                           _ptr(dmp), _ptr(fa), _ptr(rid))
         out = dict(status=st, hosts=host, scores=score, failed_at=int(fa[0]), rec_id=int(rid[0]))
         if detail:
-            out.update(ref_host=rh, ref_top=rt, ref_gap=rg)
+            unit, first = units(n, pod)
+            out.update(ref_host=rh, ref_top=rt, ref_gap=rg, step_scores=score[first])
         if dump:
             out["dump"] = dmp
         return out

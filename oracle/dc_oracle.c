@@ -603,6 +603,75 @@ int or_run_request(or_dc *d, const or_method *m, int n, const int32_t *cpu, cons
     return status;
 }
 
+/* Pods (section II-A, Eq. (8)): the containers of a pod must share one
+ * server.  The oracle schedules a request with pods as a request of pods:
+ * pod g, in the order of its first container (a container without a pod,
+ * pod[i] < 0, being a pod of its own), asks for the summed CPU and RAM of
+ * its containers, and the traffic between two pods, summed over their
+ * container pairs, is one demand between the two servers; traffic inside a
+ * pod needs no link.  or_units numbers the pods: unit[i] = pod of container
+ * i, first[g] = smallest container of pod g; returns the number of pods. */
+int or_units(int n, const int32_t *pod, int32_t *unit, int32_t *first) {
+    int nu = 0;
+    for (int i = 0; i < n; ++i) {
+        unit[i] = -1;
+        if (pod && pod[i] >= 0)
+            for (int j = 0; j < i; ++j)
+                if (pod[j] == pod[i]) { unit[i] = unit[j]; break; }
+        if (unit[i] < 0) { first[nu] = i; unit[i] = nu++; }
+    }
+    return nu;
+}
+
+/* or_run_request on the pods of a request.  follow, ref_host, ref_top,
+ * ref_gap and dump are per pod (its step); host_out and score_out are per
+ * container (the pod's server and score); *failed_at is the first container
+ * of the pod that found no server.  Returns as or_run_request, or -1 when a
+ * summed demand exceeds the capacity bound 2^22. */
+int or_run_request_pods(or_dc *d, const or_method *m, int n, const int32_t *cpu, const int32_t *ram,
+                        int ne, const int32_t *edges, const int32_t *pod, const int32_t *follow,
+                        int32_t *host_out, double *score_out, int32_t *ref_host, double *ref_top,
+                        double *ref_gap, double *dump, int32_t *failed_at, int64_t *rec_id) {
+    if (n <= 0) return -1;
+    int32_t *unit = (int32_t *)malloc(sizeof(int32_t) * n), *first = (int32_t *)malloc(sizeof(int32_t) * n);
+    int nu = or_units(n, pod, unit, first);
+    int64_t *ucpu = (int64_t *)calloc(nu, sizeof(int64_t)), *uram = (int64_t *)calloc(nu, sizeof(int64_t));
+    int64_t *ubw = (int64_t *)calloc((size_t)nu * nu, sizeof(int64_t));
+    int32_t *cu = (int32_t *)malloc(sizeof(int32_t) * nu), *ru = (int32_t *)malloc(sizeof(int32_t) * nu);
+    int32_t *ue = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)(nu * (nu - 1) / 2 + 1));
+    int32_t *hu = (int32_t *)malloc(sizeof(int32_t) * nu);
+    double *su = (double *)calloc(nu, sizeof(double));
+    for (int g = 0; g < nu; ++g) hu[g] = -1;
+    int st = -1, fu = -1, mu = 0;
+    for (int i = 0; i < n; ++i) { ucpu[unit[i]] += cpu[i]; uram[unit[i]] += ram[i]; }
+    for (int e = 0; e < ne; ++e) {
+        int a = edges[3 * e], b = edges[3 * e + 1];
+        if (a < 0 || b < 0 || a >= n || b >= n || a == b || edges[3 * e + 2] <= 0) goto done;
+        a = unit[a]; b = unit[b];
+        if (a == b) continue;                       /* inside a pod */
+        ubw[(size_t)a * nu + b] += edges[3 * e + 2];
+        ubw[(size_t)b * nu + a] += edges[3 * e + 2];
+    }
+    for (int g = 0; g < nu; ++g) {
+        if (ucpu[g] > (1 << 22) || uram[g] > (1 << 22)) goto done;
+        cu[g] = (int32_t)ucpu[g]; ru[g] = (int32_t)uram[g];
+        for (int h = g + 1; h < nu; ++h) {
+            int64_t w = ubw[(size_t)g * nu + h];
+            if (w > (1 << 22)) goto done;
+            if (w > 0) { ue[3 * mu] = g; ue[3 * mu + 1] = h; ue[3 * mu + 2] = (int32_t)w; mu++; }
+        }
+    }
+    st = or_run_request(d, m, nu, cu, ru, mu, ue, follow, hu, su, ref_host, ref_top, ref_gap, dump, &fu, rec_id);
+    for (int i = 0; i < n; ++i) {
+        if (host_out) host_out[i] = st == 1 ? hu[unit[i]] : -1;
+        if (score_out) score_out[i] = su[unit[i]];
+    }
+    if (failed_at) *failed_at = fu >= 0 ? first[fu] : -1;
+done:
+    free(unit); free(first); free(ucpu); free(uram); free(ubw); free(cu); free(ru); free(ue); free(hu); free(su);
+    return st;
+}
+
 /* Departure of an accepted request: every CPU, RAM and link amount it
  * holds is given back.  Returns 0, or -1 for an unknown / released id. */
 int or_release(or_dc *d, int64_t id) {

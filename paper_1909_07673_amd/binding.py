@@ -186,9 +186,12 @@ class Scheduler:
     def submit(self, req, instance: int = 0) -> int:
         cpu, ram = _i32(req.cpu), _i32(req.ram)
         edges = _i32(req.edges).reshape(-1)
+        pod = getattr(req, "pod", None)
+        pod = _i32(pod) if pod is not None else None
         rid = C.c_int64()
         _check(lib().dc_submit_request(self._ctx, instance, len(cpu), _p32(cpu), _p32(ram), len(edges) // 3,
-                                       _p32(edges) if len(edges) else None, None, C.byref(rid)),
+                                       _p32(edges) if len(edges) else None,
+                                       _p32(pod) if pod is not None else None, C.byref(rid)),
                "dc_submit_request")
         return rid.value
 

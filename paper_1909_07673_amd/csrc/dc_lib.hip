@@ -22,6 +22,77 @@ using namespace dcs;
 
 namespace {
 
+// A request as the device schedules it.  Containers of a pod share one
+// server (section II-A, Eq. (8)), so the unit of placement is the pod: one
+// unit per pod, in the order of each pod's first container (a container
+// without a pod is a pod of its own), asking for the summed CPU and RAM of
+// its containers.  The peers of unit g are the earlier units h whose
+// containers exchange traffic with g's, each with the summed demand: the two
+// pods sit on one server each, so their links share one route.  Traffic
+// inside a pod needs no network.  Without pods every container is a unit
+// and its peers are the earlier containers it talks to.
+struct Units {
+    int n = 0;                         // containers
+    std::vector<int> cpu, ram;         // per unit
+    std::vector<int> poff, pj, pbw;    // peers of each unit (CSR), ascending unit index
+    std::vector<int> unit_of;          // container -> unit
+    std::vector<int> first;            // unit -> its smallest container index
+    int nu() const { return (int)cpu.size(); }
+};
+
+// Builds the units of a validated request; DC_EINVAL when a summed demand
+// reaches past the 2^22 bound of capacities.  pod[i] >= 0 names container
+// i's pod (equal ids, same pod); pod[i] < 0 or pod == NULL: no pod.
+int build_units(int n, const int *cpu, const int *ram, int m, const int *edges, const int *pod, Units &u) {
+    constexpr long long kCap = 1LL << 22;
+    u = Units{};
+    u.n = n;
+    u.unit_of.assign(n, -1);
+    std::vector<long long> uc, ur;
+    std::map<int, int> pod_unit;
+    for (int i = 0; i < n; ++i) {
+        int g = -1;
+        if (pod && pod[i] >= 0) {
+            auto it = pod_unit.find(pod[i]);
+            if (it != pod_unit.end()) g = it->second;
+            else pod_unit[pod[i]] = g = (int)uc.size();
+        } else {
+            g = (int)uc.size();
+        }
+        if (g == (int)uc.size()) {
+            uc.push_back(0);
+            ur.push_back(0);
+            u.first.push_back(i);
+        }
+        u.unit_of[i] = g;
+        uc[g] += cpu[i];
+        ur[g] += ram[i];
+    }
+    const int nu = (int)uc.size();
+    for (int g = 0; g < nu; ++g) {
+        if (uc[g] > kCap || ur[g] > kCap) return DC_EINVAL;
+        u.cpu.push_back((int)uc[g]);
+        u.ram.push_back((int)ur[g]);
+    }
+    std::vector<long long> bw((size_t)nu * nu, 0);
+    for (int q = 0; q < m; ++q) {
+        const int a = u.unit_of[edges[3 * q]], b = u.unit_of[edges[3 * q + 1]];
+        if (a == b) continue;
+        bw[(size_t)a * nu + b] += edges[3 * q + 2];
+        bw[(size_t)b * nu + a] += edges[3 * q + 2];
+    }
+    u.poff.assign(1, 0);
+    for (int g = 0; g < nu; ++g) {
+        for (int h = 0; h < g; ++h) {
+            const long long w = bw[(size_t)g * nu + h];
+            if (w > kCap) return DC_EINVAL;
+            if (w > 0) { u.pj.push_back(h); u.pbw.push_back((int)w); }
+        }
+        u.poff.push_back((int)u.pj.size());
+    }
+    return DC_OK;
+}
+
 // One uploaded set of requests (the pending queue at a dc_schedule call).
 struct DevBatch {
     int R = 0, Ct = 0, Pt = 0, I = 0;
@@ -29,7 +100,8 @@ struct DevBatch {
     size_t in_ints = 0, out_ints = 0;
     Batch view{};
     std::vector<int64_t> ids;      // request id per batch request
-    std::vector<int> inst, coff, poff, pj, pbw, cpu, ram, iroff;
+    std::vector<int> inst, coff, poff, pj, pbw, cpu, ram, iroff;   // unit level (coff: units per request)
+    std::vector<int> cnt, cuoff, unit_of, first;                   // containers per request, their units, first containers
     std::vector<int> host, status, failat;
     std::vector<float> score;
     std::vector<long long> tsb, tse;
@@ -50,7 +122,9 @@ struct ReqLoc {
 // Serving form: one live request's slot in the device arena.
 struct ServeSlot {
     size_t off = 0, ints = 0;      // offset and size in the arena (int32 units)
-    int n = 0, P = 0;
+    int n = 0, P = 0;              // units and peer pairs as the device sees them
+    int nc = 0;                    // containers
+    std::vector<int> unit_of, first;
     int status = -1;               // -1 pending, 1 accepted, 0 rejected
     bool released = false;
     std::vector<int> hosts;        // attempt record from the completion
@@ -132,8 +206,8 @@ struct dc_ctx {
     size_t lds_plain = 0, lds_select = 0;
     std::vector<std::unique_ptr<DevBatch>> batches;
     std::vector<int> queued;       // batches uploaded and waiting to run
-    std::vector<int> pend_inst, pend_n;
-    std::vector<std::vector<int>> pend_cpu, pend_ram, pend_edges;
+    std::vector<int> pend_inst;
+    std::vector<Units> pend_units;
     std::vector<int64_t> pend_ids;
     std::unordered_map<int64_t, ReqLoc> loc;
     int64_t next_id = 0;
@@ -270,26 +344,25 @@ int upload_pending(dc_ctx *ctx) {
     b.coff.assign(1, 0);
     b.poff.assign(1, 0);
     b.iroff.assign(ctx->I + 1, 0);
+    b.cuoff.assign(1, 0);
     for (int idx : order) {
-        const int n = ctx->pend_n[idx];
-        const std::vector<int> &e = ctx->pend_edges[idx];
+        const Units &U = ctx->pend_units[idx];
         b.ids.push_back(ctx->pend_ids[idx]);
         b.inst.push_back(ctx->pend_inst[idx]);
         b.iroff[ctx->pend_inst[idx] + 1]++;
-        // peers of container i: edges (i, j) with j < i, ascending j
-        std::vector<int> bwm((size_t)n * n, 0);
-        for (size_t q = 0; q + 2 < e.size(); q += 3) {
-            bwm[(size_t)e[q] * n + e[q + 1]] = e[q + 2];
-            bwm[(size_t)e[q + 1] * n + e[q]] = e[q + 2];
+        const int pbase = (int)b.pj.size();
+        for (int g = 0; g < U.nu(); ++g) {
+            b.cpu.push_back(U.cpu[g]);
+            b.ram.push_back(U.ram[g]);
+            b.first.push_back(U.first[g]);
+            b.poff.push_back(pbase + U.poff[g + 1]);
         }
-        for (int i = 0; i < n; ++i) {
-            b.cpu.push_back(ctx->pend_cpu[idx][i]);
-            b.ram.push_back(ctx->pend_ram[idx][i]);
-            for (int j = 0; j < i; ++j)
-                if (bwm[(size_t)i * n + j]) { b.pj.push_back(j); b.pbw.push_back(bwm[(size_t)i * n + j]); }
-            b.poff.push_back((int)b.pj.size());
-        }
+        b.pj.insert(b.pj.end(), U.pj.begin(), U.pj.end());
+        b.pbw.insert(b.pbw.end(), U.pbw.begin(), U.pbw.end());
         b.coff.push_back((int)b.cpu.size());
+        b.cnt.push_back(U.n);
+        b.unit_of.insert(b.unit_of.end(), U.unit_of.begin(), U.unit_of.end());
+        b.cuoff.push_back((int)b.unit_of.size());
     }
     for (int i = 0; i < ctx->I; ++i) b.iroff[i + 1] += b.iroff[i];
     b.Ct = (int)b.cpu.size();
@@ -343,8 +416,7 @@ int upload_pending(dc_ctx *ctx) {
     for (int r = 0; r < b.R; ++r) ctx->loc[b.ids[r]] = ReqLoc{bi, r, false};
     ctx->batches.push_back(std::move(B));
     ctx->queued.push_back(bi);
-    ctx->pend_ids.clear(); ctx->pend_inst.clear(); ctx->pend_n.clear();
-    ctx->pend_cpu.clear(); ctx->pend_ram.clear(); ctx->pend_edges.clear();
+    ctx->pend_ids.clear(); ctx->pend_inst.clear(); ctx->pend_units.clear();
     return DC_OK;
 }
 
@@ -490,18 +562,19 @@ int collect(dc_ctx *ctx, DevBatch &b) {
     for (size_t k = 0; k < order.size(); ++k) {
         const int r = order[k];
         dc_result &res = ctx->ready[at + k];
+        const int g0 = b.coff[r], c0 = b.cuoff[r];
         res.req_id = b.ids[r];
         res.instance = b.inst[r];
         res.status = b.status[r];
-        res.n = b.coff[r + 1] - b.coff[r];
-        res.failed_at = b.status[r] ? -1 : b.failat[r];
-        // a rejected request places nothing (its attempt stays readable
-        // through dc_get_attempt)
-        if (res.status)
-            std::memcpy(res.host, b.host.data() + b.coff[r], sizeof(int32_t) * res.n);
-        else
-            std::fill(res.host, res.host + res.n, -1);
-        std::memcpy(res.score, b.score.data() + b.coff[r], sizeof(float) * res.n);
+        res.n = b.cnt[r];
+        res.failed_at = b.status[r] ? -1 : b.first[g0 + b.failat[r]];
+        // a container gets its pod's server and score; a rejected request
+        // places nothing (its attempt stays readable through dc_get_attempt)
+        for (int i = 0; i < res.n; ++i) {
+            const int g = g0 + b.unit_of[c0 + i];
+            res.host[i] = res.status ? b.host[g] : -1;
+            res.score[i] = b.score[g];
+        }
         std::fill(res.host + res.n, res.host + DC_MAX_CONTAINERS, -1);
         std::fill(res.score + res.n, res.score + DC_MAX_CONTAINERS, 0.f);
     }
@@ -640,18 +713,20 @@ int serve_poll(dc_ctx *ctx) {
             ServeSlot &sl = sv.slots[id];
             if (c.type == CMD_SUBMIT) {
                 sl.status = c.status;
-                sl.hosts.assign(c.host, c.host + c.n);
+                sl.hosts.resize(sl.nc);
                 dc_result res;
                 std::memset(&res, 0, sizeof res);
                 res.req_id = id;
                 res.instance = 0;
                 res.status = c.status;
-                res.n = c.n;
-                res.failed_at = c.status ? -1 : c.failat;
+                res.n = sl.nc;
+                res.failed_at = c.status ? -1 : sl.first[c.failat];
                 for (int i = 0; i < DC_MAX_CONTAINERS; ++i) res.host[i] = -1;
-                for (int i = 0; i < c.n; ++i) {
-                    res.host[i] = c.status ? c.host[i] : -1;
-                    res.score[i] = c.score[i];
+                for (int i = 0; i < sl.nc; ++i) {           // each container takes its pod's result
+                    const int g = sl.unit_of[i];
+                    sl.hosts[i] = c.host[g];
+                    res.host[i] = c.status ? c.host[g] : -1;
+                    res.score[i] = c.score[g];
                 }
                 ctx->ready.push_back(res);
                 sv.service_us.emplace_back(id, (float)((c.t_decide - c.t_admit) / 100.0));
@@ -665,22 +740,13 @@ int serve_poll(dc_ctx *ctx) {
     return serve_ensure_running(ctx);
 }
 
-int serve_submit(dc_ctx *ctx, int n, const int *cpu, const int *ram, int m, const int *edges, int64_t *req_id) {
+int serve_submit(dc_ctx *ctx, Units &U, int64_t *req_id) {
     Serve &sv = *ctx->sv;
     int rc = serve_poll(ctx);
     if (rc) return rc;
-    // peers of container i: edges (i, j), j < i, ascending j
-    std::vector<int> bwm((size_t)n * n, 0);
-    for (int q = 0; q < m; ++q) {
-        bwm[(size_t)edges[3 * q] * n + edges[3 * q + 1]] = edges[3 * q + 2];
-        bwm[(size_t)edges[3 * q + 1] * n + edges[3 * q]] = edges[3 * q + 2];
-    }
-    std::vector<int> poff(1, 0), pj, pbw;
-    for (int i = 0; i < n; ++i) {
-        for (int j = 0; j < i; ++j)
-            if (bwm[(size_t)i * n + j]) { pj.push_back(j); pbw.push_back(bwm[(size_t)i * n + j]); }
-        poff.push_back((int)pj.size());
-    }
+    const int n = U.nu();
+    const std::vector<int> &poff = U.poff, &pj = U.pj, &pbw = U.pbw;
+    const int *cpu = U.cpu.data(), *ram = U.ram.data();
     const int P = (int)pj.size();
     const SlotLayout L = slot_layout(n, P);
     if (sv.host_pos - sv.comp_pos >= sv.cap) return DC_EAGAIN;
@@ -704,6 +770,9 @@ int serve_submit(dc_ctx *ctx, int n, const int *cpu, const int *ram, int m, cons
     sl.ints = (size_t)L.total;
     sl.n = n;
     sl.P = P;
+    sl.nc = U.n;
+    sl.unit_of = std::move(U.unit_of);
+    sl.first = std::move(U.first);
     sv.slots[id] = sl;
     sv.rid_to_id[rid] = id;
     serve_publish(sv, CMD_SUBMIT, n, P, off, rid);
@@ -912,7 +981,7 @@ int dc_submit_request(dc_ctx *ctx, int32_t instance, int32_t n, const int32_t *c
     if (!ctx) return DC_EINVAL;
     if (ctx->poisoned) return DC_EDEVICE;
     if (instance < 0 || instance >= ctx->I || n < 1 || n > DC_MAX_CONTAINERS || !cpu || !ram) return DC_EINVAL;
-    if (m < 0 || m > n * (n - 1) / 2 || (m > 0 && !edges) || pod) return DC_EINVAL;
+    if (m < 0 || m > n * (n - 1) / 2 || (m > 0 && !edges)) return DC_EINVAL;
     std::vector<char> seen((size_t)n * n, 0);
     for (int q = 0; q < m; ++q) {
         const int i = edges[3 * q], j = edges[3 * q + 1], bw = edges[3 * q + 2];
@@ -922,12 +991,12 @@ int dc_submit_request(dc_ctx *ctx, int32_t instance, int32_t n, const int32_t *c
     }
     for (int i = 0; i < n; ++i)
         if (cpu[i] < 0 || ram[i] < 0 || cpu[i] > (1 << 22) || ram[i] > (1 << 22)) return DC_EINVAL;
-    if (ctx->sv) return serve_submit(ctx, n, cpu, ram, m, edges, req_id);
+    Units U;
+    const int urc = build_units(n, cpu, ram, m, edges, pod, U);
+    if (urc) return urc;
+    if (ctx->sv) return serve_submit(ctx, U, req_id);
     ctx->pend_inst.push_back(instance);
-    ctx->pend_n.push_back(n);
-    ctx->pend_cpu.emplace_back(cpu, cpu + n);
-    ctx->pend_ram.emplace_back(ram, ram + n);
-    ctx->pend_edges.emplace_back(edges, edges + 3 * (size_t)m);
+    ctx->pend_units.push_back(std::move(U));
     const int64_t id = ctx->next_id++;
     ctx->pend_ids.push_back(id);
     if (req_id) *req_id = id;
@@ -1054,8 +1123,8 @@ int dc_get_attempt(dc_ctx *ctx, int64_t req_id, int32_t cap, int32_t *hosts, int
     DevBatch &b = *ctx->batches[it->second.batch];
     const int r = it->second.r;
     if ((int)b.status.size() <= r) return DC_ENOENT;
-    const int g0 = b.coff[r], cnt = b.coff[r + 1] - g0;
-    for (int i = 0; i < cnt && i < cap; ++i) hosts[i] = b.host[g0 + i];
+    const int g0 = b.coff[r], c0 = b.cuoff[r], cnt = b.cnt[r];
+    for (int i = 0; i < cnt && i < cap; ++i) hosts[i] = b.host[g0 + b.unit_of[c0 + i]];
     if (n) *n = cnt;
     return DC_OK;
 }

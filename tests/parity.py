@@ -15,11 +15,14 @@ import oracle as O
 TOL = 1e-5   # relative score tolerance for FP32 scores against FP64
 
 
-def gpu_follow(sched, rid, res):
-    """Servers the GPU gave each container; -1 from the failing step on."""
-    follow = sched.attempt(rid).copy()
+def gpu_follow(sched, rid, res, req=None):
+    """Server the GPU gave each step (a pod, or a container without pods);
+    -1 from the failing step on."""
+    att = sched.attempt(rid)
+    unit, first = O.units(len(att), getattr(req, "pod", None))
+    follow = att[first].copy()
     if res.status == 0:
-        follow[res.failed_at:] = -1
+        follow[unit[res.failed_at]:] = -1
     return follow
 
 
@@ -41,19 +44,22 @@ def check_scores(gpu, ref, tol=TOL, where=""):
 def lockstep(o, sched, ids, reqs, results, tol=TOL, trace=None, check_paths=False, state_every=False,
              instance=0, final_state=True):
     """Replays `reqs` (submitted to `sched` with ids `ids`, results keyed by
-    id) on oracle `o` in lockstep.  trace: optional dict (request id ->
-    list of (container, gpu score vector)).  state_every: compare the
+    id) on oracle `o` in lockstep, one step per pod (per container without
+    pods).  trace: optional dict (request id -> list of (step, gpu score
+    vector)).  state_every: compare the
     integer state after each request (only meaningful when the GPU has
     scheduled exactly these requests so far, one schedule call each).
     Returns statistics."""
     st = dict(requests=0, accepted=0, rejected=0, steps=0, near_tie=0, scored_steps=0, rec_ids=[])
     for pos, (rid, req) in enumerate(zip(ids, reqs)):
         g = results[rid]
-        follow = gpu_follow(sched, rid, g)
+        follow = gpu_follow(sched, rid, g, req)
+        unit, first = O.units(req.n, getattr(req, "pod", None))
         want_dump = trace is not None and rid in trace
         ref = o.run_request(req, follow=follow, detail=True, dump=want_dump)
         assert ref["status"] == g.status, f"request {pos}: oracle status {ref['status']} vs gpu {g.status}"
-        steps = g.n if g.status == 1 else g.failed_at + 1
+        assert ref["failed_at"] == g.failed_at
+        steps = len(first) if g.status == 1 else unit[g.failed_at] + 1
         for i in range(steps):
             if follow[i] < 0:
                 assert ref["ref_host"][i] < 0, f"request {pos} step {i}: oracle found a server"
@@ -64,10 +70,11 @@ def lockstep(o, sched, ids, reqs, results, tol=TOL, trace=None, check_paths=Fals
                 assert ref["ref_gap"][i] <= tol * max(abs(top), 1e-30), (
                     f"request {pos} step {i}: gpu {follow[i]} vs oracle {ref['ref_host'][i]}, "
                     f"gap {ref['ref_gap'][i]:.3e} top {top:.6f}")
-                assert ref["scores"][i] >= top - tol * max(abs(top), 1e-30)
+                assert ref["step_scores"][i] >= top - tol * max(abs(top), 1e-30)
             if g.status == 1:
-                assert abs(float(g.scores[i]) - ref["scores"][i]) <= tol * max(abs(top), 1e-30), (
-                    f"request {pos} step {i}: score {g.scores[i]} vs {ref['scores'][i]}")
+                gs = float(g.scores[first[i]])
+                assert abs(gs - ref["step_scores"][i]) <= tol * max(abs(top), 1e-30), (
+                    f"request {pos} step {i}: score {gs} vs {ref['step_scores'][i]}")
         if want_dump:
             for i, vec in trace[rid]:
                 check_scores(vec, ref["dump"][i], tol, where=f"request {pos} step {i}")

@@ -382,3 +382,61 @@ def test_grid_barrier_timeout_is_reported(mode):
         np.testing.assert_array_equal(res[x].hosts, res2[y].hosts)
     a.close()
     b.close()
+
+
+# ---------------------------------------------------------------- pods
+@pytest.mark.parametrize("method", [dc.DC_TOPSIS, dc.DC_AHP])
+def test_pods_tiny_lockstep(method):
+    """k=4 requests with pods (up to half the containers in pods of 2-4):
+    every step (one per pod) against the oracle, score vectors included."""
+    tot = dict(steps=0, accepted=0, rejected=0)
+    for seed in range(20):
+        insts, reqs = make_config("tiny_pods", seed=seed)
+        s = dc.Scheduler(insts, method=method, trace_stride=1, trace_cap=4096)
+        o = O.Oracle(insts[0], _omethod(method))
+        for req in reqs[0]:
+            rid = s.submit(req)
+            res = {r.req_id: r for r in s.schedule()}
+            st = lockstep(o, s, [rid], [req], res, trace=trace_by_request(s), check_paths=True)
+            assert st["scored_steps"] == st["steps"]
+            for k in tot:
+                tot[k] += st[k]
+        s.close()
+    assert tot["accepted"] > 50 and tot["steps"] > 100
+
+
+def test_pods_k16_plain_batched_serving():
+    """k=16 with pods: plain in lockstep with the oracle (paths and final
+    state), batched and serving bit-identical to plain."""
+    insts, reqs = make_config("pods", seed=2, n_req=250)
+    assert sum(r.pod is not None and (r.pod >= 0).any() for r in reqs[0]) > 50
+    p, pids, pres = _run(insts, reqs, trace_stride=5, trace_cap=4096)
+    o = O.Oracle(insts[0], _omethod(dc.DC_TOPSIS))
+    st = lockstep(o, p, pids[0], reqs[0], pres, trace=trace_by_request(p), check_paths=True)
+    assert st["accepted"] > 20 and st["rejected"] > 0 and st["scored_steps"] > 10
+    b, bids, bres = _run(insts, reqs, mode=dc.DC_MODE_BATCHED)
+    sv = dc.Scheduler(insts, mode=dc.DC_MODE_SERVING)
+    sids = [sv.submit(r) for r in reqs[0]]
+    sres = {r.req_id: r for r in sv.drain()}
+    for x, y, z in zip(pids[0], bids[0], sids):
+        for other in (bres[y], sres[z]):
+            assert other.status == pres[x].status and other.failed_at == pres[x].failed_at
+            np.testing.assert_array_equal(other.hosts, pres[x].hosts)
+            np.testing.assert_array_equal(other.scores.view(np.uint32), pres[x].scores.view(np.uint32))
+    np.testing.assert_array_equal(b.state(0), p.state(0))
+    np.testing.assert_array_equal(sv.state(0), p.state(0))
+    for x, z in zip(pids[0], sids):
+        if pres[x].status == 1:
+            np.testing.assert_array_equal(sv.paths(z), p.paths(x))
+    for sched in (p, b, sv):
+        sched.close()
+
+
+def test_pods_invalid():
+    insts, _ = make_config("tiny", seed=0)
+    s = dc.Scheduler(insts)
+    big = Request(np.full(4, 1 << 21, np.int32), np.ones(4, np.int32), np.zeros((0, 3), np.int32),
+                  np.zeros(4, np.int32))
+    with pytest.raises(dc.DcError):
+        s.submit(big)          # summed CPU of the pod beyond 2^22
+    s.close()

@@ -388,3 +388,124 @@ def test_invalid_requests_rejected(oracle_lib):
     dup = Request(np.array([1, 1], np.int32), np.array([1, 1], np.int32),
                   np.array([[0, 1, 5], [1, 0, 5]], np.int32))
     assert o.run_request(dup)["status"] == -1
+
+
+# ---------------------------------------------------------------- pods (Eq. (8))
+def _pods_of(n, pod):
+    """Pods in the order of their first container, computed here from the
+    definition: (unit of each container, containers of each pod)."""
+    unit, groups, seen = [], [], {}
+    for i in range(n):
+        key = ("c", i) if pod is None or pod[i] < 0 else ("p", int(pod[i]))
+        if key not in seen:
+            seen[key] = len(groups)
+            groups.append([])
+        unit.append(seen[key])
+        groups[seen[key]].append(i)
+    return unit, groups
+
+
+def test_pods_of_singletons_equal_no_pods(oracle_lib):
+    """A request whose pods all hold one container schedules exactly as the
+    same request without pods (same servers, scores, paths and state)."""
+    rng = np.random.default_rng(21)
+    inst = make_instance(6, 32, 256, 5000, 8000, 8000, background=0.5, rng=rng)
+    a, b, c = O.Oracle(inst), O.Oracle(inst), O.Oracle(inst)
+    for r in make_requests(40, rng, 2, 8):
+        n = r.n
+        ra = a.run_request(r)
+        rb = b.run_request(Request(r.cpu, r.ram, r.edges, np.full(n, -1, np.int32)))
+        rc = c.run_request(Request(r.cpu, r.ram, r.edges, np.arange(n, dtype=np.int32) * 7))
+        for x in (rb, rc):
+            assert x["status"] == ra["status"] and x["failed_at"] == ra["failed_at"]
+            np.testing.assert_array_equal(x["hosts"], ra["hosts"])
+            np.testing.assert_array_equal(x["scores"], ra["scores"])
+        if ra["status"] == 1:
+            for o2, x in ((b, rb), (c, rc)):
+                pa, pb = a.paths(ra["rec_id"]), o2.paths(x["rec_id"])
+                np.testing.assert_array_equal(pa[0], pb[0])
+    np.testing.assert_array_equal(a.state(), b.state())
+    np.testing.assert_array_equal(a.state(), c.state())
+
+
+def test_one_pod_is_one_container(oracle_lib):
+    """All containers in one pod: placed like one container with the summed
+    demand, whatever traffic they exchange (it stays on the server)."""
+    rng = np.random.default_rng(22)
+    inst = make_instance(4, 32, 256, 10000, 10000, 10000, background=0.6, rng=rng)
+    a, b = O.Oracle(inst), O.Oracle(inst)
+    for r in make_requests(30, rng, 2, 4, cpu_hi=6, ram_hi=40):
+        ra = a.run_request(Request(r.cpu, r.ram, r.edges, np.zeros(r.n, np.int32)))
+        one = Request(np.array([r.cpu.sum()], np.int32), np.array([r.ram.sum()], np.int32),
+                      np.zeros((0, 3), np.int32))
+        rb = b.run_request(one)
+        assert ra["status"] == rb["status"]
+        if ra["status"] == 1:
+            assert np.all(ra["hosts"] == rb["hosts"][0])
+            assert np.all(ra["scores"] == rb["scores"][0])
+            assert a.paths(ra["rec_id"])[0].shape[0] == 0
+        else:
+            assert ra["failed_at"] == 0
+    np.testing.assert_array_equal(a.state(), b.state())
+
+
+@pytest.mark.parametrize("kind", [O.TOPSIS, O.AHP])
+def test_pod_placements_sound(oracle_lib, kind):
+    """k=4, loaded: every accepted request with pods keeps each pod on one
+    server (Eq. (8)), fits CPU and RAM (Eq. (4)) and routes the summed
+    traffic between two pods on a path joining their servers within the
+    link residuals (Eq. (5)); a rejected one changes nothing; a request that
+    is one pod is rejected only when no server fits its summed demand."""
+    rng = np.random.default_rng(31 + kind)
+    inst = make_instance(4, 32, 256, 4000, 4000, 4000, background=0.8, rng=rng)
+    o = O.Oracle(inst, O.method(kind))
+    ends, _ = _ft_links(4)
+    n_acc = n_rej = 0
+    for t in range(80):
+        n = int(rng.integers(2, 6))
+        req = make_requests(1, rng, n, n, cpu_lo=1, cpu_hi=10, ram_lo=1, ram_hi=60, bw_lo=100,
+                            bw_hi=1500, pod_frac=1.0)[0]
+        unit, groups = _pods_of(n, req.pod)
+        before = o.state().astype(np.int64)
+        res = o.run_request(req)
+        after = o.state().astype(np.int64)
+        assert np.all(after >= 0)
+        if res["status"] != 1:
+            n_rej += 1
+            assert res["status"] == 0 and res["failed_at"] == groups[unit[res["failed_at"]]][0]
+            np.testing.assert_array_equal(after, before)
+            if len(groups) == 1:
+                fits = (before[0] >= req.cpu.sum()) & (before[1] >= req.ram.sum())
+                assert not fits.any()
+            continue
+        n_acc += 1
+        hosts = res["hosts"]
+        for g in groups:
+            assert len(set(hosts[g].tolist())) == 1          # Eq. (8)
+        use_cpu = np.bincount(hosts, weights=req.cpu, minlength=16)
+        use_ram = np.bincount(hosts, weights=req.ram, minlength=16)
+        assert np.all(use_cpu <= before[0]) and np.all(use_ram <= before[1])
+        # summed traffic between pods, expected in pod order then earlier pod
+        dem = {}
+        for a, b, bw in req.edges:
+            ua, ub = unit[a], unit[b]
+            if ua != ub:
+                key = (max(ua, ub), min(ua, ub))
+                dem[key] = dem.get(key, 0) + int(bw)
+        links, bws = o.paths(res["rec_id"])
+        keys = sorted(dem)
+        assert len(keys) == len(links)
+        link_use = np.zeros(48, np.int64)
+        for (g, h), path, bw in zip(keys, links, bws):
+            assert int(bw) == dem[(g, h)]
+            cur = ("h", int(hosts[groups[g][0]]))
+            for l in path[path >= 0]:
+                x, y = ends[l]
+                assert cur in (x, y)
+                cur = y if cur == x else x
+                link_use[l] += bw
+            assert cur == ("h", int(hosts[groups[h][0]]))
+        np.testing.assert_array_equal(after[0], before[0] - use_cpu)
+        np.testing.assert_array_equal(after[1], before[1] - use_ram)
+        np.testing.assert_array_equal(after[3:].reshape(-1), before[3:].reshape(-1) - link_use)
+    assert n_acc >= 10 and n_rej >= 5

@@ -72,11 +72,13 @@ class Instance:
 
 @dataclasses.dataclass
 class Request:
-    """A tenant request: n containers with CPU/RAM demands and undirected
-    communication edges (i, j, bw) with i < j."""
+    """A tenant request: n containers with CPU/RAM demands, undirected
+    communication edges (i, j, bw) with i < j, and optionally the pod of
+    each container (pod[i] >= 0: its pod id; -1: no pod)."""
     cpu: np.ndarray     # int32 [n]
     ram: np.ndarray     # int32 [n]
     edges: np.ndarray   # int32 [m][3]
+    pod: Optional[np.ndarray] = None   # int32 [n] or None
 
     @property
     def n(self) -> int:
@@ -140,16 +142,37 @@ def _random_connected_edges(n: int, density: float, rng: np.random.Generator,
     return out
 
 
+def _random_pods(n: int, frac: float, rng: np.random.Generator) -> np.ndarray:
+    """Up to floor(frac * n) containers (a uniform count, uniform choice)
+    grouped into pods of 2-4 containers; the others get no pod (-1)."""
+    pod = np.full(n, -1, dtype=np.int32)
+    g = int(rng.integers(0, int(frac * n) + 1))
+    if g < 2:
+        return pod
+    members = rng.permutation(n)[:g]
+    pid, at = 0, 0
+    while at < g:
+        size = int(rng.integers(2, 5))
+        if g - (at + size) == 1:        # no pod of one container
+            size += 1
+        pod[members[at:at + size]] = pid
+        pid += 1
+        at += size
+    return pod
+
+
 def make_requests(count: int, rng: np.random.Generator, n_lo: int, n_hi: int,
                   cpu_lo: int = 1, cpu_hi: int = 8, ram_lo: int = 1, ram_hi: int = 32,
-                  bw_lo: int = 100, bw_hi: int = 2000, density: float = 0.5) -> List[Request]:
+                  bw_lo: int = 100, bw_hi: int = 2000, density: float = 0.5,
+                  pod_frac: float = 0.0) -> List[Request]:
     reqs = []
     for _ in range(count):
         n = int(rng.integers(n_lo, n_hi + 1))
         cpu = rng.integers(cpu_lo, cpu_hi + 1, size=n).astype(np.int32)
         ram = rng.integers(ram_lo, ram_hi + 1, size=n).astype(np.int32)
         edges = _random_connected_edges(n, density, rng, bw_lo, bw_hi)
-        reqs.append(Request(cpu, ram, edges))
+        pod = _random_pods(n, pod_frac, rng) if pod_frac > 0 else None
+        reqs.append(Request(cpu, ram, edges, pod))
     return reqs
 
 
@@ -186,6 +209,12 @@ CONFIGS = {
                     n_req=(64, 512), n=(2, 48), instances=256),
     "serving": dict(k=48, caps=(32, 256, 40000, 100000, 100000), background=0.7,
                     n_req=None, n=(2, 64), instances=1),
+    # requests with pods: up to half of each request's containers grouped
+    # into pods of 2-4 (the share the paper's second workload uses)
+    "tiny_pods": dict(k=4, caps=(32, 256, 10000, 10000, 10000), background=0.0,
+                      n_req=(20, 20), n=(2, 6), instances=1, pod_frac=0.5),
+    "pods":    dict(k=16, caps=(32, 256, 40000, 100000, 100000), background=0.7,
+                    n_req=(2000, 2000), n=(2, 32), instances=1, pod_frac=0.5),
 }
 
 
@@ -208,7 +237,7 @@ def make_config(name: str, seed: int = 0, instances: Optional[int] = None,
         else:
             lo, hi = cfg["n_req"] if cfg["n_req"] else (100, 100)
             cnt = int(rng.integers(lo, hi + 1))
-        reqs.append(make_requests(cnt, rng, *cfg["n"]))
+        reqs.append(make_requests(cnt, rng, *cfg["n"], pod_frac=cfg.get("pod_frac", 0.0)))
         insts.append(inst)
     return insts, reqs
 
