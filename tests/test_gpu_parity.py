@@ -113,13 +113,21 @@ def test_topsis_five_criteria_with_cost():
     lockstep(o, s, ids[0], reqs[0], res, trace=trace_by_request(s), check_paths=True)
 
 
-def test_topsis_clustering_weights():
-    """Table IV 'Clustering' weights (0.17, 0.17, 0.5, 0.16)."""
-    w = (0.17, 0.17, 0.5, 0.16)
-    insts, reqs = make_config("plain", seed=6, n_req=80)
-    s, ids, res = _run(insts, reqs, weight=w, trace_stride=5, trace_cap=4096)
-    o = O.Oracle(insts[0], O.method(kind=O.TOPSIS, weight=list(w)))
-    lockstep(o, s, ids[0], reqs[0], res, trace=trace_by_request(s))
+@pytest.mark.parametrize("method", [dc.DC_TOPSIS, dc.DC_AHP])
+@pytest.mark.parametrize("w", [(0.17, 0.17, 0.5, 0.16), (0.17, 0.17, 0.16, 0.5)], ids=["clustering", "network"])
+def test_table4_weight_scenarios(method, w):
+    """Table IV 'Clustering' and 'Network' weights (CPU, RAM, fragmentation,
+    bandwidth) with TOPSIS (k=16) and AHP (k=4, every step)."""
+    if method == dc.DC_TOPSIS:
+        insts, reqs = make_config("plain", seed=6, n_req=80)
+        stride = 5
+    else:
+        insts, reqs = make_config("tiny", seed=6)
+        stride = 1
+    s, ids, res = _run(insts, reqs, method=method, weight=w, trace_stride=stride, trace_cap=4096)
+    o = O.Oracle(insts[0], O.method(kind=method, weight=list(w)))
+    st = lockstep(o, s, ids[0], reqs[0], res, trace=trace_by_request(s), check_paths=True)
+    assert st["scored_steps"] > 0
 
 
 def test_batched_matches_oracle_and_plain():
@@ -439,4 +447,70 @@ def test_pods_invalid():
                   np.zeros(4, np.int32))
     with pytest.raises(dc.DcError):
         s.submit(big)          # summed CPU of the pod beyond 2^22
+    s.close()
+
+
+def _ft_link_hops(paths):
+    return int((paths >= 0).sum())
+
+
+@pytest.mark.parametrize("wl", ["ahp", "plain", "pods"])
+def test_full_size_accounting(wl):
+    """The measured configurations at full size (AHP k=32 with 500 requests,
+    TOPSIS k=16 with 2,000 requests, with and without pods), checked by
+    properties that hold at any size: the state change equals the accepted
+    placements (CPU, RAM, placed counts per server) and their routes (link
+    usage = summed demand x hops), nothing goes negative, and releasing every
+    accepted request restores the initial state bit-exactly."""
+    insts, reqs = make_config(wl, seed=0)
+    kw = {}
+    if wl == "ahp":
+        kw = dict(method=dc.DC_AHP, crit=C5, cost=C5_COST)
+    s = dc.Scheduler(insts, **kw)
+    s0 = s.state(0).astype(np.int64)
+    ids = [s.submit(r) for r in reqs[0]]
+    res = {r.req_id: r for r in s.schedule()}
+    s1 = s.state(0).astype(np.int64)
+    assert np.all(s1 >= 0)
+    N = insts[0].n_hosts
+    cpu = np.zeros(N, np.int64)
+    ram = np.zeros(N, np.int64)
+    npl = np.zeros(N, np.int64)
+    hops_bw = 0
+    acc = []
+    for rid, req in zip(ids, reqs[0]):
+        r = res[rid]
+        if r.status != 1:
+            assert np.all(r.hosts == -1)
+            continue
+        acc.append(rid)
+        np.add.at(cpu, r.hosts, req.cpu)
+        np.add.at(ram, r.hosts, req.ram)
+        if getattr(req, "pod", None) is None:
+            np.add.at(npl, r.hosts, 1)
+        else:
+            unit, first = O.units(req.n, req.pod)
+            np.add.at(npl, r.hosts[first], 1)
+            for g in range(len(first)):
+                assert np.all(r.hosts[unit == g] == r.hosts[first[g]])
+        # demand per routed pair, in the paths' order
+        unit, first = O.units(req.n, getattr(req, "pod", None))
+        dem = {}
+        for a, b, bw in req.edges:
+            ua, ub = unit[a], unit[b]
+            if ua != ub:
+                key = (max(ua, ub), min(ua, ub))
+                dem[key] = dem.get(key, 0) + int(bw)
+        paths = s.paths(rid)
+        assert len(paths) == len(dem)
+        for key, p in zip(sorted(dem), paths):
+            hops_bw += dem[key] * _ft_link_hops(p)
+    assert len(acc) > 10
+    np.testing.assert_array_equal(s0[0] - s1[0], cpu)
+    np.testing.assert_array_equal(s0[1] - s1[1], ram)
+    np.testing.assert_array_equal(s1[2] - s0[2], npl)
+    assert int((s0[3:] - s1[3:]).sum()) == hops_bw
+    for rid in acc:
+        assert s.release(rid) == dc.DC_OK
+    np.testing.assert_array_equal(s.state(0), s0)
     s.close()
