@@ -118,22 +118,29 @@ __global__ __launch_bounds__(BS) void k_criteria_plain(Params p) {
 // q (column server): equal -> 1; p > q -> s = ratio p/q rounded half up,
 // clamped to 9 (q = 0 -> 9); p < q -> 1/s(q, p).  Returned scaled by 2520
 // (the lcm of 1..9), so every entry and every column sum is an exact
-// integer.  s = floor((2 hi + lo) / (2 lo)) is estimated with a reciprocal
-// (r_hi_lo = 1/(2 lo)) and corrected by the exact remainder.
-__device__ __forceinline__ float rcp2(float v) { return v > 0.f ? __builtin_amdgcn_rcpf(2.f * v) : __builtin_inff(); }
+// integer.
+//
+// With hi = max(p, q), lo = min(p, q), num = 2 hi + lo: s = min(9,
+// floor(num / (2 lo))).  rcp2 gives 1/(2 lo) from the hardware reciprocal
+// (within 1 ulp) scaled down by 2^-21, so num * rl lies strictly below the
+// exact quotient; its floor is then at most one below s wherever s < 11,
+// and one test of the exact remainder num - s * 2 lo (all integers below
+// 2^24) corrects it; larger quotients are clamped to 9 anyway.  lo = 0
+// makes rl = +inf: hi > 0 gives +inf, clamped to 9; hi = 0 gives NaN, which
+// max(., 0) turns into 0 and the remainder test (0 >= 0) into 1.
+__device__ __forceinline__ float rcp2(float v) {
+    return v > 0.f ? __builtin_amdgcn_rcpf(2.f * v) * (1.0f - 0x1p-21f) : __builtin_inff();
+}
 
 __device__ __forceinline__ float saaty2520(float p, float q, float rp, float rq) {
     const bool ge = p >= q;
-    const float hi = ge ? p : q, lo = ge ? q : p, rl = ge ? rq : rp;
-    const float num = fmaf(2.f, hi, lo);
-    const float two_lo = lo + lo;
-    float s = floorf(num * rl);
+    const float hi = fmaxf(p, q), lo = fminf(p, q), rl = ge ? rq : rp;
+    const float num = fmaf(2.f, hi, lo), two_lo = lo + lo;
+    float s = floorf(fmaxf(num * rl, 0.f));
     const float rem = fmaf(-s, two_lo, num);
-    s = rem < 0.f ? s - 1.f : s;
     s = rem >= two_lo ? s + 1.f : s;
     s = fminf(s, 9.f);
-    s = lo == 0.f ? (hi == 0.f ? 1.f : 9.f) : s;
-    return ge ? 2520.f * s : rintf(2520.f * __builtin_amdgcn_rcpf(s));
+    return rintf(2520.f * (ge ? s : __builtin_amdgcn_rcpf(s)));
 }
 
 // Pass A: column sums colsum_c[j] = sum_i a_c(i, j), never storing the
