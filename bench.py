@@ -49,6 +49,10 @@ WORKLOADS = {
                  text="k=16 fat-tree (1024 hosts), 2000 FCFS requests of 2-32 containers with up to half of each "
                       "request's containers in pods of 2-4 (one placement per pod), 0-70% background, TOPSIS, "
                       "plain form (one launch per pod step)"),
+    "route_end": dict(preset="plain", mode="plain", method="topsis", routing=1,
+                      text="k=16 fat-tree (1024 hosts), 2000 FCFS requests of 2-32 containers, 0-70% background, "
+                           "TOPSIS, links routed after each request's last container (one wave per pair on the "
+                           "residuals the placement left), plain form (one launch per container step)"),
     "tiles": dict(preset=None, mode="tiles", method="topsis",
                   text="TOPSIS scoring + selection alone (dc_topsis_tiles) over 32,768 materialised 4 x 1024 "
                        "integer decision matrices (512 MiB, the batched shape: 256 instances x 128 steps), "
@@ -68,6 +72,8 @@ def _pod_steps(req, status, failed_at):
     """Steps a request took: one per pod (a container without a pod is a pod
     of its own), in the order of each pod's first container."""
     pod = getattr(req, "pod", None)
+    if status == 0 and failed_at >= req.n:      # every pod placed, links did not fit
+        status = 1
     if pod is None:
         return req.n if status == 1 else failed_at + 1
     seen, unit = {}, []
@@ -130,7 +136,8 @@ def run_batch(args, wl):
         kw = dict(method=dc.DC_AHP, crit=(dc.DC_CRIT_CPU, dc.DC_CRIT_RAM, dc.DC_CRIT_UPLINK, dc.DC_CRIT_PATHBW,
                                           dc.DC_CRIT_HOPS), cost=(0, 0, 0, 0, 1))
     mode = dc.DC_MODE_BATCHED if wl["mode"] == "batched" else dc.DC_MODE_PLAIN
-    s = dc.Scheduler(insts, mode=mode, stream=stream, grid=args.grid, graph=args.graph, block=args.block, **kw)
+    s = dc.Scheduler(insts, mode=mode, stream=stream, grid=args.grid, graph=args.graph, block=args.block,
+                     routing=wl.get("routing", 0), **kw)
     for i, rl in enumerate(reqs):
         for r in rl:
             s.submit(r, instance=i)
@@ -184,7 +191,7 @@ def run_batch(args, wl):
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                            "avg_launch_us": avg_launch_s * 1e6, "launches_per_step": per_step_launches,
                            "bytes_per_launch": bytes_per_launch}
-        meth = oracle.method(kind=oracle.TOPSIS)
+        meth = oracle.method(kind=oracle.TOPSIS, route_end=bool(wl.get("routing", 0)))
         if not args.no_scoring_kernel:
             # the scoring stage alone, streaming resident matrices (HBM-bound)
             out["scoring_kernel_roofline"] = dict(

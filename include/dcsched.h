@@ -62,6 +62,7 @@ enum dc_status {
 enum dc_method { DC_TOPSIS = 0, DC_AHP = 1 };
 enum dc_ahp_scale { DC_AHP_SAATY9 = 0, DC_AHP_RATIO = 1 };
 enum dc_mode { DC_MODE_PLAIN = 0, DC_MODE_BATCHED = 1, DC_MODE_SERVING = 2 };
+enum dc_routing { DC_ROUTE_EACH = 0, DC_ROUTE_END = 1 };
 
 /* Criteria (section V): available CPU, available RAM, fragmentation flag
  * f_u (1 when u hosts a container placed by this library), path bandwidth
@@ -103,7 +104,13 @@ typedef struct dc_config {
     int32_t grid_timeout_us; /* cooperative step: longest wait at one grid barrier
                                before the step gives up and the context reports
                                DC_EDEVICE (0 = 100000 us)                         */
-    int32_t reserved[2];
+    int32_t routing;        /* 0 = each unit's links are routed when it is placed;
+                               1 = a request's links are routed after its last
+                               unit is placed (section V-D): every pair's widest
+                               path on the residuals the placement left, then all
+                               demands taken at once; a request whose demands do
+                               not fit is rejected with failed_at = n            */
+    int32_t reserved[1];
 } dc_config;
 
 typedef struct dc_result {
@@ -112,7 +119,8 @@ typedef struct dc_result {
     int32_t status;         /* 1 accepted, 0 rejected                               */
     int32_t n;              /* containers                                           */
     int32_t failed_at;      /* rejected: first container of the first pod with no
-                               server; accepted: -1                                 */
+                               server, or n when the links did not fit (routing
+                               at the end of the request); accepted: -1            */
     int32_t host[DC_MAX_CONTAINERS];  /* M_c; -1 when rejected                     */
     float score[DC_MAX_CONTAINERS];   /* score of the chosen server                */
 } dc_result;

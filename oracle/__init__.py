@@ -35,14 +35,16 @@ def build(force: bool = True) -> str:
 
 class Method(C.Structure):
     _fields_ = [("method", C.c_int32), ("ahp_scale", C.c_int32), ("ncrit", C.c_int32),
-                ("pad", C.c_int32), ("crit", C.c_int32 * 8), ("cost", C.c_int32 * 8),
+                ("route_end", C.c_int32), ("crit", C.c_int32 * 8), ("cost", C.c_int32 * 8),
                 ("weight", C.c_double * 8)]
 
 
 def method(kind=TOPSIS, crit=(CRIT_CPU, CRIT_RAM, CRIT_ACTIVE, CRIT_PATHBW), cost=None,
-           weight=None, scale=SAATY9) -> Method:
+           weight=None, scale=SAATY9, route_end=False) -> Method:
+    """route_end: route a request's links after its last pod is placed
+    (section V-D) instead of at each placement."""
     m = Method()
-    m.method, m.ahp_scale, m.ncrit = kind, scale, len(crit)
+    m.method, m.ahp_scale, m.ncrit, m.route_end = kind, scale, len(crit), int(route_end)
     cost = cost or [0] * len(crit)
     weight = weight or [1.0 / len(crit)] * len(crit)
     for c in range(len(crit)):

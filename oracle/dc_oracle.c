@@ -40,7 +40,8 @@ enum { M_TOPSIS = 0, M_AHP = 1 };
 enum { AHP_SAATY9 = 0, AHP_RATIO = 1 };
 
 typedef struct {
-    int32_t method, ahp_scale, ncrit, pad;
+    int32_t method, ahp_scale, ncrit;
+    int32_t route_end;   /* 1: links routed after the last container is placed (section V-D) */
     int32_t crit[OR_MAX_CRIT];
     int32_t cost[OR_MAX_CRIT];
     double weight[OR_MAX_CRIT];
@@ -539,11 +540,13 @@ int or_run_request(or_dc *d, const or_method *m, int n, const int32_t *cpu, cons
         qsort(order, N, sizeof(cand), cmp_cand);
         /* own choice and the runner-up among commit-successful servers */
         int top1 = -1; double s1 = 0.0, s2 = -INFINITY;
+        /* routing at the end of the request: a placement takes CPU and RAM only */
+        const int Pc = m->route_end ? 0 : P;
         for (int r = 0; r < N; ++r) {
             int u = order[r].u;
             if (!feas[u]) continue;
-            if (try_commit(d, u, cpu[i], ram[i], P, ph, pbw, tmp)) {
-                undo_commit(d, u, cpu[i], ram[i], P, tmp);
+            if (try_commit(d, u, cpu[i], ram[i], Pc, ph, pbw, tmp)) {
+                undo_commit(d, u, cpu[i], ram[i], Pc, tmp);
                 if (top1 < 0) { top1 = u; s1 = order[r].s; if (!ref_gap) break; }
                 else { s2 = order[r].s; break; }
             }
@@ -557,13 +560,42 @@ int or_run_request(or_dc *d, const or_method *m, int n, const int32_t *cpu, cons
             take = follow[i];
         }
         if (take < 0) { status = 0; fail_i = i; break; }
-        if (!try_commit(d, take, cpu[i], ram[i], P, ph, pbw, paths + (size_t)i * n)) {
+        if (!try_commit(d, take, cpu[i], ram[i], Pc, ph, pbw, paths + (size_t)i * n)) {
             status = -2; fail_i = i; break;
         }
-        npeer[i] = P;
+        npeer[i] = Pc;
         host[i] = take;
         if (host_out) host_out[i] = take;
         if (score_out) score_out[i] = score[take];
+    }
+    if (status == 1 && m->route_end) {
+        /* every pair's widest minimum-hop path on the residuals the placement
+         * left, each pair on its own; then all demands at once, and the
+         * request fits only if no link goes negative */
+        for (int i = 0; i < n; ++i) {
+            int P = 0;
+            for (int j = 0; j < i; ++j) {
+                if (!bwm[(size_t)i * n + j]) continue;
+                or_path *pp = paths + (size_t)i * n + P;
+                pp->nl = 0; pp->bw = bwm[(size_t)i * n + j];
+                if (host[j] != host[i]) {
+                    int64_t b; int32_t links[6], hops;
+                    or_widest_enum(d, host[i], host[j], &b, links, &hops);
+                    pp->nl = hops;
+                    for (int l = 0; l < hops; ++l) pp->link[l] = links[l];
+                }
+                P++;
+            }
+            npeer[i] = P;
+        }
+        int fits = 1;
+        for (int i = 0; i < n; ++i)
+            for (int p = 0; p < npeer[i]; ++p) {
+                const or_path *pp = paths + (size_t)i * n + p;
+                for (int l = 0; l < pp->nl; ++l) d->link_res[pp->link[l]] -= pp->bw;
+            }
+        for (int e = 0; e < 3 * N; ++e) if (d->link_res[e] < 0) fits = 0;
+        if (!fits) { status = 0; fail_i = n; }
     }
     if (status != 1) {
         for (int i = fail_i - 1; i >= 0; --i)
@@ -666,7 +698,7 @@ int or_run_request_pods(or_dc *d, const or_method *m, int n, const int32_t *cpu,
         if (host_out) host_out[i] = st == 1 ? hu[unit[i]] : -1;
         if (score_out) score_out[i] = su[unit[i]];
     }
-    if (failed_at) *failed_at = fu >= 0 ? first[fu] : -1;
+    if (failed_at) *failed_at = fu < 0 ? -1 : fu < nu ? first[fu] : n;   /* nu: the links did not fit */
 done:
     free(unit); free(first); free(ucpu); free(uram); free(ubw); free(cu); free(ru); free(ue); free(hu); free(su);
     return st;

@@ -17,6 +17,7 @@ DC_OK, DC_EINVAL, DC_ENOMEM, DC_EAGAIN, DC_ENOENT, DC_EDEVICE, DC_ESTATE = 0, -1
 DC_TOPSIS, DC_AHP = 0, 1
 DC_AHP_SAATY9, DC_AHP_RATIO = 0, 1
 DC_MODE_PLAIN, DC_MODE_BATCHED, DC_MODE_SERVING = 0, 1, 2
+DC_ROUTE_EACH, DC_ROUTE_END = 0, 1
 DC_CRIT_CPU, DC_CRIT_RAM, DC_CRIT_ACTIVE, DC_CRIT_PATHBW, DC_CRIT_UPLINK, DC_CRIT_HOPS = range(6)
 DC_MAX_CONTAINERS, DC_MAX_CRIT = 64, 8
 
@@ -33,7 +34,8 @@ class dc_config(C.Structure):
                 ("host_used", C.c_void_p), ("link_used", C.c_void_p), ("stream", C.c_void_p),
                 ("mem_budget", C.c_size_t), ("block", C.c_int32), ("trace_stride", C.c_int32),
                 ("trace_cap", C.c_int32), ("grid", C.c_int32), ("graph", C.c_int32),
-                ("grid_timeout_us", C.c_int32), ("reserved", C.c_int32 * 2)]
+                ("grid_timeout_us", C.c_int32), ("routing", C.c_int32),
+                ("reserved", C.c_int32 * 1)]
 
 
 class dc_result(C.Structure):
@@ -133,7 +135,8 @@ class Scheduler:
                  crit: Iterable[int] = DEFAULT_CRIT, cost: Optional[Iterable[int]] = None,
                  weight: Optional[Iterable[float]] = None, ahp_scale: int = DC_AHP_SAATY9,
                  stream=None, block: int = 0, trace_stride: int = 0, trace_cap: int = 0,
-                 mem_budget: int = 0, grid: int = 0, graph: int = 0, grid_timeout_us: int = 0):
+                 mem_budget: int = 0, grid: int = 0, graph: int = 0, grid_timeout_us: int = 0,
+                 routing: int = 0):
         inst0 = instances[0]
         crit = list(crit)
         cost = list(cost) if cost is not None else [0] * len(crit)
@@ -161,6 +164,7 @@ class Scheduler:
         cfg.grid = grid
         cfg.graph = graph
         cfg.grid_timeout_us = grid_timeout_us
+        cfg.routing = routing
         self.N, self.I, self.k = N, len(instances), inst0.k
         self.cfg = cfg
         self._ctx = C.c_void_p()

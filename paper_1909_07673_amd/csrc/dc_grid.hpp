@@ -190,7 +190,7 @@ __device__ bool grid_topsis_step(const Topo &t, const State &st, const Method &m
             outp += (rem & far & (pv != w)) ? bw : 0;
         }
         feas &= (up_u >= up_acc);
-        if (P > 0) feas &= (sm.capE[el] >= oute) & (capP_own >= outp);
+        if (P > 0 && !m.route_end) feas &= (sm.capE[el] >= oute) & (capP_own >= outp);
         xs[nc * hh + x] = feas;
 #pragma unroll
         for (int c = 0; c < kMaxCrit; ++c) {
@@ -291,9 +291,11 @@ __device__ bool grid_topsis_step(const Topo &t, const State &st, const Method &m
     auto key_of = [&](int x) -> unsigned long long {
         const int u = ubase + x;
         int f = xs[nc * hh + x];
-        f &= (dh1 < 0) | ((dh0 == dh1) & (u == dh0));
-        f &= (de1 < 0) | ((de0 == de1) & (w * h + fdiv(x, t.rh) == de0));
-        f &= (dp1 < 0) | ((dp0 == dp1) & (w == dp0));
+        if (!m.route_end) {
+            f &= (dh1 < 0) | ((dh0 == dh1) & (u == dh0));
+            f &= (de1 < 0) | ((de0 == de1) & (w * h + fdiv(x, t.rh) == de0));
+            f &= (dp1 < 0) | ((dp0 == dp1) & (w == dp0));
+        }
         if (!f) return 0ull;
         return score_key(topsis_close(nc, [&](int c) { return xs[c * hh + x]; }, q, ap, am), u);
     };
@@ -345,23 +347,34 @@ __device__ bool grid_topsis_step(const Topo &t, const State &st, const Method &m
             return false;
         }
         const int u = static_cast<int>(~static_cast<unsigned>(kb & 0xffffffffu));
-        if (w == 0 && threadIdx.x < kWave) {
-            // commit_wave reads the peer servers from LDS; its routing uses
-            // the global state
-            Smem cs;
-            cs.pk = sm.pk;
-            const bool ok = commit_wave(t, st, u, s.cpu, s.ram, P, cs, b.code + s.p0, lane);
-            if (lane == 0) {
-                __hip_atomic_store(g.flag, ok ? 1 : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (ok) {
-                    b.host[s.g] = u;
-                    b.score[s.g] = __uint_as_float(static_cast<unsigned>(kb >> 32) - 1u);
-                    if (s.i == s.n - 1) b.tse[s.r] = dev_clock();
+        if (w == 0) {
+            // workgroup 0 commits: 1 placed, 0 retry with the next server,
+            // 2 request rejected when its links were routed at its end
+            if (threadIdx.x < kWave) {
+                // commit_wave reads the peer servers from LDS; its routing
+                // uses the global state
+                Smem cs;
+                cs.pk = sm.pk;
+                const bool ok = commit_wave(t, st, u, s.cpu, s.ram, m.route_end ? 0 : P, cs, b.code + s.p0, lane);
+                if (lane == 0) {
+                    sm.misc[M_ROUTE + 1] = ok;
+                    if (ok) {
+                        b.host[s.g] = u;
+                        b.score[s.g] = __uint_as_float(static_cast<unsigned>(kb >> 32) - 1u);
+                        if (s.i == s.n - 1) b.tse[s.r] = dev_clock();
+                    }
                 }
             }
+            __syncthreads();
+            int res = sm.misc[M_ROUTE + 1];
+            if (res && m.route_end && s.i == s.n - 1)
+                res = route_request_end<BS>(t, st, b, sm.misc + M_ROUTE, s,
+                                            [&](int q) { return q == s.i ? u : rv.hosts[q]; }) ? 1 : 2;
+            if (threadIdx.x == 0) __hip_atomic_store(g.flag, res, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         if (!grid_sync(g, sm.misc + M_OK, timeout)) return false;             // barrier 3
         const int ok = __hip_atomic_load(g.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (ok == 2) return false;
         if (ok) {
             if (rv.hosts_out && threadIdx.x == 0) rv.hosts_out[s.i] = u;
             __syncthreads();

@@ -304,7 +304,7 @@ __global__ __launch_bounds__(BS) void k_ahp_select(Params p) {
     if (threadIdx.x == 0) trace_slot(p.tr, p.inst, p.b.rid[p.s.r], p.s.i);   // scores written by k_ahp_pg
     load_peers<BS, false>(t, p.st, rv, sm, p.s.P);
     const float *pg = reinterpret_cast<const float *>(p.xs + (size_t)(nc + 1) * N);
-    select_commit<BS, 1>(t, p.st, p.b, sm, p.xs + (size_t)nc * N, p.s, rv,
+    select_commit<BS, 1>(t, p.st, p.b, sm, p.xs + (size_t)nc * N, p.s, rv, p.m.route_end,
                       [&](int u) { return score_key(pg[u], u); });
 }
 

@@ -263,6 +263,7 @@ int check_config(const dc_config *c) {
     if (c->grid < 0 || c->grid > 2) return DC_EINVAL;
     if (c->graph < 0 || c->graph > 2) return DC_EINVAL;
     if (c->grid_timeout_us < 0) return DC_EINVAL;
+    if (c->routing < 0 || c->routing > 1) return DC_EINVAL;
     return DC_OK;
 }
 
@@ -567,7 +568,8 @@ int collect(dc_ctx *ctx, DevBatch &b) {
         res.instance = b.inst[r];
         res.status = b.status[r];
         res.n = b.cnt[r];
-        res.failed_at = b.status[r] ? -1 : b.first[g0 + b.failat[r]];
+        const int nu = b.coff[r + 1] - g0;       // failat == nu: the links did not fit
+        res.failed_at = b.status[r] ? -1 : (b.failat[r] < nu ? b.first[g0 + b.failat[r]] : b.cnt[r]);
         // a container gets its pod's server and score; a rejected request
         // places nothing (its attempt stays readable through dc_get_attempt)
         for (int i = 0; i < res.n; ++i) {
@@ -720,7 +722,7 @@ int serve_poll(dc_ctx *ctx) {
                 res.instance = 0;
                 res.status = c.status;
                 res.n = sl.nc;
-                res.failed_at = c.status ? -1 : sl.first[c.failat];
+                res.failed_at = c.status ? -1 : (c.failat < sl.n ? sl.first[c.failat] : sl.nc);
                 for (int i = 0; i < DC_MAX_CONTAINERS; ++i) res.host[i] = -1;
                 for (int i = 0; i < sl.nc; ++i) {           // each container takes its pod's result
                     const int g = sl.unit_of[i];
@@ -859,6 +861,7 @@ int dc_create(const dc_config *cfg, dc_ctx **out) {
     ctx->m.method = cfg->method;
     ctx->m.scale = cfg->ahp_scale;
     ctx->m.nc = cfg->ncrit;
+    ctx->m.route_end = cfg->routing;
     for (int c = 0; c < DC_MAX_CRIT; ++c) {
         ctx->m.crit[c] = c < cfg->ncrit ? cfg->crit[c] : 0;
         ctx->m.cost[c] = c < cfg->ncrit ? (cfg->crit_cost[c] != 0) : 0;

@@ -45,7 +45,8 @@ struct State {
 };
 
 struct Method {
-    int method, scale, nc, pad;
+    int method, scale, nc;
+    int route_end;      // 1: links routed after a request's last unit is placed (section V-D)
     int crit[kMaxCrit];
     int cost[kMaxCrit];
     float w[kMaxCrit];
@@ -96,7 +97,7 @@ struct Trace {
 enum {
     M_OK = 0, M_TRACE = 1,
     M_DH0 = 2, M_DH1 = 3, M_DE0 = 4, M_DE1 = 5, M_DP0 = 6, M_DP1 = 7,   // deficits (min, max id)
-    M_ALIVE = 8, M_MISC = 16
+    M_ALIVE = 8, M_ROUTE = 9, M_MISC = 16
 };
 
 constexpr int kMaxWaves = 16;          // 1024-thread workgroups
@@ -519,9 +520,11 @@ __device__ void criteria_stage(const Topo &t, const State &st, const Method &m, 
                 if (ch == 0) {
                     pbw_acc[g] = up_u[g]; up_acc[g] = 0; hop_acc[g] = 0; oute[g] = 0; outp[g] = 0;
                     int f = (st.cpu[us] >= cpu_i) & (st.ram[us] >= ram_i);
-                    f &= (dh1 < 0) | ((dh0 == dh1) & (u == dh0));
-                    f &= (de1 < 0) | ((de0 == de1) & (eu[g] == de0));
-                    f &= (dp1 < 0) | ((dp0 == dp1) & (pu[g] == dp0));
+                    if (!m.route_end) {
+                        f &= (dh1 < 0) | ((dh0 == dh1) & (u == dh0));
+                        f &= (de1 < 0) | ((de0 == de1) & (eu[g] == de0));
+                        f &= (dp1 < 0) | ((dp0 == dp1) & (pu[g] == dp0));
+                    }
                     feas[g] = f;
                 } else {
                     feas[g] = xs[nc * N + us];
@@ -566,7 +569,7 @@ __device__ void criteria_stage(const Topo &t, const State &st, const Method &m, 
                     continue;
                 }
                 int f = feas[g] & (up_u[g] >= up_acc[g]);
-                if (P > 0) f &= (sm.capE[eu[g]] >= oute[g]) & (sm.capP[pu[g]] >= outp[g]);
+                if (P > 0 && !m.route_end) f &= (sm.capE[eu[g]] >= oute[g]) & (sm.capP[pu[g]] >= outp[g]);
                 xs[nc * N + u] = f;
 #pragma unroll
                 for (int c = 0; c < kMaxCrit; ++c) {
@@ -735,6 +738,70 @@ __device__ __forceinline__ int trace_slot(const Trace &tr, int inst, int rid, in
     return slot;
 }
 
+// Routing after the last unit of request r is placed (section V-D, with
+// Method::route_end): every routed pair's widest minimum-hop path is chosen
+// on the residuals the placement left, all pairs independently (one wave per
+// unit's pairs); then every demand is taken off its links at once.  If a
+// link goes negative the request does not fit: everything it took is given
+// back and it is rejected with failed_at = n.  host(g) is the server of unit
+// g (u for the unit just placed).  Returns true when the request was
+// accepted.
+template <int BS, class HostFn>
+__device__ bool route_request_end(const Topo &t, const State &st, const Batch &b, int *lds_ok, const StepIn &s,
+                                  HostFn host) {
+    constexpr int NW = BS / kWave;
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    // the commit's stores (server, codes) are visible to every wave from here
+    __threadfence();
+    if (threadIdx.x == 0) *lds_ok = 1;
+    __syncthreads();
+    for (int g = wid; g < s.n; g += NW) {
+        const int u = host(g), eu = fdiv(u, t.rh), pu = fdiv(u, t.rhh);
+        for (int x = b.poff[s.g0 + g]; x < b.poff[s.g0 + g + 1]; ++x) {
+            const int v = host(b.pj[x]);
+            int c = -1;
+            if (v != u) {
+                const unsigned best = widest_wave(t, st, u, v, eu, pu, fdiv(v, t.rh), fdiv(v, t.rhh), lane);
+                c = 1023 - static_cast<int>(best & 1023u);
+            }
+            if (lane == 0) b.code[x] = c;
+        }
+    }
+    __threadfence();
+    __syncthreads();
+    for (int g = wid; g < s.n; g += NW) {                  // take every demand off its path
+        const int u = host(g);
+        for (int x = b.poff[s.g0 + g]; x < b.poff[s.g0 + g + 1]; ++x) {
+            const int c = b.code[x];
+            if (c >= 0) path_apply_lanes<true>(t, st, u, host(b.pj[x]), c, -b.pbw[x], lane);
+        }
+    }
+    __threadfence();
+    __syncthreads();
+    for (int g = wid; g < s.n; g += NW) {                  // any link overdrawn?
+        const int u = host(g);
+        for (int x = b.poff[s.g0 + g]; x < b.poff[s.g0 + g + 1]; ++x) {
+            const int c = b.code[x];
+            if (c >= 0 && lane < 6) {
+                const int *l = path_link(t, st, u, host(b.pj[x]), c, lane);
+                if (l && __hip_atomic_load(l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < 0) *lds_ok = 0;
+            }
+        }
+    }
+    __syncthreads();
+    if (*lds_ok) return true;
+    give_back<BS>(t, st, b, s.r, s.n);          // all units and their routes
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        b.status[s.r] = 0;
+        b.failat[s.r] = s.n;
+        b.tse[s.r] = dev_clock();
+    }
+    __threadfence_block();
+    __syncthreads();
+    return false;
+}
+
 // Select-and-commit loop shared by TOPSIS and AHP: key_of(u) gives the
 // score key of a feasible server (score bits + 1 above ~u, so a feasible
 // server's key is never 0).  Servers are visited in decreasing key order by
@@ -744,7 +811,7 @@ __device__ __forceinline__ int trace_slot(const Trace &tr, int inst, int rid, in
 // back when no server is left.  Returns true when the container was placed.
 template <int BS, int G, class KeyFn>
 __device__ bool select_commit(const Topo &t, const State &st, const Batch &b, const Smem &sm, int *feas_row,
-                              const StepIn &s, const ReqView &rv, KeyFn key_of) {
+                              const StepIn &s, const ReqView &rv, int m_route_end, KeyFn key_of) {
     const int lane = threadIdx.x & (kWave - 1);
     auto scan = [&]() {
         unsigned long long kb = 0;
@@ -780,7 +847,7 @@ __device__ bool select_commit(const Topo &t, const State &st, const Batch &b, co
         }
         const int u = static_cast<int>(~static_cast<unsigned>(kb & 0xffffffffu));
         if (threadIdx.x < kWave) {
-            const bool ok = commit_wave(t, st, u, s.cpu, s.ram, s.P, sm, b.code + s.p0, lane);
+            const bool ok = commit_wave(t, st, u, s.cpu, s.ram, m_route_end ? 0 : s.P, sm, b.code + s.p0, lane);
             if (lane == 0) {
                 sm.misc[M_OK] = ok;
                 if (ok) {
@@ -795,7 +862,12 @@ __device__ bool select_commit(const Topo &t, const State &st, const Batch &b, co
         }
         __threadfence_block();
         __syncthreads();
-        if (sm.misc[M_OK]) return true;
+        if (sm.misc[M_OK]) {
+            if (m_route_end && s.i == s.n - 1)
+                return route_request_end<BS>(t, st, b, sm.misc + M_ROUTE, s,
+                                             [&](int g) { return g == s.i ? u : rv.hosts[g]; });
+            return true;
+        }
         if (u % BS == static_cast<int>(threadIdx.x)) mine = scan();
     }
 }
@@ -842,7 +914,7 @@ __device__ bool topsis_step(const Topo &t, const State &st, const Method &m, con
     const int slot = sm.misc[M_TRACE];
     if (slot >= 0)
         for (int u = threadIdx.x; u < N; u += BS) tr.scores[static_cast<size_t>(slot) * N + u] = closeness(u);
-    return select_commit<BS, G>(t, st, b, sm, xs + nc * N, s, rv,
+    return select_commit<BS, G>(t, st, b, sm, xs + nc * N, s, rv, m.route_end,
                                              [&](int u) { return score_key(closeness(u), u); });
 }
 

@@ -21,7 +21,7 @@ def gpu_follow(sched, rid, res, req=None):
     att = sched.attempt(rid)
     unit, first = O.units(len(att), getattr(req, "pod", None))
     follow = att[first].copy()
-    if res.status == 0:
+    if res.status == 0 and res.failed_at < res.n:      # failed_at == n: placed, links did not fit
         follow[unit[res.failed_at]:] = -1
     return follow
 
@@ -59,7 +59,7 @@ def lockstep(o, sched, ids, reqs, results, tol=TOL, trace=None, check_paths=Fals
         ref = o.run_request(req, follow=follow, detail=True, dump=want_dump)
         assert ref["status"] == g.status, f"request {pos}: oracle status {ref['status']} vs gpu {g.status}"
         assert ref["failed_at"] == g.failed_at
-        steps = len(first) if g.status == 1 else unit[g.failed_at] + 1
+        steps = len(first) if g.status == 1 or g.failed_at == req.n else unit[g.failed_at] + 1
         for i in range(steps):
             if follow[i] < 0:
                 assert ref["ref_host"][i] < 0, f"request {pos} step {i}: oracle found a server"

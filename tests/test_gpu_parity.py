@@ -514,3 +514,63 @@ def test_full_size_accounting(wl):
         assert s.release(rid) == dc.DC_OK
     np.testing.assert_array_equal(s.state(0), s0)
     s.close()
+
+
+# ---------------------------------------------------------------- routing at the end of a request
+@pytest.mark.parametrize("method", [dc.DC_TOPSIS, dc.DC_AHP])
+def test_route_end_tiny_lockstep(method):
+    """Links routed after the last container (section V-D): k=4, every step
+    and every routed path against the oracle, with and without pods."""
+    tot = dict(accepted=0, rejected=0, steps=0)
+    for seed in range(16):
+        for preset in ("tiny", "tiny_pods"):
+            insts, reqs = make_config(preset, seed=seed)
+            s = dc.Scheduler(insts, method=method, routing=dc.DC_ROUTE_END, trace_stride=1, trace_cap=4096)
+            o = O.Oracle(insts[0], O.method(kind=method, route_end=True))
+            for req in reqs[0]:
+                rid = s.submit(req)
+                res = {r.req_id: r for r in s.schedule()}
+                st = lockstep(o, s, [rid], [req], res, trace=trace_by_request(s), check_paths=True)
+                for k in tot:
+                    tot[k] += st[k]
+            s.close()
+    assert tot["accepted"] > 100 and tot["steps"] > 300
+
+
+def test_route_end_k16_forms_agree():
+    """k=16, routing at the end: plain in lockstep with the oracle (some
+    requests rejected because their links do not fit); batched, serving and
+    the cooperative step bit-identical to plain."""
+    insts, reqs = make_config("plain", seed=12, n_req=250)
+    p, pids, pres = _run(insts, reqs, routing=dc.DC_ROUTE_END, trace_stride=7, trace_cap=4096)
+    o = O.Oracle(insts[0], O.method(kind=O.TOPSIS, route_end=True))
+    st = lockstep(o, p, pids[0], reqs[0], pres, trace=trace_by_request(p), check_paths=True)
+    assert st["accepted"] > 20 and st["scored_steps"] > 10
+    n = {x: r.n for x, r in zip(pids[0], reqs[0])}
+    assert any(pres[x].status == 0 and pres[x].failed_at == n[x] for x in pids[0])
+    others = [_run(insts, reqs, mode=dc.DC_MODE_BATCHED, routing=dc.DC_ROUTE_END),
+              _run(insts, reqs, routing=dc.DC_ROUTE_END, grid=2)]
+    sv = dc.Scheduler(insts, mode=dc.DC_MODE_SERVING, routing=dc.DC_ROUTE_END)
+    sids = [sv.submit(r) for r in reqs[0]]
+    others.append((sv, [sids], {r.req_id: r for r in sv.drain()}))
+    for sched, ids, res in others:
+        for x, y in zip(pids[0], ids[0]):
+            assert res[y].status == pres[x].status and res[y].failed_at == pres[x].failed_at
+            np.testing.assert_array_equal(res[y].hosts, pres[x].hosts)
+            np.testing.assert_array_equal(res[y].scores.view(np.uint32), pres[x].scores.view(np.uint32))
+            if pres[x].status == 1:
+                np.testing.assert_array_equal(sched.paths(y), p.paths(x))
+        np.testing.assert_array_equal(sched.state(0), p.state(0))
+        sched.close()
+    p.close()
+
+
+def test_route_end_k48_cooperative_sampled():
+    """k=48 (cooperative step, workgroup 0 routes the request's links):
+    lockstep on a prefix, score vectors sampled."""
+    insts, reqs = make_config("serving", seed=3, n_req=6)
+    s, ids, res = _run(insts, reqs, routing=dc.DC_ROUTE_END, trace_stride=5, trace_cap=64)
+    o = O.Oracle(insts[0], O.method(kind=O.TOPSIS, route_end=True))
+    st = lockstep(o, s, ids[0], reqs[0], res, trace=trace_by_request(s), check_paths=True)
+    assert st["scored_steps"] >= 1
+    s.close()

@@ -509,3 +509,73 @@ def test_pod_placements_sound(oracle_lib, kind):
         np.testing.assert_array_equal(after[1], before[1] - use_ram)
         np.testing.assert_array_equal(after[3:].reshape(-1), before[3:].reshape(-1) - link_use)
     assert n_acc >= 10 and n_rej >= 5
+
+
+# ---------------------------------------------------------------- routing at the end of a request (section V-D)
+def test_route_end_pairs_share_the_pre_routing_residuals(oracle_lib):
+    """Hand case, k=4: containers 1 and 2 on server 4 (pod 1) each send
+    1000 Mbps to container 0 on server 0 (pod 0).  The aggregation-core
+    links of core (0, 0) hold 1500, every other one 1000.  Routed at each
+    placement, the second pair sees 500 left on core (0, 0) and takes core
+    (0, 1): accepted.  Routed at the end, both pairs pick core (0, 0) on the
+    residuals the placement left and overdraw it: rejected, failed_at = n,
+    nothing taken."""
+    inst = make_instance(4, 32, 256, 40000, 10000, 1000)
+    req = Request(np.ones(3, np.int32), np.ones(3, np.int32), np.array([[0, 1, 1000], [0, 2, 1000]], np.int32))
+    out = {}
+    for end in (False, True):
+        o = O.Oracle(inst, O.method(route_end=end))
+        o.set_link(2 * 16 + 0, 1500)       # pod 0, aggregation 0, core 0
+        o.set_link(2 * 16 + 4, 1500)       # pod 1, aggregation 0, core 0
+        s0 = o.state().copy()
+        res = o.run_request(req, follow=np.array([0, 4, 4], np.int32))
+        out[end] = (o, s0, res)
+    o, s0, res = out[False]
+    assert res["status"] == 1
+    links, bws = o.paths(res["rec_id"])
+    got = [sorted(int(l) for l in p if l >= 0) for p in links]
+    assert got == [[0, 4, 16, 20, 32, 36], [0, 4, 16, 20, 33, 37]]
+    o, s0, res = out[True]
+    assert res["status"] == 0 and res["failed_at"] == 3
+    np.testing.assert_array_equal(o.state(), s0)
+
+
+def test_route_end_without_links_equals_route_each(oracle_lib):
+    """Requests without traffic between containers schedule identically
+    whichever way links are routed."""
+    rng = np.random.default_rng(41)
+    inst = make_instance(6, 32, 256, 5000, 8000, 8000, background=0.5, rng=rng)
+    a, b = O.Oracle(inst), O.Oracle(inst, O.method(route_end=True))
+    for r in make_requests(40, rng, 1, 8):
+        r = Request(r.cpu, r.ram, np.zeros((0, 3), np.int32))
+        ra, rb = a.run_request(r), b.run_request(r)
+        assert ra["status"] == rb["status"]
+        np.testing.assert_array_equal(ra["hosts"], rb["hosts"])
+    np.testing.assert_array_equal(a.state(), b.state())
+
+
+@pytest.mark.parametrize("kind", [O.TOPSIS, O.AHP])
+def test_route_end_sound(oracle_lib, kind):
+    """Routing at the end on a loaded k=4: an accepted request's pairs each
+    run on a path joining their servers and the residuals absorb all of them
+    (link usage = sum of demand x hops); a rejected one changes nothing."""
+    rng = np.random.default_rng(51 + kind)
+    inst = make_instance(4, 32, 256, 3000, 3000, 3000, background=0.8, rng=rng)
+    o = O.Oracle(inst, O.method(kind, route_end=True))
+    ends, _ = _ft_links(4)
+    n_acc = n_rej = n_route = 0
+    for t in range(80):
+        n = int(rng.integers(2, 5))
+        req = make_requests(1, rng, n, n, cpu_lo=1, cpu_hi=10, ram_lo=1, ram_hi=60, bw_lo=200, bw_hi=1500)[0]
+        before = o.state().astype(np.int64)
+        res = o.run_request(req)
+        after = o.state().astype(np.int64)
+        assert np.all(after >= 0)
+        if res["status"] != 1:
+            n_rej += 1
+            n_route += res["failed_at"] == n
+            np.testing.assert_array_equal(after, before)
+            continue
+        n_acc += 1
+        _verify_solution(4, before, after, req, res["hosts"], *o.paths(res["rec_id"]))
+    assert n_acc >= 10 and n_rej >= 5 and n_route >= 1
