@@ -18,7 +18,7 @@ section II-A, with the k-ary fat-tree of section IV-A):
   host_used[2][N] (CPU cores, RAM GB) and link_used[3][N] (Mbps).
 """
 from .gen import (FatTree, Instance, Request, make_instance, make_requests,
-                  make_config, make_trace, CONFIGS, pack_requests, make_tiles, TILE_RANGES)
+                  make_config, make_trace, CONFIGS, pack_requests, make_tiles, TILE_RANGES, make_event_workload)
 
 __all__ = ["FatTree", "Instance", "Request", "make_instance", "make_requests",
-           "make_config", "make_trace", "CONFIGS", "pack_requests", "make_tiles", "TILE_RANGES"]
+           "make_config", "make_trace", "CONFIGS", "pack_requests", "make_tiles", "TILE_RANGES", "make_event_workload"]

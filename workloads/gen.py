@@ -242,6 +242,25 @@ def make_config(name: str, seed: int = 0, instances: Optional[int] = None,
     return insts, reqs
 
 
+def make_event_workload(seed: int, k: int = 20, n_req: int = 6000, n: int = 4, total_events: int = 500,
+                        span: int = 250):
+    """The shape of the paper's GPU evaluation (section VI-A): a k-ary
+    fat-tree of 24-core / 256 GB servers with 1 Gbps links and no other
+    load; n_req requests of n containers, up to half of them in pods, up to
+    50 Mbps between a pair of containers, CPU up to 2 cores and RAM up to 4
+    GB per container.  Each request arrives at a uniform event in
+    [0, span) and runs for a uniform 1..span events of a total_events run.
+    Returns (instance, requests, arrival events, durations)."""
+    rng = _rng(np.random.SeedSequence([seed, 6]))
+    inst = make_instance(k, 24, 256, 1000, 1000, 1000)
+    reqs = make_requests(n_req, rng, n, n, cpu_lo=1, cpu_hi=2, ram_lo=1, ram_hi=4, bw_lo=1, bw_hi=50,
+                         pod_frac=0.5)
+    arrive = np.sort(rng.integers(0, span, size=n_req))
+    dur = rng.integers(1, span + 1, size=n_req)
+    assert total_events >= 2 * span
+    return inst, reqs, arrive, dur
+
+
 def make_trace(seed: int, duration_s: float, rate_per_s: float = 5000.0,
                mean_life_s: float = 60.0, n_lo: int = 2, n_hi: int = 64):
     """Poisson arrivals (exponential inter-arrival, mean 1/rate) with
