@@ -454,16 +454,20 @@ def _ft_link_hops(paths):
     return int((paths >= 0).sum())
 
 
-@pytest.mark.parametrize("wl", ["ahp", "plain", "pods"])
+@pytest.mark.parametrize("wl", ["ahp", "plain", "pods", "pods_route_end"])
 def test_full_size_accounting(wl):
     """The measured configurations at full size (AHP k=32 with 500 requests,
-    TOPSIS k=16 with 2,000 requests, with and without pods), checked by
+    TOPSIS k=16 with 2,000 requests, with and without pods, and with pods
+    and links routed at each request's end), checked by
     properties that hold at any size: the state change equals the accepted
     placements (CPU, RAM, placed counts per server) and their routes (link
     usage = summed demand x hops), nothing goes negative, and releasing every
     accepted request restores the initial state bit-exactly."""
-    insts, reqs = make_config(wl, seed=0)
     kw = {}
+    if wl == "pods_route_end":
+        wl = "pods"
+        kw = dict(routing=dc.DC_ROUTE_END)
+    insts, reqs = make_config(wl, seed=0)
     if wl == "ahp":
         kw = dict(method=dc.DC_AHP, crit=C5, cost=C5_COST)
     s = dc.Scheduler(insts, **kw)
