@@ -54,18 +54,22 @@ def _replay(s, reqs, cmds, alone):
     return ids, res
 
 
-def _k16():
-    insts, reqs = make_config("plain", seed=21, n_req=160)
+def _k16(preset="plain"):
+    insts, reqs = make_config(preset, seed=21, n_req=160)
     return insts, reqs[0]
 
 
-@pytest.mark.parametrize("grid", [1, 2])
-def test_serving_alone_equals_mix_and_oracle(grid):
-    insts, reqs = _k16()
+@pytest.mark.parametrize("grid,preset,routing", [(1, "plain", 0), (2, "plain", 0), (1, "pods", 1), (2, "pods", 0)])
+def test_serving_alone_equals_mix_and_oracle(grid, preset, routing):
+    """Each request's result is the same alone and in the mix (single
+    workgroup against the cooperative kernel), and in lockstep with the
+    oracle over interleaved requests and departures; also with pods and with
+    links routed at the end of each request."""
+    insts, reqs = _k16(preset)
     cmds = _commands(reqs)
-    mix = dc.Scheduler(insts, mode=dc.DC_MODE_SERVING, grid=grid)
+    mix = dc.Scheduler(insts, mode=dc.DC_MODE_SERVING, grid=grid, routing=routing)
     ids_m, res_m = _replay(mix, reqs, cmds, alone=False)
-    alone = dc.Scheduler(insts, mode=dc.DC_MODE_SERVING, grid=3 - grid)
+    alone = dc.Scheduler(insts, mode=dc.DC_MODE_SERVING, grid=3 - grid, routing=routing)
     ids_a, res_a = _replay(alone, reqs, cmds, alone=True)
     for t in range(len(reqs)):
         a, b = res_m[ids_m[t]], res_a[ids_a[t]]
@@ -74,7 +78,7 @@ def test_serving_alone_equals_mix_and_oracle(grid):
         np.testing.assert_array_equal(a.scores.view(np.uint32), b.scores.view(np.uint32))
     np.testing.assert_array_equal(mix.state(0), alone.state(0))
     # the oracle replays the same commands in the same order
-    o = O.Oracle(insts[0], O.method(kind=O.TOPSIS))
+    o = O.Oracle(insts[0], O.method(kind=O.TOPSIS, route_end=bool(routing)))
     rec = {}
     for kind, t in cmds:
         if kind == "submit":
