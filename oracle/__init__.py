@@ -79,10 +79,10 @@ def lib():
         L.or_saaty.argtypes = [C.c_double, C.c_double]
         L.or_step_scores.argtypes = [P, C.POINTER(Method), C.c_int, C.c_int, C.c_int, i32p, i32p,
                                      f64p, i32p, f64p]
-        L.or_run_request.argtypes = [P, C.POINTER(Method), C.c_int, i32p, i32p, C.c_int, P, P,
-                                     P, P, P, P, P, P, P, P]
-        L.or_run_request_pods.argtypes = [P, C.POINTER(Method), C.c_int, i32p, i32p, C.c_int, P, P, P,
-                                          P, P, P, P, P, P, P, P]
+        L.or_run_request.argtypes = [P, C.POINTER(Method), C.c_int, i32p, i32p, C.c_int, P, P, P, P, P,
+                                     P, P, P, P, P, P, P, P, P, P, P]
+        L.or_run_request_pods.argtypes = [P, C.POINTER(Method), C.c_int, i32p, i32p, C.c_int, P, P, P, P, P,
+                                          P, P, P, P, P, P, P, P, P, P, P, P]
         L.or_units.argtypes = [C.c_int, P, i32p, i32p]
         L.or_release.argtypes = [P, C.c_int64]
         L.or_get_paths.argtypes = [P, C.c_int64, C.c_int, i32p, i64p]
@@ -192,14 +192,25 @@ class Oracle:
     def run_request(self, req, follow=None, detail=False, dump=False):
         """Schedule one request.  Returns a dict with status (1 accepted,
         0 rejected, <0 error), hosts, scores (per container), failed_at,
-        rec_id and, with detail=True, the per-step own choice / top score /
-        top-two gap / chosen score (ref_host, ref_top, ref_gap,
-        step_scores).  A step places one pod (one container without pods);
-        follow and the per-step outputs are indexed by step."""
+        rec_id, the allocations cpu_a, ram_a (per container) and bw_a (per
+        edge) of an accepted request and, with detail=True, the per-step own
+        choice / top score / top-two gap / chosen score (ref_host, ref_top,
+        ref_gap, step_scores).  A step places one pod (one container without
+        pods); follow and the per-step outputs are indexed by step.  The
+        request's cpu, ram and edge demands are minima; optional cpu_max,
+        ram_max and bw_max give the interval maxima (section II-A)."""
         n = req.n
         cpu = np.ascontiguousarray(req.cpu, dtype=np.int32)
         ram = np.ascontiguousarray(req.ram, dtype=np.int32)
         edges = np.ascontiguousarray(req.edges, dtype=np.int32).reshape(-1)
+
+        def opt(name):
+            v = getattr(req, name, None)
+            return None if v is None else np.ascontiguousarray(v, dtype=np.int32)
+        cx, rx, bx = opt("cpu_max"), opt("ram_max"), opt("bw_max")
+        cpu_a = np.full(n, -1, dtype=np.int32)
+        ram_a = np.full(n, -1, dtype=np.int32)
+        bw_a = np.full(max(req.m, 1), -1, dtype=np.int32)
         pod = getattr(req, "pod", None)
         pod = None if pod is None else np.ascontiguousarray(pod, dtype=np.int32)
         nu = len(units(n, pod)[1])
@@ -213,14 +224,17 @@ class Oracle:
         fa = np.zeros(1, dtype=np.int32)
         rid = np.zeros(1, dtype=np.int64)
         if pod is None:
-            st = lib().or_run_request(self.h, C.byref(self.m), n, cpu, ram, req.m, _ptr(edges), _ptr(fol),
-                                      _ptr(host), _ptr(score), _ptr(rh), _ptr(rt), _ptr(rg), _ptr(dmp),
-                                      _ptr(fa), _ptr(rid))
+            st = lib().or_run_request(self.h, C.byref(self.m), n, cpu, ram, req.m, _ptr(edges), _ptr(cx),
+                                      _ptr(rx), _ptr(bx), _ptr(fol), _ptr(host), _ptr(score), _ptr(rh),
+                                      _ptr(rt), _ptr(rg), _ptr(dmp), _ptr(fa), _ptr(rid), _ptr(cpu_a),
+                                      _ptr(ram_a), _ptr(bw_a))
         else:
-            st = lib().or_run_request_pods(self.h, C.byref(self.m), n, cpu, ram, req.m, _ptr(edges), _ptr(pod),
-                                           _ptr(fol), _ptr(host), _ptr(score), _ptr(rh), _ptr(rt), _ptr(rg),
-                                           _ptr(dmp), _ptr(fa), _ptr(rid))
-        out = dict(status=st, hosts=host, scores=score, failed_at=int(fa[0]), rec_id=int(rid[0]))
+            st = lib().or_run_request_pods(self.h, C.byref(self.m), n, cpu, ram, req.m, _ptr(edges), _ptr(cx),
+                                           _ptr(rx), _ptr(bx), _ptr(pod), _ptr(fol), _ptr(host), _ptr(score),
+                                           _ptr(rh), _ptr(rt), _ptr(rg), _ptr(dmp), _ptr(fa), _ptr(rid),
+                                           _ptr(cpu_a), _ptr(ram_a), _ptr(bw_a))
+        out = dict(status=st, hosts=host, scores=score, failed_at=int(fa[0]), rec_id=int(rid[0]),
+                   cpu_a=cpu_a, ram_a=ram_a, bw_a=bw_a[: req.m])
         if detail:
             unit, first = units(n, pod)
             out.update(ref_host=rh, ref_top=rt, ref_gap=rg, step_scores=score[first])

@@ -21,6 +21,8 @@
  *     with one residual per undirected link: section V-D.
  *   - capacity / bandwidth constraints Eqs. (4)-(5) and the accept/reject
  *     decision with mappings M_c, M_ec: sections II-A and III-B.
+ *   - demands given as minimum / maximum intervals and the utilities
+ *     U(i), U(ij) of what is allocated: section II-A, Eqs. (1)-(2).
  * Readings where the paper is silent or garbled are listed beside the code.
  *
  * Parity pins: every function here is pinned by the CPU tests (hand-worked
@@ -51,10 +53,10 @@ typedef struct {
     int64_t id;
     int n;
     int *host;          /* n */
-    int *cpu, *ram;     /* n */
+    int *cpu, *ram;     /* n, allocated */
     int npath;
     int *plink;         /* npath * 6 link ids, -1 padded */
-    int64_t *pbw;       /* npath */
+    int64_t *pbw;       /* npath, allocated */
     int live;
 } or_record;
 
@@ -451,22 +453,33 @@ int or_step_scores(or_dc *d, const or_method *m, int cpu_i, int ram_i, int P,
 /* active, and route every remote placed peer in ascending order on its   */
 /* widest shortest path under the current residuals (ties: the            */
 /* lexicographically first path).  Fails, leaving no trace, when a         */
-/* resource or a path bottleneck does not cover the demand (Eqs. (4)-(5)). */
+/* resource or a path bottleneck does not cover the minimum demand (Eqs.   */
+/* (4)-(5)).                                                               */
+/*                                                                          */
+/* Demand intervals (section II-A): a container runs with any amount in    */
+/* [min, max] and its utility (Eqs. (1)-(2)) grows with the amount, so a   */
+/* placement takes as much as the server has left, up to the maximum:      */
+/* min(max, residual) of CPU and of RAM, and min(max, bottleneck) on each   */
+/* peer path.  A peer on the same server needs no link and gets its max.   */
+/* Fixed demands are the case min = max.                                    */
 /* ------------------------------------------------------------------ */
 typedef struct { int nl; int link[6]; int64_t bw; } or_path;
 
-static int try_commit(or_dc *d, int u, int cpu_i, int ram_i, int P, const int *ph,
-                      const int *pbw, or_path *paths) {
+static int64_t min64(int64_t a, int64_t b) { return a < b ? a : b; }
+
+static int try_commit(or_dc *d, int u, int cpu_i, int cpu_x, int ram_i, int ram_x, int P, const int *ph,
+                      const int *pbw, const int *pbx, or_path *paths, int *cpu_a, int *ram_a) {
     if (d->cpu_res[u] < cpu_i || d->ram_res[u] < ram_i) return 0;
     int routed = 0, ok = 1;
     for (int p = 0; p < P; ++p) {
-        paths[p].nl = 0; paths[p].bw = pbw[p];
+        paths[p].nl = 0; paths[p].bw = pbx[p];
         if (ph[p] == u) continue;
         int64_t b; int32_t links[6], hops;
         or_widest_enum(d, u, ph[p], &b, links, &hops);
         if (b < pbw[p]) { ok = 0; break; }
         paths[p].nl = hops;
-        for (int l = 0; l < hops; ++l) { paths[p].link[l] = links[l]; d->link_res[links[l]] -= pbw[p]; }
+        paths[p].bw = min64(pbx[p], b);
+        for (int l = 0; l < hops; ++l) { paths[p].link[l] = links[l]; d->link_res[links[l]] -= paths[p].bw; }
         routed = p + 1;
     }
     if (!ok) {
@@ -474,14 +487,16 @@ static int try_commit(or_dc *d, int u, int cpu_i, int ram_i, int P, const int *p
             for (int l = 0; l < paths[p].nl; ++l) d->link_res[paths[p].link[l]] += paths[p].bw;
         return 0;
     }
-    d->cpu_res[u] -= cpu_i; d->ram_res[u] -= ram_i; d->nplaced[u] += 1;
+    *cpu_a = (int)min64(cpu_x, d->cpu_res[u]);
+    *ram_a = (int)min64(ram_x, d->ram_res[u]);
+    d->cpu_res[u] -= *cpu_a; d->ram_res[u] -= *ram_a; d->nplaced[u] += 1;
     return 1;
 }
 
-static void undo_commit(or_dc *d, int u, int cpu_i, int ram_i, int P, const or_path *paths) {
+static void undo_commit(or_dc *d, int u, int cpu_a, int ram_a, int P, const or_path *paths) {
     for (int p = P - 1; p >= 0; --p)
         for (int l = 0; l < paths[p].nl; ++l) d->link_res[paths[p].link[l]] += paths[p].bw;
-    d->cpu_res[u] += cpu_i; d->ram_res[u] += ram_i; d->nplaced[u] -= 1;
+    d->cpu_res[u] += cpu_a; d->ram_res[u] += ram_a; d->nplaced[u] -= 1;
 }
 
 typedef struct { double s; int u; } cand;
@@ -503,27 +518,42 @@ static int cmp_cand(const void *x, const void *y) {
 /* Per step outputs (nullable): own choice, its score, the score gap to the */
 /* second commit-successful server, the score of the committed server, and */
 /* the full score vector (n x N).                                          */
+/* Demand intervals (nullable, then max = min): cpu_max, ram_max per       */
+/* container, bw_max per edge (edges hold the minimum).  Allocations       */
+/* (nullable outputs, accepted requests): cpu_a, ram_a per container and    */
+/* bw_a per edge.                                                           */
 /* Returns 1 accepted, 0 rejected, -1 invalid request, -2 the followed      */
 /* server cannot be committed, -3 the followed side rejected while this one */
 /* found a server (or the reverse).                                        */
 /* ------------------------------------------------------------------ */
 int or_run_request(or_dc *d, const or_method *m, int n, const int32_t *cpu, const int32_t *ram,
-                   int ne, const int32_t *edges, const int32_t *follow,
+                   int ne, const int32_t *edges, const int32_t *cpu_max, const int32_t *ram_max,
+                   const int32_t *bw_max, const int32_t *follow,
                    int32_t *host_out, double *score_out, int32_t *ref_host, double *ref_top,
-                   double *ref_gap, double *dump, int32_t *failed_at, int64_t *rec_id) {
+                   double *ref_gap, double *dump, int32_t *failed_at, int64_t *rec_id,
+                   int32_t *cpu_a, int32_t *ram_a, int32_t *bw_a) {
     int N = d->N;
     if (n <= 0) return -1;
+    for (int i = 0; i < n; ++i)
+        if ((cpu_max && cpu_max[i] < cpu[i]) || (ram_max && ram_max[i] < ram[i])) return -1;
     /* peer lists: for container i, edges (i, j) with j < i, j ascending */
     int64_t *bwm = (int64_t *)calloc((size_t)n * n, sizeof(int64_t));
+    int64_t *bwx = (int64_t *)calloc((size_t)n * n, sizeof(int64_t));
     for (int e = 0; e < ne; ++e) {
         int a = edges[3 * e], b = edges[3 * e + 1], bw = edges[3 * e + 2];
-        if (a < 0 || b < 0 || a >= n || b >= n || a == b || bw <= 0 || bwm[(size_t)a * n + b]) { free(bwm); return -1; }
+        int bx = bw_max ? bw_max[e] : bw;
+        if (a < 0 || b < 0 || a >= n || b >= n || a == b || bw <= 0 || bx < bw || bwm[(size_t)a * n + b]) {
+            free(bwm); free(bwx); return -1;
+        }
         bwm[(size_t)a * n + b] = bw; bwm[(size_t)b * n + a] = bw;
+        bwx[(size_t)a * n + b] = bx; bwx[(size_t)b * n + a] = bx;
     }
     int *host = (int *)malloc(sizeof(int) * n);
+    int *ca = (int *)malloc(sizeof(int) * n), *ra = (int *)malloc(sizeof(int) * n);
     or_path *paths = (or_path *)malloc(sizeof(or_path) * (size_t)n * n);
     int *npeer = (int *)calloc(n, sizeof(int));
     int *ph = (int *)malloc(sizeof(int) * n), *pbw = (int *)malloc(sizeof(int) * n);
+    int *pbx = (int *)malloc(sizeof(int) * n);
     double *X = (double *)malloc(sizeof(double) * (size_t)OR_MAX_CRIT * N);
     int32_t *feas = (int32_t *)malloc(sizeof(int32_t) * N);
     double *score = (double *)malloc(sizeof(double) * N);
@@ -533,7 +563,9 @@ int or_run_request(or_dc *d, const or_method *m, int n, const int32_t *cpu, cons
     for (int i = 0; i < n; ++i) {
         int P = 0;
         for (int j = 0; j < i; ++j)
-            if (bwm[(size_t)i * n + j]) { ph[P] = host[j]; pbw[P] = (int)bwm[(size_t)i * n + j]; P++; }
+            if (bwm[(size_t)i * n + j]) {
+                ph[P] = host[j]; pbw[P] = (int)bwm[(size_t)i * n + j]; pbx[P] = (int)bwx[(size_t)i * n + j]; P++;
+            }
         or_step_scores(d, m, cpu[i], ram[i], P, ph, pbw, X, feas, score);
         if (dump) memcpy(dump + (size_t)i * N, score, sizeof(double) * N);
         for (int u = 0; u < N; ++u) { order[u].s = score[u]; order[u].u = u; }
@@ -542,11 +574,13 @@ int or_run_request(or_dc *d, const or_method *m, int n, const int32_t *cpu, cons
         int top1 = -1; double s1 = 0.0, s2 = -INFINITY;
         /* routing at the end of the request: a placement takes CPU and RAM only */
         const int Pc = m->route_end ? 0 : P;
+        const int cx = cpu_max ? cpu_max[i] : cpu[i], rx = ram_max ? ram_max[i] : ram[i];
         for (int r = 0; r < N; ++r) {
             int u = order[r].u;
             if (!feas[u]) continue;
-            if (try_commit(d, u, cpu[i], ram[i], Pc, ph, pbw, tmp)) {
-                undo_commit(d, u, cpu[i], ram[i], Pc, tmp);
+            int c_a, r_a;
+            if (try_commit(d, u, cpu[i], cx, ram[i], rx, Pc, ph, pbw, pbx, tmp, &c_a, &r_a)) {
+                undo_commit(d, u, c_a, r_a, Pc, tmp);
                 if (top1 < 0) { top1 = u; s1 = order[r].s; if (!ref_gap) break; }
                 else { s2 = order[r].s; break; }
             }
@@ -560,7 +594,7 @@ int or_run_request(or_dc *d, const or_method *m, int n, const int32_t *cpu, cons
             take = follow[i];
         }
         if (take < 0) { status = 0; fail_i = i; break; }
-        if (!try_commit(d, take, cpu[i], ram[i], Pc, ph, pbw, paths + (size_t)i * n)) {
+        if (!try_commit(d, take, cpu[i], cx, ram[i], rx, Pc, ph, pbw, pbx, paths + (size_t)i * n, ca + i, ra + i)) {
             status = -2; fail_i = i; break;
         }
         npeer[i] = Pc;
@@ -570,18 +604,21 @@ int or_run_request(or_dc *d, const or_method *m, int n, const int32_t *cpu, cons
     }
     if (status == 1 && m->route_end) {
         /* every pair's widest minimum-hop path on the residuals the placement
-         * left, each pair on its own; then all demands at once, and the
-         * request fits only if no link goes negative */
+         * left, each pair on its own, taking min(max, bottleneck) but at
+         * least the minimum; then all of it at once, and the request fits
+         * only if no link goes negative (a pair whose bottleneck is below
+         * its minimum drives that link negative) */
         for (int i = 0; i < n; ++i) {
             int P = 0;
             for (int j = 0; j < i; ++j) {
                 if (!bwm[(size_t)i * n + j]) continue;
                 or_path *pp = paths + (size_t)i * n + P;
-                pp->nl = 0; pp->bw = bwm[(size_t)i * n + j];
+                pp->nl = 0; pp->bw = bwx[(size_t)i * n + j];
                 if (host[j] != host[i]) {
                     int64_t b; int32_t links[6], hops;
                     or_widest_enum(d, host[i], host[j], &b, links, &hops);
                     pp->nl = hops;
+                    pp->bw = b < bwm[(size_t)i * n + j] ? bwm[(size_t)i * n + j] : min64(b, bwx[(size_t)i * n + j]);
                     for (int l = 0; l < hops; ++l) pp->link[l] = links[l];
                 }
                 P++;
@@ -599,7 +636,7 @@ int or_run_request(or_dc *d, const or_method *m, int n, const int32_t *cpu, cons
     }
     if (status != 1) {
         for (int i = fail_i - 1; i >= 0; --i)
-            undo_commit(d, host[i], cpu[i], ram[i], npeer[i], paths + (size_t)i * n);
+            undo_commit(d, host[i], ca[i], ra[i], npeer[i], paths + (size_t)i * n);
         if (host_out) for (int i = 0; i < n; ++i) host_out[i] = -1;
     }
     if (failed_at) *failed_at = fail_i;
@@ -620,7 +657,9 @@ int or_run_request(or_dc *d, const or_method *m, int n, const int32_t *cpu, cons
         R->pbw = (int64_t *)malloc(sizeof(int64_t) * (np ? np : 1));
         int q = 0;
         for (int i = 0; i < n; ++i) {
-            R->host[i] = host[i]; R->cpu[i] = cpu[i]; R->ram[i] = ram[i];
+            R->host[i] = host[i]; R->cpu[i] = ca[i]; R->ram[i] = ra[i];
+            if (cpu_a) cpu_a[i] = ca[i];
+            if (ram_a) ram_a[i] = ra[i];
             for (int p = 0; p < npeer[i]; ++p, ++q) {
                 const or_path *pp = paths + (size_t)i * n + p;
                 R->pbw[q] = pp->bw;
@@ -629,8 +668,16 @@ int or_run_request(or_dc *d, const or_method *m, int n, const int32_t *cpu, cons
         }
         if (rec_id) *rec_id = R->id;
         d->nrec++;
+        /* per edge: the allocation of its pair's path (peers ascending) */
+        if (bw_a)
+            for (int e = 0; e < ne; ++e) {
+                int a = edges[3 * e], b = edges[3 * e + 1];
+                int hi = a > b ? a : b, lo = a > b ? b : a, p = 0;
+                for (int j = 0; j < lo; ++j) p += bwm[(size_t)hi * n + j] != 0;
+                bw_a[e] = (int32_t)paths[(size_t)hi * n + p].bw;
+            }
     }
-    free(bwm); free(host); free(paths); free(npeer); free(ph); free(pbw);
+    free(bwm); free(bwx); free(host); free(ca); free(ra); free(paths); free(npeer); free(ph); free(pbw); free(pbx);
     free(X); free(feas); free(score); free(order); free(tmp);
     return status;
 }
@@ -658,49 +705,110 @@ int or_units(int n, const int32_t *pod, int32_t *unit, int32_t *first) {
 /* or_run_request on the pods of a request.  follow, ref_host, ref_top,
  * ref_gap and dump are per pod (its step); host_out and score_out are per
  * container (the pod's server and score); *failed_at is the first container
- * of the pod that found no server.  Returns as or_run_request, or -1 when a
- * summed demand exceeds the capacity bound 2^22. */
+ * of the pod that found no server.  A pod's interval is the sum of its
+ * containers' minima and maxima, and so is the traffic between two pods.
+ * What a pod is given goes back to its containers in container order: each
+ * first gets its minimum, then the rest up to each one's maximum in turn;
+ * likewise a pod pair's bandwidth over its edges in edge order.  An edge
+ * inside a pod, or between pods on one server, uses no link and gets its
+ * maximum.  Returns as or_run_request, or -1 when a summed demand exceeds
+ * the capacity bound 2^22. */
+static void split_alloc(int64_t a, int cnt, const int *idx, const int32_t *mn, const int32_t *mx, int32_t *out) {
+    for (int x = 0; x < cnt; ++x) { out[idx[x]] = mn[idx[x]]; a -= mn[idx[x]]; }
+    for (int x = 0; x < cnt; ++x) {
+        int64_t room = (int64_t)mx[idx[x]] - mn[idx[x]], t = a < room ? a : room;
+        out[idx[x]] += (int32_t)t; a -= t;
+    }
+}
+
 int or_run_request_pods(or_dc *d, const or_method *m, int n, const int32_t *cpu, const int32_t *ram,
-                        int ne, const int32_t *edges, const int32_t *pod, const int32_t *follow,
+                        int ne, const int32_t *edges, const int32_t *cpu_max, const int32_t *ram_max,
+                        const int32_t *bw_max, const int32_t *pod, const int32_t *follow,
                         int32_t *host_out, double *score_out, int32_t *ref_host, double *ref_top,
-                        double *ref_gap, double *dump, int32_t *failed_at, int64_t *rec_id) {
+                        double *ref_gap, double *dump, int32_t *failed_at, int64_t *rec_id,
+                        int32_t *cpu_a, int32_t *ram_a, int32_t *bw_a) {
     if (n <= 0) return -1;
     int32_t *unit = (int32_t *)malloc(sizeof(int32_t) * n), *first = (int32_t *)malloc(sizeof(int32_t) * n);
     int nu = or_units(n, pod, unit, first);
     int64_t *ucpu = (int64_t *)calloc(nu, sizeof(int64_t)), *uram = (int64_t *)calloc(nu, sizeof(int64_t));
+    int64_t *ucx = (int64_t *)calloc(nu, sizeof(int64_t)), *urx = (int64_t *)calloc(nu, sizeof(int64_t));
     int64_t *ubw = (int64_t *)calloc((size_t)nu * nu, sizeof(int64_t));
+    int64_t *ubx = (int64_t *)calloc((size_t)nu * nu, sizeof(int64_t));
     int32_t *cu = (int32_t *)malloc(sizeof(int32_t) * nu), *ru = (int32_t *)malloc(sizeof(int32_t) * nu);
-    int32_t *ue = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)(nu * (nu - 1) / 2 + 1));
+    int32_t *cux = (int32_t *)malloc(sizeof(int32_t) * nu), *rux = (int32_t *)malloc(sizeof(int32_t) * nu);
+    int32_t *cua = (int32_t *)malloc(sizeof(int32_t) * nu), *rua = (int32_t *)malloc(sizeof(int32_t) * nu);
+    const int mcap = nu * (nu - 1) / 2 + 1;
+    int32_t *ue = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)mcap);
+    int32_t *uex = (int32_t *)malloc(sizeof(int32_t) * (size_t)mcap), *uea = (int32_t *)malloc(sizeof(int32_t) * (size_t)mcap);
     int32_t *hu = (int32_t *)malloc(sizeof(int32_t) * nu);
+    int *idx = (int *)malloc(sizeof(int) * (size_t)(n > ne ? n : ne) + sizeof(int));
     double *su = (double *)calloc(nu, sizeof(double));
     for (int g = 0; g < nu; ++g) hu[g] = -1;
     int st = -1, fu = -1, mu = 0;
-    for (int i = 0; i < n; ++i) { ucpu[unit[i]] += cpu[i]; uram[unit[i]] += ram[i]; }
+    for (int i = 0; i < n; ++i) {
+        int cx = cpu_max ? cpu_max[i] : cpu[i], rx = ram_max ? ram_max[i] : ram[i];
+        if (cx < cpu[i] || rx < ram[i]) goto done;
+        ucpu[unit[i]] += cpu[i]; uram[unit[i]] += ram[i];
+        ucx[unit[i]] += cx; urx[unit[i]] += rx;
+    }
     for (int e = 0; e < ne; ++e) {
-        int a = edges[3 * e], b = edges[3 * e + 1];
-        if (a < 0 || b < 0 || a >= n || b >= n || a == b || edges[3 * e + 2] <= 0) goto done;
+        int a = edges[3 * e], b = edges[3 * e + 1], bx = bw_max ? bw_max[e] : edges[3 * e + 2];
+        if (a < 0 || b < 0 || a >= n || b >= n || a == b || edges[3 * e + 2] <= 0 || bx < edges[3 * e + 2]) goto done;
         a = unit[a]; b = unit[b];
         if (a == b) continue;                       /* inside a pod */
         ubw[(size_t)a * nu + b] += edges[3 * e + 2];
         ubw[(size_t)b * nu + a] += edges[3 * e + 2];
+        ubx[(size_t)a * nu + b] += bx;
+        ubx[(size_t)b * nu + a] += bx;
     }
     for (int g = 0; g < nu; ++g) {
-        if (ucpu[g] > (1 << 22) || uram[g] > (1 << 22)) goto done;
+        if (ucx[g] > (1 << 22) || urx[g] > (1 << 22)) goto done;
         cu[g] = (int32_t)ucpu[g]; ru[g] = (int32_t)uram[g];
+        cux[g] = (int32_t)ucx[g]; rux[g] = (int32_t)urx[g];
         for (int h = g + 1; h < nu; ++h) {
-            int64_t w = ubw[(size_t)g * nu + h];
-            if (w > (1 << 22)) goto done;
-            if (w > 0) { ue[3 * mu] = g; ue[3 * mu + 1] = h; ue[3 * mu + 2] = (int32_t)w; mu++; }
+            int64_t w = ubw[(size_t)g * nu + h], wx = ubx[(size_t)g * nu + h];
+            if (wx > (1 << 22)) goto done;
+            if (w > 0) {
+                ue[3 * mu] = g; ue[3 * mu + 1] = h; ue[3 * mu + 2] = (int32_t)w; uex[mu] = (int32_t)wx; mu++;
+            }
         }
     }
-    st = or_run_request(d, m, nu, cu, ru, mu, ue, follow, hu, su, ref_host, ref_top, ref_gap, dump, &fu, rec_id);
+    st = or_run_request(d, m, nu, cu, ru, mu, ue, cux, rux, uex, follow, hu, su, ref_host, ref_top, ref_gap, dump,
+                        &fu, rec_id, cua, rua, uea);
     for (int i = 0; i < n; ++i) {
         if (host_out) host_out[i] = st == 1 ? hu[unit[i]] : -1;
         if (score_out) score_out[i] = su[unit[i]];
     }
+    if (st == 1) {
+        for (int g = 0; g < nu; ++g) {
+            int cnt = 0;
+            for (int i = 0; i < n; ++i) if (unit[i] == g) idx[cnt++] = i;
+            if (cpu_a) split_alloc(cua[g], cnt, idx, cpu, cpu_max ? cpu_max : cpu, cpu_a);
+            if (ram_a) split_alloc(rua[g], cnt, idx, ram, ram_max ? ram_max : ram, ram_a);
+        }
+        if (bw_a) {
+            int32_t *emin = (int32_t *)malloc(sizeof(int32_t) * (size_t)(ne ? ne : 1));
+            int32_t *emax = (int32_t *)malloc(sizeof(int32_t) * (size_t)(ne ? ne : 1));
+            for (int e = 0; e < ne; ++e) {
+                emin[e] = edges[3 * e + 2]; emax[e] = bw_max ? bw_max[e] : edges[3 * e + 2];
+                bw_a[e] = emax[e];                  /* inside a pod: no link */
+            }
+            for (int q = 0; q < mu; ++q) {
+                int cnt = 0;
+                for (int e = 0; e < ne; ++e) {
+                    int a = unit[edges[3 * e]], b = unit[edges[3 * e + 1]];
+                    if ((a == ue[3 * q] && b == ue[3 * q + 1]) || (b == ue[3 * q] && a == ue[3 * q + 1])) idx[cnt++] = e;
+                }
+                split_alloc(uea[q], cnt, idx, emin, emax, bw_a);
+            }
+            free(emin); free(emax);
+        }
+    }
     if (failed_at) *failed_at = fu < 0 ? -1 : fu < nu ? first[fu] : n;   /* nu: the links did not fit */
 done:
-    free(unit); free(first); free(ucpu); free(uram); free(ubw); free(cu); free(ru); free(ue); free(hu); free(su);
+    free(unit); free(first); free(ucpu); free(uram); free(ucx); free(urx); free(ubw); free(ubx);
+    free(cu); free(ru); free(cux); free(rux); free(cua); free(rua); free(ue); free(uex); free(uea); free(hu);
+    free(idx); free(su);
     return st;
 }
 

@@ -74,11 +74,16 @@ class Instance:
 class Request:
     """A tenant request: n containers with CPU/RAM demands, undirected
     communication edges (i, j, bw) with i < j, and optionally the pod of
-    each container (pod[i] >= 0: its pod id; -1: no pod)."""
+    each container (pod[i] >= 0: its pod id; -1: no pod).  With demand
+    intervals (section II-A) cpu, ram and the edges' bw are the minima and
+    cpu_max, ram_max, bw_max (per edge) the maxima; None means max = min."""
     cpu: np.ndarray     # int32 [n]
     ram: np.ndarray     # int32 [n]
     edges: np.ndarray   # int32 [m][3]
     pod: Optional[np.ndarray] = None   # int32 [n] or None
+    cpu_max: Optional[np.ndarray] = None   # int32 [n] or None
+    ram_max: Optional[np.ndarray] = None   # int32 [n] or None
+    bw_max: Optional[np.ndarray] = None    # int32 [m] or None
 
     @property
     def n(self) -> int:
@@ -164,7 +169,10 @@ def _random_pods(n: int, frac: float, rng: np.random.Generator) -> np.ndarray:
 def make_requests(count: int, rng: np.random.Generator, n_lo: int, n_hi: int,
                   cpu_lo: int = 1, cpu_hi: int = 8, ram_lo: int = 1, ram_hi: int = 32,
                   bw_lo: int = 100, bw_hi: int = 2000, density: float = 0.5,
-                  pod_frac: float = 0.0) -> List[Request]:
+                  pod_frac: float = 0.0, ranges: Optional[str] = None) -> List[Request]:
+    """ranges: None (fixed demands); "widen": the drawn demands are the
+    minima and each maximum is min + U{0..min}; "lower": the drawn demands
+    are the maxima and each minimum is U{1..max}."""
     reqs = []
     for _ in range(count):
         n = int(rng.integers(n_lo, n_hi + 1))
@@ -172,7 +180,22 @@ def make_requests(count: int, rng: np.random.Generator, n_lo: int, n_hi: int,
         ram = rng.integers(ram_lo, ram_hi + 1, size=n).astype(np.int32)
         edges = _random_connected_edges(n, density, rng, bw_lo, bw_hi)
         pod = _random_pods(n, pod_frac, rng) if pod_frac > 0 else None
-        reqs.append(Request(cpu, ram, edges, pod))
+        req = Request(cpu, ram, edges, pod)
+        if ranges == "widen":
+            req.cpu_max = (cpu + rng.integers(0, cpu.astype(np.int64) + 1)).astype(np.int32)
+            req.ram_max = (ram + rng.integers(0, ram.astype(np.int64) + 1)).astype(np.int32)
+            bw = edges[:, 2].astype(np.int64)
+            req.bw_max = (bw + rng.integers(0, bw + 1)).astype(np.int32)
+        elif ranges == "lower":
+            req.cpu_max, req.ram_max = cpu, ram
+            req.cpu = rng.integers(1, cpu.astype(np.int64) + 1).astype(np.int32)
+            req.ram = rng.integers(1, ram.astype(np.int64) + 1).astype(np.int32)
+            req.bw_max = edges[:, 2].copy()
+            req.edges = edges.copy()
+            req.edges[:, 2] = rng.integers(1, edges[:, 2].astype(np.int64) + 1)
+        elif ranges is not None:
+            raise ValueError(f"unknown ranges mode {ranges!r}")
+        reqs.append(req)
     return reqs
 
 
@@ -215,6 +238,13 @@ CONFIGS = {
                       n_req=(20, 20), n=(2, 6), instances=1, pod_frac=0.5),
     "pods":    dict(k=16, caps=(32, 256, 40000, 100000, 100000), background=0.7,
                     n_req=(2000, 2000), n=(2, 32), instances=1, pod_frac=0.5),
+    # demand intervals: each drawn demand is a minimum and its maximum is up
+    # to twice it; 5 Gbps links at k = 4 so that paths, too, run short of
+    # the maxima
+    "tiny_ranges": dict(k=4, caps=(32, 256, 5000, 5000, 5000), background=0.0,
+                        n_req=(20, 20), n=(2, 6), instances=1, ranges="widen"),
+    "ranges":  dict(k=16, caps=(32, 256, 40000, 100000, 100000), background=0.7,
+                    n_req=(2000, 2000), n=(2, 32), instances=1, pod_frac=0.5, ranges="widen"),
 }
 
 
@@ -237,24 +267,27 @@ def make_config(name: str, seed: int = 0, instances: Optional[int] = None,
         else:
             lo, hi = cfg["n_req"] if cfg["n_req"] else (100, 100)
             cnt = int(rng.integers(lo, hi + 1))
-        reqs.append(make_requests(cnt, rng, *cfg["n"], pod_frac=cfg.get("pod_frac", 0.0)))
+        reqs.append(make_requests(cnt, rng, *cfg["n"], pod_frac=cfg.get("pod_frac", 0.0),
+                                  ranges=cfg.get("ranges")))
         insts.append(inst)
     return insts, reqs
 
 
 def make_event_workload(seed: int, k: int = 20, n_req: int = 6000, n: int = 4, total_events: int = 500,
-                        span: int = 250):
+                        span: int = 250, ranges: Optional[str] = "lower"):
     """The shape of the paper's GPU evaluation (section VI-A): a k-ary
     fat-tree of 24-core / 256 GB servers with 1 Gbps links and no other
     load; n_req requests of n containers, up to half of them in pods, up to
     50 Mbps between a pair of containers, CPU up to 2 cores and RAM up to 4
     GB per container.  Each request arrives at a uniform event in
     [0, span) and runs for a uniform 1..span events of a total_events run.
+    Demands are intervals by default (ranges="lower": those bounds are the
+    maxima, the minima uniform below them).
     Returns (instance, requests, arrival events, durations)."""
     rng = _rng(np.random.SeedSequence([seed, 6]))
     inst = make_instance(k, 24, 256, 1000, 1000, 1000)
     reqs = make_requests(n_req, rng, n, n, cpu_lo=1, cpu_hi=2, ram_lo=1, ram_hi=4, bw_lo=1, bw_hi=50,
-                         pod_frac=0.5)
+                         pod_frac=0.5, ranges=ranges)
     arrive = np.sort(rng.integers(0, span, size=n_req))
     dur = rng.integers(1, span + 1, size=n_req)
     assert total_events >= 2 * span
