@@ -191,7 +191,7 @@ def run_batch(args, wl):
     }
     if wl["method"] == "topsis":
         kname = ("k_topsis_batched" if mode == dc.DC_MODE_BATCHED else
-                 "k_topsis_grid" if args.grid == 2 or (args.grid == 0 and insts[0].k >= 32) else "k_topsis_plain")
+                 "k_topsis_grid" if args.grid == 2 else "k_topsis_plain")
         bytes_per_launch = BYTES_PER_HOST_SCORE * hs / per_step_launches
         achieved = bytes_per_launch / avg_launch_s / 1e9
         out["roofline"] = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
@@ -470,10 +470,11 @@ def run_serving(args, wl):
     N = insts[0].n_hosts
     reqs, arr, dep = make_trace(seed=0, duration_s=args.trace_s)
     forms = {}
-    # grid 0: one cooperative workgroup per pod (the default at this size);
-    # grid 1: the single-workgroup step, for comparison
+    # serving: the cooperative persistent kernel (the default at this size);
+    # plain: one launch per container step on one workgroup (the default);
+    # the other two variants for comparison
     variants = (("serving", dc.DC_MODE_SERVING, 0), ("plain", dc.DC_MODE_PLAIN, 0),
-                ("serving_1wg", dc.DC_MODE_SERVING, 1), ("plain_1wg", dc.DC_MODE_PLAIN, 1))
+                ("serving_1wg", dc.DC_MODE_SERVING, 1), ("plain_grid", dc.DC_MODE_PLAIN, 2))
     for name, mode, grid in variants:
         s = dc.Scheduler(insts, mode=mode, grid=grid)
         done, soj, wall = replay(s, dc, reqs, arr, dep, mode == dc.DC_MODE_SERVING, args.trace_s)

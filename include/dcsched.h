@@ -95,8 +95,9 @@ typedef struct dc_config {
     int32_t block;          /* threads per workgroup, 0 = automatic / autotuned     */
     int32_t trace_stride;   /* record the score vector of every trace_stride-th step (0 = off) */
     int32_t trace_cap;      /* at most this many recorded steps                     */
-    int32_t grid;           /* TOPSIS plain and serving forms: 0 = automatic (one
-                               cooperative workgroup per pod from k = 32 on),
+    int32_t grid;           /* TOPSIS plain and serving forms: 0 = automatic (the
+                               serving form from k = 32 on runs one cooperative
+                               workgroup per pod; the plain form one workgroup),
                                1 = one workgroup per step, 2 = one workgroup per pod */
     int32_t graph;          /* batched form: 0 = automatic (on), 1 = launch directly,
                                2 = capture each queued batch's launch in a HIP graph

@@ -959,7 +959,10 @@ int dc_create(const dc_config *cfg, dc_ctx **out) {
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, c->stream, c->d_tcount, 0, (long long)I);
     }
     const bool grid_ok = cfg->method == DC_TOPSIS && cfg->mode != DC_MODE_BATCHED && I == 1;
-    if (grid_ok && (cfg->grid == 2 || (cfg->grid == 0 && k >= 32))) {
+    // automatic: the persistent serving kernel from k = 32 on; per-step
+    // cooperative launches cost more to launch than they save, so the plain
+    // form takes them only when asked (grid = 2)
+    if (grid_ok && (cfg->grid == 2 || (cfg->grid == 0 && k >= 32 && cfg->mode == DC_MODE_SERVING))) {
         if (cfg->grid_timeout_us > 0) c->grid_timeout = 100LL * cfg->grid_timeout_us;   // 100 MHz clock
         const int grc = grid_init(c);
         if (grc) { dc_destroy(ctx.release()); return grc; }
