@@ -149,6 +149,25 @@ int dc_submit_request(dc_ctx *ctx, int32_t instance, int32_t n, const int32_t *c
                       const int32_t *ram, int32_t m, const int32_t *edges,
                       const int32_t *pod, int64_t *req_id);
 
+/* dc_submit_request with demands given as minimum / maximum intervals
+ * (section II-A): a container runs with any CPU and RAM in
+ * [cpu_min[i], cpu_max[i]] and [ram_min[i], ram_max[i]], a pair with any
+ * bandwidth in [edges[q][2], bw_max[q]].  Every feasibility check uses the
+ * minima.  Since the utilities U(i), U(ij) of Eqs. (1)-(2) grow with what is
+ * given, a placement takes as much as the chosen server has left, up to the
+ * maximum, and each routed pair min(maximum, path bottleneck); a pair on
+ * one server (or inside a pod) gets its maximum.  A pod asks for the sums of
+ * its containers' minima and maxima, and two pods' traffic for the sums of
+ * their edges' minima and maxima.  cpu_max, ram_max, bw_max may each be
+ * NULL (maximum = minimum, which is dc_submit_request).  DC_EINVAL when a
+ * maximum is below its minimum or a summed maximum passes 2^22; otherwise
+ * as dc_submit_request.  The caller keeps ownership of every array; they
+ * are copied before the call returns. */
+int dc_submit_request_ranged(dc_ctx *ctx, int32_t instance, int32_t n, const int32_t *cpu_min,
+                             const int32_t *cpu_max, const int32_t *ram_min,
+                             const int32_t *ram_max, int32_t m, const int32_t *edges,
+                             const int32_t *bw_max, const int32_t *pod, int64_t *req_id);
+
 /* Plain and batched forms: schedule every queued request (FCFS per
  * instance) and block until done; results of the scheduled requests go to
  * out[0..*n_out) in request id order (at most max_results are written; the
@@ -177,6 +196,15 @@ int dc_release(dc_ctx *ctx, int64_t req_id);
  * uses no link).  Link id = level*N + index. *n receives the number of
  * pairs; at most cap pairs are written. */
 int dc_get_paths(dc_ctx *ctx, int64_t req_id, int32_t cap, int32_t *link_ids, int32_t *n);
+
+/* What an accepted request was given (section II-A, for the utilities of
+ * Eqs. (1)-(2)): cpu[n], ram[n] per container and bw[m] per edge, in
+ * submission order (each may be NULL).  A pod's CPU and RAM, and the
+ * bandwidth between two pods, go back to its containers (edges) in order:
+ * each first gets its minimum, then what is left up to each one's maximum in
+ * turn.  DC_ENOENT for unknown, pending, rejected or (serving form) released
+ * ids. */
+int dc_get_alloc(dc_ctx *ctx, int64_t req_id, int32_t *cpu, int32_t *ram, int32_t *bw);
 
 /* Servers chosen for each container of a scheduled request, including,
  * for a rejected request, the servers its pods placed before the failing

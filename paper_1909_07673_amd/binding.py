@@ -72,6 +72,9 @@ def lib():
         L.dc_create.argtypes = [C.POINTER(dc_config), C.POINTER(P)]
         L.dc_submit_request.argtypes = [P, C.c_int32, C.c_int32, i32p, i32p, C.c_int32, i32p, i32p,
                                         C.POINTER(C.c_int64)]
+        L.dc_submit_request_ranged.argtypes = [P, C.c_int32, C.c_int32, i32p, i32p, i32p, i32p, C.c_int32, i32p,
+                                               i32p, i32p, C.POINTER(C.c_int64)]
+        L.dc_get_alloc.argtypes = [P, C.c_int64, i32p, i32p, i32p]
         L.dc_schedule.argtypes = [P, C.c_int32, C.POINTER(dc_result), C.POINTER(C.c_int32)]
         L.dc_release.argtypes = [P, C.c_int64]
         L.dc_get_paths.argtypes = [P, C.c_int64, C.c_int32, i32p, C.POINTER(C.c_int32)]
@@ -188,16 +191,33 @@ class Scheduler:
             pass
 
     def submit(self, req, instance: int = 0) -> int:
+        """Queue a request; with any of req.cpu_max, req.ram_max, req.bw_max
+        set its demands are intervals (dc_submit_request_ranged)."""
         cpu, ram = _i32(req.cpu), _i32(req.ram)
         edges = _i32(req.edges).reshape(-1)
         pod = getattr(req, "pod", None)
         pod = _i32(pod) if pod is not None else None
         rid = C.c_int64()
-        _check(lib().dc_submit_request(self._ctx, instance, len(cpu), _p32(cpu), _p32(ram), len(edges) // 3,
-                                       _p32(edges) if len(edges) else None,
-                                       _p32(pod) if pod is not None else None, C.byref(rid)),
-               "dc_submit_request")
+        mx = [getattr(req, k, None) for k in ("cpu_max", "ram_max", "bw_max")]
+        if all(x is None for x in mx):
+            _check(lib().dc_submit_request(self._ctx, instance, len(cpu), _p32(cpu), _p32(ram), len(edges) // 3,
+                                           _p32(edges) if len(edges) else None,
+                                           _p32(pod) if pod is not None else None, C.byref(rid)),
+                   "dc_submit_request")
+            return rid.value
+        cx, rx, bx = (None if x is None else _i32(x) for x in mx)
+        opt = lambda a: _p32(a) if a is not None and len(a) else None
+        _check(lib().dc_submit_request_ranged(self._ctx, instance, len(cpu), _p32(cpu), opt(cx), _p32(ram), opt(rx),
+                                              len(edges) // 3, opt(edges), opt(bx), opt(pod), C.byref(rid)),
+               "dc_submit_request_ranged")
         return rid.value
+
+    def alloc(self, req_id: int, n: int, m: int):
+        """What accepted request req_id (n containers, m edges) was given:
+        (cpu[n], ram[n], bw[m])."""
+        cpu, ram, bw = np.zeros(n, np.int32), np.zeros(n, np.int32), np.zeros(max(m, 1), np.int32)
+        _check(lib().dc_get_alloc(self._ctx, req_id, _p32(cpu), _p32(ram), _p32(bw)), "dc_get_alloc")
+        return cpu, ram, bw[:m]
 
     def schedule(self, max_results: int = 1 << 20) -> List[Result]:
         out = []

@@ -355,7 +355,7 @@ __device__ bool grid_topsis_step(const Topo &t, const State &st, const Method &m
                 // uses the global state
                 Smem cs;
                 cs.pk = sm.pk;
-                const bool ok = commit_wave(t, st, u, s.cpu, s.ram, m.route_end ? 0 : P, cs, b.code + s.p0, lane);
+                const bool ok = commit_wave(t, st, b, u, s, m.route_end ? 0 : P, cs, b.pbmax + s.p0, lane);
                 if (lane == 0) {
                     sm.misc[M_ROUTE + 1] = ok;
                     if (ok) {
@@ -416,7 +416,7 @@ __global__ __launch_bounds__(BS) void k_serve_grid(Params p, ServeArgs a, GridCt
     const GSmem sm = gcarve(dsm, p.t.h, p.t.hh, p.m.nc);
     int *rq_host = grid_req_lds(dsm, p.t.h, p.t.hh, p.m.nc);
     int *rq_cpu = rq_host + kMaxN, *rq_ram = rq_cpu + kMaxN, *rq_poff = rq_ram + kMaxN;
-    int *rq_pj = rq_poff + kMaxN + 4, *rq_pbw = rq_pj + kMaxPairs;
+    int *rq_pj = rq_poff + kMaxN + 4, *rq_pbw = rq_pj + kMaxPairs, *rq_pbmax = rq_pbw + kMaxPairs;
     const bool lead = blockIdx.x == 0;
     int pos = a.start;
     long long idle0 = dev_clock();
@@ -475,6 +475,7 @@ __global__ __launch_bounds__(BS) void k_serve_grid(Params p, ServeArgs a, GridCt
             for (int x = threadIdx.x; x < P; x += BS) {
                 rq_pj[x] = stg[L.pj + x];
                 rq_pbw[x] = stg[L.pbw + x];
+                rq_pbmax[x] = stg[L.pbmax + x];
                 if (lead) sb[L.code + x] = -1;
             }
             if (lead && threadIdx.x == 0) {
@@ -484,8 +485,8 @@ __global__ __launch_bounds__(BS) void k_serve_grid(Params p, ServeArgs a, GridCt
             __syncthreads();
             for (int i = 0; i < n; ++i) {
                 const int q0 = rq_poff[i];
-                const StepIn s{0, i, n, 0, i, q0, rq_poff[i + 1] - q0, rq_cpu[i], rq_ram[i]};
-                const ReqView rv{rq_pj + q0, rq_pbw + q0, rq_host, rq_host};
+                const StepIn s{0, i, n, 0, i, q0, rq_poff[i + 1] - q0, rq_cpu[i], rq_ram[i], b.cmax[i], b.rmax[i]};
+                const ReqView rv{rq_pj + q0, rq_pbw + q0, rq_host, rq_host, rq_pbmax + q0};
                 if (!grid_topsis_step<BS>(p.t, p.st, p.m, b, sm, g, timeout, s, rv, p.tr)) {
                     fault = __hip_atomic_load(g.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
                     break;

@@ -23,7 +23,8 @@ struct Params {
     float *rowpart;  // [nc][nJ][N]
     int ti, tj, nI, nJ;
     StepIn s;        // the container step of a plain launch
-    int pj[kMaxN], pbw[kMaxN];   // its placed peers (container index, demand)
+    int pj[kMaxN], pbw[kMaxN];   // its placed peers (container index, minimum demand)
+    int pbmax[kMaxN];            // and their maximum demands
 };
 
 constexpr int kAhpBlock = 256;
@@ -75,7 +76,7 @@ __device__ __forceinline__ void stage_out(int *g, const int *lds, int n) {
 // The plain form passes the container's peer list in the kernel arguments,
 // so only the peers' servers are read from memory.
 __device__ __forceinline__ ReqView plain_view(const Params &p) {
-    return ReqView{p.pj, p.pbw, p.b.host + p.s.g0, nullptr};
+    return ReqView{p.pj, p.pbw, p.b.host + p.s.g0, nullptr, p.pbmax};
 }
 
 // One launch per container step, one workgroup.  With RES the instance's
@@ -310,9 +311,9 @@ __global__ __launch_bounds__(BS) void k_ahp_select(Params p) {
 
 // ---------------------------------------------------------------- batched form
 // LDS ints of the request prefetch of the batched form: hosts, cpu, ram
-// (kMaxN each), relative peer offsets (kMaxN + 4), peers and demands
-// (kMaxPairs each).
-__host__ __device__ inline size_t req_lds_ints() { return 4 * (size_t)kMaxN + 4 + 2 * (size_t)kMaxPairs; }
+// (kMaxN each), relative peer offsets (kMaxN + 4), peers, minimum and
+// maximum demands (kMaxPairs each).
+__host__ __device__ inline size_t req_lds_ints() { return 4 * (size_t)kMaxN + 4 + 3 * (size_t)kMaxPairs; }
 
 // One persistent workgroup per data-center instance: the instance's state,
 // the per-server scratch and the request being scheduled live in LDS for
@@ -328,7 +329,7 @@ __global__ __launch_bounds__(BS) void k_topsis_batched(Params p) {
     int *ls = xs + (size_t)xs_rows(p.m.nc) * N;
     int *rq_host = ls + 6 * (size_t)N;
     int *rq_cpu = rq_host + kMaxN, *rq_ram = rq_cpu + kMaxN, *rq_poff = rq_ram + kMaxN;
-    int *rq_pj = rq_poff + kMaxN + 4, *rq_pbw = rq_pj + kMaxPairs;
+    int *rq_pj = rq_poff + kMaxN + 4, *rq_pbw = rq_pj + kMaxPairs, *rq_pbmax = rq_pbw + kMaxPairs;
     const State gs = state_at(p.state_base, p.state_stride, inst, N);
     stage_in<BS>(ls, gs.cpu, 6 * N);
     const State st{ls, ls + N, ls + 2 * N, ls + 3 * N, ls + 4 * N, ls + 5 * N};
@@ -347,12 +348,14 @@ __global__ __launch_bounds__(BS) void k_topsis_batched(Params p) {
         for (int x = threadIdx.x; x < npair; x += BS) {
             rq_pj[x] = p.b.pj[pb + x];
             rq_pbw[x] = p.b.pbw[pb + x];
+            rq_pbmax[x] = p.b.pbmax[pb + x];
         }
         __syncthreads();
         for (int i = 0; i < n; ++i) {
             const int q0 = rq_poff[i];
-            const StepIn s{r, i, n, g0, g0 + i, pb + q0, rq_poff[i + 1] - q0, rq_cpu[i], rq_ram[i]};
-            const ReqView rv{rq_pj + q0, rq_pbw + q0, rq_host, rq_host};
+            const StepIn s{r, i, n, g0, g0 + i, pb + q0, rq_poff[i + 1] - q0, rq_cpu[i], rq_ram[i],
+                           p.b.cmax[g0 + i], p.b.rmax[g0 + i]};
+            const ReqView rv{rq_pj + q0, rq_pbw + q0, rq_host, rq_host, rq_pbmax + q0};
             // one server per thread at 1024 threads keeps the loop in registers
             if (!topsis_step<BS, BS >= 1024 ? 1 : host_group(BS), true>(p.t, st, p.m, p.b, sm, xs, p.pc_cap, p.tr, inst,
                                                                   s, rv))

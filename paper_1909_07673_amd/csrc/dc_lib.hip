@@ -22,6 +22,14 @@ using namespace dcs;
 
 namespace {
 
+// A request's containers and edges as submitted, kept so that what each
+// unit and unit pair is given can be handed back to them.
+struct Members {
+    std::vector<int> cpu, cmax, ram, rmax;   // per container: demand intervals
+    std::vector<int> emin, emax;             // per edge: bandwidth interval
+    std::vector<int> epair;                  // per edge: the unit pair carrying it (unit CSR index), -1 inside a unit
+};
+
 // A request as the device schedules it.  Containers of a pod share one
 // server (section II-A, Eq. (8)), so the unit of placement is the pod: one
 // unit per pod, in the order of each pod's first container (a container
@@ -30,26 +38,34 @@ namespace {
 // containers exchange traffic with g's, each with the summed demand: the two
 // pods sit on one server each, so their links share one route.  Traffic
 // inside a pod needs no network.  Without pods every container is a unit
-// and its peers are the earlier containers it talks to.
+// and its peers are the earlier containers it talks to.  Demands are
+// intervals (section II-A); minima and maxima are summed separately.
 struct Units {
     int n = 0;                         // containers
-    std::vector<int> cpu, ram;         // per unit
-    std::vector<int> poff, pj, pbw;    // peers of each unit (CSR), ascending unit index
+    std::vector<int> cpu, ram;         // per unit, minima
+    std::vector<int> cmax, rmax;       // per unit, maxima
+    std::vector<int> poff, pj, pbw;    // peers of each unit (CSR), ascending unit index, minimum demand
+    std::vector<int> pbmax;            // maximum demand of each peer pair
     std::vector<int> unit_of;          // container -> unit
     std::vector<int> first;            // unit -> its smallest container index
+    Members mem;
     int nu() const { return (int)cpu.size(); }
 };
 
 // Builds the units of a validated request; DC_EINVAL when a summed demand
 // reaches past the 2^22 bound of capacities.  pod[i] >= 0 names container
 // i's pod (equal ids, same pod); pod[i] < 0 or pod == NULL: no pod.
-int build_units(int n, const int *cpu, const int *ram, int m, const int *edges, const int *pod, Units &u) {
+// cpu_max, ram_max, bw_max (per edge) are the maxima, or NULL for fixed
+// demands.
+int build_units(int n, const int *cpu, const int *cpu_max, const int *ram, const int *ram_max, int m,
+                const int *edges, const int *bw_max, const int *pod, Units &u) {
     constexpr long long kCap = 1LL << 22;
     u = Units{};
     u.n = n;
     u.unit_of.assign(n, -1);
-    std::vector<long long> uc, ur;
+    std::vector<long long> uc, ur, ucx, urx;
     std::map<int, int> pod_unit;
+    Members &M = u.mem;
     for (int i = 0; i < n; ++i) {
         int g = -1;
         if (pod && pod[i] >= 0) {
@@ -62,35 +78,91 @@ int build_units(int n, const int *cpu, const int *ram, int m, const int *edges, 
         if (g == (int)uc.size()) {
             uc.push_back(0);
             ur.push_back(0);
+            ucx.push_back(0);
+            urx.push_back(0);
             u.first.push_back(i);
         }
         u.unit_of[i] = g;
+        M.cpu.push_back(cpu[i]);
+        M.ram.push_back(ram[i]);
+        M.cmax.push_back(cpu_max ? cpu_max[i] : cpu[i]);
+        M.rmax.push_back(ram_max ? ram_max[i] : ram[i]);
         uc[g] += cpu[i];
         ur[g] += ram[i];
+        ucx[g] += M.cmax.back();
+        urx[g] += M.rmax.back();
     }
     const int nu = (int)uc.size();
     for (int g = 0; g < nu; ++g) {
-        if (uc[g] > kCap || ur[g] > kCap) return DC_EINVAL;
+        if (ucx[g] > kCap || urx[g] > kCap) return DC_EINVAL;
         u.cpu.push_back((int)uc[g]);
         u.ram.push_back((int)ur[g]);
+        u.cmax.push_back((int)ucx[g]);
+        u.rmax.push_back((int)urx[g]);
     }
-    std::vector<long long> bw((size_t)nu * nu, 0);
+    std::vector<long long> bw((size_t)nu * nu, 0), bwx((size_t)nu * nu, 0);
     for (int q = 0; q < m; ++q) {
         const int a = u.unit_of[edges[3 * q]], b = u.unit_of[edges[3 * q + 1]];
+        M.emin.push_back(edges[3 * q + 2]);
+        M.emax.push_back(bw_max ? bw_max[q] : edges[3 * q + 2]);
         if (a == b) continue;
         bw[(size_t)a * nu + b] += edges[3 * q + 2];
         bw[(size_t)b * nu + a] += edges[3 * q + 2];
+        bwx[(size_t)a * nu + b] += M.emax.back();
+        bwx[(size_t)b * nu + a] += M.emax.back();
     }
+    std::vector<int> pidx((size_t)nu * nu, -1);
     u.poff.assign(1, 0);
     for (int g = 0; g < nu; ++g) {
         for (int h = 0; h < g; ++h) {
-            const long long w = bw[(size_t)g * nu + h];
-            if (w > kCap) return DC_EINVAL;
-            if (w > 0) { u.pj.push_back(h); u.pbw.push_back((int)w); }
+            const long long w = bw[(size_t)g * nu + h], wx = bwx[(size_t)g * nu + h];
+            if (wx > kCap) return DC_EINVAL;
+            if (w > 0) {
+                pidx[(size_t)g * nu + h] = pidx[(size_t)h * nu + g] = (int)u.pj.size();
+                u.pj.push_back(h);
+                u.pbw.push_back((int)w);
+                u.pbmax.push_back((int)wx);
+            }
         }
         u.poff.push_back((int)u.pj.size());
     }
+    for (int q = 0; q < m; ++q)
+        M.epair.push_back(pidx[(size_t)u.unit_of[edges[3 * q]] * nu + u.unit_of[edges[3 * q + 1]]]);
     return DC_OK;
+}
+
+// Hands the allocation a of a unit (or unit pair) back to its members who[]
+// in order: each first gets its minimum, then what is left goes up to each
+// one's maximum in turn.
+void hand_back(long long a, const std::vector<int> &who, const std::vector<int> &mn, const std::vector<int> &mx,
+               int32_t *out) {
+    for (int x : who) { out[x] = mn[x]; a -= mn[x]; }
+    for (int x : who) {
+        const long long t = std::min<long long>(a, (long long)mx[x] - mn[x]);
+        out[x] += (int32_t)t;
+        a -= t;
+    }
+}
+
+// Allocations per container and per edge from those of the units (ua_cpu,
+// ua_ram, nu entries) and unit pairs (pa, relative to the request's first
+// pair).  An edge inside a unit uses no link and gets its maximum.
+void members_alloc(const Members &M, const std::vector<int> &unit_of, int nu, const int *ua_cpu,
+                   const int *ua_ram, const int *pa, int32_t *cpu, int32_t *ram, int32_t *bw) {
+    const int n = (int)M.cpu.size(), m = (int)M.emin.size();
+    std::vector<std::vector<int>> who(nu);
+    for (int i = 0; i < n; ++i) who[unit_of[i]].push_back(i);
+    for (int g = 0; g < nu; ++g) {
+        if (cpu) hand_back(ua_cpu[g], who[g], M.cpu, M.cmax, cpu);
+        if (ram) hand_back(ua_ram[g], who[g], M.ram, M.rmax, ram);
+    }
+    if (!bw) return;
+    std::map<int, std::vector<int>> by_pair;
+    for (int q = 0; q < m; ++q) {
+        if (M.epair[q] < 0) bw[q] = M.emax[q];
+        else by_pair[M.epair[q]].push_back(q);
+    }
+    for (const auto &kv : by_pair) hand_back(pa[kv.first], kv.second, M.emin, M.emax, bw);
 }
 
 // One uploaded set of requests (the pending queue at a dc_schedule call).
@@ -101,6 +173,9 @@ struct DevBatch {
     Batch view{};
     std::vector<int64_t> ids;      // request id per batch request
     std::vector<int> inst, coff, poff, pj, pbw, cpu, ram, iroff;   // unit level (coff: units per request)
+    std::vector<int> cmax, rmax, pbmax;                            // unit level maxima
+    std::vector<Members> mem;                                      // per request
+    size_t o_alloc = 0;                                            // output offset of cpua, rama, pbwa
     std::vector<int> cnt, cuoff, unit_of, first;                   // containers per request, their units, first containers
     std::vector<int> host, status, failat;
     std::vector<float> score;
@@ -125,6 +200,7 @@ struct ServeSlot {
     int n = 0, P = 0;              // units and peer pairs as the device sees them
     int nc = 0;                    // containers
     std::vector<int> unit_of, first;
+    Members mem;
     int status = -1;               // -1 pending, 1 accepted, 0 rejected
     bool released = false;
     std::vector<int> hosts;        // attempt record from the completion
@@ -355,11 +431,15 @@ int upload_pending(dc_ctx *ctx) {
         for (int g = 0; g < U.nu(); ++g) {
             b.cpu.push_back(U.cpu[g]);
             b.ram.push_back(U.ram[g]);
+            b.cmax.push_back(U.cmax[g]);
+            b.rmax.push_back(U.rmax[g]);
             b.first.push_back(U.first[g]);
             b.poff.push_back(pbase + U.poff[g + 1]);
         }
         b.pj.insert(b.pj.end(), U.pj.begin(), U.pj.end());
         b.pbw.insert(b.pbw.end(), U.pbw.begin(), U.pbw.end());
+        b.pbmax.insert(b.pbmax.end(), U.pbmax.begin(), U.pbmax.end());
+        b.mem.push_back(std::move(ctx->pend_units[idx].mem));
         b.coff.push_back((int)b.cpu.size());
         b.cnt.push_back(U.n);
         b.unit_of.insert(b.unit_of.end(), U.unit_of.begin(), U.unit_of.end());
@@ -368,10 +448,13 @@ int upload_pending(dc_ctx *ctx) {
     for (int i = 0; i < ctx->I; ++i) b.iroff[i + 1] += b.iroff[i];
     b.Ct = (int)b.cpu.size();
     b.Pt = (int)b.pj.size();
-    // device layout: inputs coff, cpu, ram, poff, pj, pbw, iroff; outputs
-    size_t n_in = (size_t)(b.R + 1) + 2 * b.Ct + (b.Ct + 1) + 2 * (size_t)b.Pt + (b.I + 1) + b.R;
+    // device layout: inputs coff, cpu, ram, poff, pj, pbw, iroff, rid, cmax,
+    // rmax, pbmax; outputs host, code, failat, status, score, stamps, then
+    // the allocations cpua, rama, pbwa
+    size_t n_in = (size_t)(b.R + 1) + 2 * b.Ct + (b.Ct + 1) + 2 * (size_t)b.Pt + (b.I + 1) + b.R + 2 * b.Ct + b.Pt;
     n_in += n_in & 1;   // keeps the int64 stamps in the output region 8-byte aligned
-    const size_t n_out = (size_t)b.Ct + b.Pt + b.R + b.R + b.Ct + 1 + 4 * (size_t)b.R;
+    b.o_alloc = (size_t)b.Ct + b.Pt + b.R + b.R + b.Ct + 1 + 4 * (size_t)b.R;
+    const size_t n_out = b.o_alloc + 2 * (size_t)b.Ct + b.Pt;
     b.in_ints = n_in;
     b.out_ints = n_out;
     std::vector<int> img(n_in, 0);
@@ -387,6 +470,9 @@ int upload_pending(dc_ctx *ctx) {
     std::vector<int> rid32(b.R);
     for (int r = 0; r < b.R; ++r) rid32[r] = (int)(b.ids[r] & 0x7fffffff);
     const size_t o_rid = o; put(rid32);
+    const size_t o_cmax = o; put(b.cmax);
+    const size_t o_rmax = o; put(b.rmax);
+    const size_t o_pbmax = o; put(b.pbmax);
     HIPCHK(hipMalloc(&b.dmem, (n_in + n_out) * sizeof(int)));
     HIPCHK(hipMemcpyAsync(b.dmem, img.data(), n_in * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
     int *d = b.dmem;
@@ -399,6 +485,12 @@ int upload_pending(dc_ctx *ctx) {
     b.view.pbw = d + o_pbw;
     b.view.iroff = d + o_iroff;
     b.view.rid = d + o_rid;
+    b.view.cmax = d + o_cmax;
+    b.view.rmax = d + o_rmax;
+    b.view.pbmax = d + o_pbmax;
+    b.view.cpua = out + b.o_alloc;
+    b.view.rama = out + b.o_alloc + b.Ct;
+    b.view.pbwa = out + b.o_alloc + 2 * b.Ct;
     b.view.host = out;
     b.view.code = out + b.Ct;
     b.view.failat = out + b.Ct + b.Pt;
@@ -458,10 +550,11 @@ int run_plain(dc_ctx *ctx, DevBatch &b) {
         const int g0 = b.coff[r], n = b.coff[r + 1] - g0;
         for (int i = 0; i < n; ++i) {
             const int g = g0 + i;
-            p.s = StepIn{r, i, n, g0, g, b.poff[g], b.poff[g + 1] - b.poff[g], b.cpu[g], b.ram[g]};
+            p.s = StepIn{r, i, n, g0, g, b.poff[g], b.poff[g + 1] - b.poff[g], b.cpu[g], b.ram[g], b.cmax[g], b.rmax[g]};
             for (int q = 0; q < p.s.P; ++q) {
                 p.pj[q] = b.pj[p.s.p0 + q];
                 p.pbw[q] = b.pbw[p.s.p0 + q];
+                p.pbmax[q] = b.pbmax[p.s.p0 + q];
             }
             switch (ctx->plain_bs) {
             case 64: launch_plain_step<64>(ctx, p); break;
@@ -536,7 +629,7 @@ int run_batched(dc_ctx *ctx, DevBatch &b, int bs) {
 // The route codes stay on the device; dc_get_paths fetches the few it needs.
 int collect(dc_ctx *ctx, DevBatch &b) {
     const int *dout = b.dmem + b.in_ints;
-    const size_t tail0 = (size_t)b.Ct + b.Pt, tail = b.out_ints - tail0;
+    const size_t tail0 = (size_t)b.Ct + b.Pt, tail = b.o_alloc - tail0;   // the allocations stay on the device
     if (!b.pinned) HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&b.pinned), (b.Ct + tail) * sizeof(int), 0));
     int *out = b.pinned;
     HIPCHK(hipMemcpyAsync(out, dout, (size_t)b.Ct * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
@@ -762,9 +855,12 @@ int serve_submit(dc_ctx *ctx, Units &U, int64_t *req_id) {
     std::memcpy(stg + L.cpu, cpu, sizeof(int) * n);
     std::memcpy(stg + L.ram, ram, sizeof(int) * n);
     std::memcpy(stg + L.poff, poff.data(), sizeof(int) * (n + 1));
+    std::memcpy(stg + L.cmax, U.cmax.data(), sizeof(int) * n);
+    std::memcpy(stg + L.rmax, U.rmax.data(), sizeof(int) * n);
     if (P) {
         std::memcpy(stg + L.pj, pj.data(), sizeof(int) * P);
         std::memcpy(stg + L.pbw, pbw.data(), sizeof(int) * P);
+        std::memcpy(stg + L.pbmax, U.pbmax.data(), sizeof(int) * P);
     }
     stg[L.rid] = rid;
     ServeSlot sl;
@@ -775,7 +871,8 @@ int serve_submit(dc_ctx *ctx, Units &U, int64_t *req_id) {
     sl.nc = U.n;
     sl.unit_of = std::move(U.unit_of);
     sl.first = std::move(U.first);
-    sv.slots[id] = sl;
+    sl.mem = std::move(U.mem);
+    sv.slots[id] = std::move(sl);
     sv.rid_to_id[rid] = id;
     serve_publish(sv, CMD_SUBMIT, n, P, off, rid);
     if (req_id) *req_id = id;
@@ -982,23 +1079,29 @@ int dc_create(const dc_config *cfg, dc_ctx **out) {
     return DC_OK;
 }
 
-int dc_submit_request(dc_ctx *ctx, int32_t instance, int32_t n, const int32_t *cpu, const int32_t *ram,
-                      int32_t m, const int32_t *edges, const int32_t *pod, int64_t *req_id) {
+int dc_submit_request_ranged(dc_ctx *ctx, int32_t instance, int32_t n, const int32_t *cpu_min,
+                             const int32_t *cpu_max, const int32_t *ram_min, const int32_t *ram_max, int32_t m,
+                             const int32_t *edges, const int32_t *bw_max, const int32_t *pod, int64_t *req_id) {
     if (!ctx) return DC_EINVAL;
     if (ctx->poisoned) return DC_EDEVICE;
-    if (instance < 0 || instance >= ctx->I || n < 1 || n > DC_MAX_CONTAINERS || !cpu || !ram) return DC_EINVAL;
+    if (instance < 0 || instance >= ctx->I || n < 1 || n > DC_MAX_CONTAINERS || !cpu_min || !ram_min) return DC_EINVAL;
     if (m < 0 || m > n * (n - 1) / 2 || (m > 0 && !edges)) return DC_EINVAL;
+    constexpr int kCap = 1 << 22;
     std::vector<char> seen((size_t)n * n, 0);
     for (int q = 0; q < m; ++q) {
         const int i = edges[3 * q], j = edges[3 * q + 1], bw = edges[3 * q + 2];
-        if (i < 0 || j < 0 || i >= n || j >= n || i == j || bw <= 0 || bw > (1 << 22)) return DC_EINVAL;
+        const int bx = bw_max ? bw_max[q] : bw;
+        if (i < 0 || j < 0 || i >= n || j >= n || i == j || bw <= 0 || bx < bw || bx > kCap) return DC_EINVAL;
         if (seen[(size_t)i * n + j]) return DC_EINVAL;
         seen[(size_t)i * n + j] = seen[(size_t)j * n + i] = 1;
     }
-    for (int i = 0; i < n; ++i)
-        if (cpu[i] < 0 || ram[i] < 0 || cpu[i] > (1 << 22) || ram[i] > (1 << 22)) return DC_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        const int cx = cpu_max ? cpu_max[i] : cpu_min[i], rx = ram_max ? ram_max[i] : ram_min[i];
+        if (cpu_min[i] < 0 || ram_min[i] < 0 || cx < cpu_min[i] || rx < ram_min[i] || cx > kCap || rx > kCap)
+            return DC_EINVAL;
+    }
     Units U;
-    const int urc = build_units(n, cpu, ram, m, edges, pod, U);
+    const int urc = build_units(n, cpu_min, cpu_max, ram_min, ram_max, m, edges, bw_max, pod, U);
     if (urc) return urc;
     if (ctx->sv) return serve_submit(ctx, U, req_id);
     ctx->pend_inst.push_back(instance);
@@ -1007,6 +1110,11 @@ int dc_submit_request(dc_ctx *ctx, int32_t instance, int32_t n, const int32_t *c
     ctx->pend_ids.push_back(id);
     if (req_id) *req_id = id;
     return DC_OK;
+}
+
+int dc_submit_request(dc_ctx *ctx, int32_t instance, int32_t n, const int32_t *cpu, const int32_t *ram,
+                      int32_t m, const int32_t *edges, const int32_t *pod, int64_t *req_id) {
+    return dc_submit_request_ranged(ctx, instance, n, cpu, nullptr, ram, nullptr, m, edges, nullptr, pod, req_id);
 }
 
 int dc_schedule(dc_ctx *ctx, int32_t max_results, dc_result *out, int32_t *n_out) {
@@ -1111,6 +1219,40 @@ int dc_get_paths(dc_ctx *ctx, int64_t req_id, int32_t cap, int32_t *link_ids, in
             if (u != v && c >= 0) host_path_links(ctx->t, u, v, c, dst);
         }
     if (n) *n = q;
+    return DC_OK;
+}
+
+int dc_get_alloc(dc_ctx *ctx, int64_t req_id, int32_t *cpu, int32_t *ram, int32_t *bw) {
+    if (!ctx) return DC_EINVAL;
+    if (ctx->sv) {
+        auto sit = ctx->sv->slots.find(req_id);
+        if (sit == ctx->sv->slots.end() || sit->second.status != 1 || sit->second.released) return DC_ENOENT;
+        const ServeSlot &sl = sit->second;
+        std::vector<int> slot(sl.ints);
+        HIPCHK(hipMemcpyAsync(slot.data(), ctx->sv->arena + sl.off, sl.ints * sizeof(int), hipMemcpyDeviceToHost,
+                              ctx->sv->aux));
+        HIPCHK(hipStreamSynchronize(ctx->sv->aux));
+        const SlotLayout L = slot_layout(sl.n, sl.P);
+        members_alloc(sl.mem, sl.unit_of, sl.n, slot.data() + L.cpua, slot.data() + L.rama, slot.data() + L.pbwa,
+                      cpu, ram, bw);
+        return DC_OK;
+    }
+    auto it = ctx->loc.find(req_id);
+    if (it == ctx->loc.end()) return DC_ENOENT;
+    DevBatch &b = *ctx->batches[it->second.batch];
+    const int r = it->second.r;
+    if ((int)b.status.size() <= r || b.status[r] != 1) return DC_ENOENT;
+    const int g0 = b.coff[r], nu = b.coff[r + 1] - g0;
+    const int x0 = b.poff[g0], nx = b.poff[g0 + nu] - x0;
+    std::vector<int> ua(2 * (size_t)nu + std::max(nx, 1));
+    HIPCHK(hipMemcpyAsync(ua.data(), b.view.cpua + g0, nu * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ua.data() + nu, b.view.rama + g0, nu * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    if (nx > 0)
+        HIPCHK(hipMemcpyAsync(ua.data() + 2 * nu, b.view.pbwa + x0, nx * sizeof(int), hipMemcpyDeviceToHost,
+                              ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    const std::vector<int> uo(b.unit_of.begin() + b.cuoff[r], b.unit_of.begin() + b.cuoff[r + 1]);
+    members_alloc(b.mem[r], uo, nu, ua.data(), ua.data() + nu, ua.data() + 2 * nu, cpu, ram, bw);
     return DC_OK;
 }
 

@@ -28,8 +28,8 @@ struct Comp {
 // Layout of a request slot, in int32 units: inputs (copied from the
 // staging area) then outputs.
 struct SlotLayout {
-    int coff, cpu, ram, poff, pj, pbw, rid, in_end;
-    int host, code, failat, status, score, ts, total;
+    int coff, cpu, ram, poff, pj, pbw, cmax, rmax, pbmax, rid, in_end;
+    int host, code, failat, status, score, cpua, rama, pbwa, ts, total;
 };
 
 __host__ __device__ inline SlotLayout slot_layout(int n, int P) {
@@ -41,6 +41,9 @@ __host__ __device__ inline SlotLayout slot_layout(int n, int P) {
     L.poff = o; o += n + 1;
     L.pj = o; o += P;
     L.pbw = o; o += P;
+    L.cmax = o; o += n;
+    L.rmax = o; o += n;
+    L.pbmax = o; o += P;
     L.rid = o; o += 1;
     L.in_end = o;
     L.host = o; o += n;
@@ -48,6 +51,9 @@ __host__ __device__ inline SlotLayout slot_layout(int n, int P) {
     L.failat = o; o += 1;
     L.status = o; o += 1;
     L.score = o; o += n;
+    L.cpua = o; o += n;
+    L.rama = o; o += n;
+    L.pbwa = o; o += P;
     o += o & 1;
     L.ts = o; o += 4;               // tsb, tse (int64)
     L.total = o;
@@ -62,6 +68,12 @@ __device__ __forceinline__ Batch slot_batch(int *sb, const SlotLayout &L) {
     b.poff = sb + L.poff;
     b.pj = sb + L.pj;
     b.pbw = sb + L.pbw;
+    b.cmax = sb + L.cmax;
+    b.rmax = sb + L.rmax;
+    b.pbmax = sb + L.pbmax;
+    b.cpua = sb + L.cpua;
+    b.rama = sb + L.rama;
+    b.pbwa = sb + L.pbwa;
     b.host = sb + L.host;
     b.score = reinterpret_cast<float *>(sb + L.score);
     b.code = sb + L.code;
@@ -90,7 +102,7 @@ __global__ __launch_bounds__(BS) void k_serve(Params p, ServeArgs a) {
     Smem sm = carve(dsm, p.pc_cap, p.t.nsw);
     int *rq_host = lds_after_tables(dsm, p.pc_cap, p.t.nsw);
     int *rq_cpu = rq_host + kMaxN, *rq_ram = rq_cpu + kMaxN, *rq_poff = rq_ram + kMaxN;
-    int *rq_pj = rq_poff + kMaxN + 4, *rq_pbw = rq_pj + kMaxPairs;
+    int *rq_pj = rq_poff + kMaxN + 4, *rq_pbw = rq_pj + kMaxPairs, *rq_pbmax = rq_pbw + kMaxPairs;
     __shared__ int cmdv[8];
     int pos = a.start;
     long long idle0 = dev_clock();
@@ -142,6 +154,7 @@ __global__ __launch_bounds__(BS) void k_serve(Params p, ServeArgs a) {
             for (int x = threadIdx.x; x < P; x += BS) {
                 rq_pj[x] = stg[L.pj + x];
                 rq_pbw[x] = stg[L.pbw + x];
+                rq_pbmax[x] = stg[L.pbmax + x];
                 sb[L.code + x] = -1;
             }
             if (threadIdx.x == 0) {
@@ -151,8 +164,8 @@ __global__ __launch_bounds__(BS) void k_serve(Params p, ServeArgs a) {
             __syncthreads();
             for (int i = 0; i < n; ++i) {
                 const int q0 = rq_poff[i];
-                const StepIn s{0, i, n, 0, i, q0, rq_poff[i + 1] - q0, rq_cpu[i], rq_ram[i]};
-                const ReqView rv{rq_pj + q0, rq_pbw + q0, rq_host, rq_host};
+                const StepIn s{0, i, n, 0, i, q0, rq_poff[i + 1] - q0, rq_cpu[i], rq_ram[i], b.cmax[i], b.rmax[i]};
+                const ReqView rv{rq_pj + q0, rq_pbw + q0, rq_host, rq_host, rq_pbmax + q0};
                 if (!topsis_step<BS, BS >= 1024 ? 1 : host_group(BS)>(p.t, p.st, p.m, b, sm, p.xs, p.pc_cap, p.tr, 0,
                                                                       s, rv))
                     break;

@@ -11,6 +11,7 @@
 //   section V-C             TOPSIS
 //   section V-D             widest shortest path, one residual per undirected link
 //   Eqs. (4)-(5)            capacity and bandwidth constraints
+//   section II-A, Eqs. (1)-(2)  demand intervals [min, max] and their utilities
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -54,9 +55,15 @@ struct Method {
 
 // Requests of one schedule call, CSR layout.  Container g of request r is
 // coff[r] + i; its placed peers are pj[poff[g]..poff[g+1]) (container index
-// within the request, ascending) with demands pbw[].
+// within the request, ascending) with demands pbw[].  Demands are intervals
+// (section II-A): cpu, ram, pbw are the minima, cmax, rmax, pbmax the
+// maxima (equal for fixed demands); cpua, rama, pbwa receive what each
+// container and pair was given, which is what a release gives back.
 struct Batch {
     const int *coff, *cpu, *ram, *poff, *pj, *pbw;
+    const int *cmax, *rmax, *pbmax;
+    int *cpua, *rama;  // [Ct] allocated CPU and RAM
+    int *pbwa;         // [Pt] allocated bandwidth
     int *host;      // [Ct] chosen server, -1 until placed
     float *score;   // [Ct] score of the chosen server
     int *code;      // [Pt] path choice per peer pair, -1 when co-located
@@ -72,7 +79,8 @@ struct StepIn {
     int r, i, n;       // request (batch index), container index, containers of the request
     int g0, g;         // global index of the request's container 0 and of this container
     int p0, P;         // first peer pair of this container and number of placed peers
-    int cpu, ram;      // demand
+    int cpu, ram;      // demand (minimum)
+    int cmax, rmax;    // demand maximum
 };
 
 // Where a step reads its request data: the container's peer list (P
@@ -81,6 +89,7 @@ struct StepIn {
 struct ReqView {
     const int *pj, *pbw, *hosts;
     int *hosts_out;    // LDS copy of hosts to update (batched form), or nullptr
+    const int *pbmax;  // the peers' maximum demands
 };
 
 // Constant-rate device clock (100 MHz), read without a memory access.
@@ -112,7 +121,7 @@ struct Smem {
     int4 *pk;                         // [kMaxN] packed peer: server, edge | pod << 16, demand, uplink residual
     int *wst;                         // [kStatFields][kMaxWaves] per-wave column statistics
     unsigned *ahi, *alo;              // [2][kMaxWaves] per-wave argmax keys (alternating per retry)
-    int *ph, *pbw;                    // [kMaxN] peer server, demand
+    int *ph, *pbw;                    // [kMaxN] peer server, maximum demand
     int *capP;                        // [kMaxPods] summed aggregation-core residual per pod
     int *misc;                        // [M_MISC]
     int *capE;                        // [nsw] summed edge-aggregation residual per edge switch
@@ -247,11 +256,6 @@ __device__ __forceinline__ unsigned widest_wave(const Topo &t, const State &st, 
     return wave_umax(best);
 }
 
-// Commit container (cpu_i, ram_i) on server u with its P placed peers
-// (servers ph[], demands pbw[], ascending container index): route each
-// remote peer on its widest shortest path under the current residuals,
-// failing when a bottleneck is below the demand (Eqs. (4)-(5)).  On failure
-// every change is undone.  Run by one whole wave; lane 0 writes.
 // Lanes 0..5 each update one link of the path (its links are distinct).
 template <bool ATOMIC>
 __device__ __forceinline__ void path_apply_lanes(const Topo &t, const State &st, int u, int v, int c, int delta,
@@ -265,11 +269,23 @@ __device__ __forceinline__ void path_apply_lanes(const Topo &t, const State &st,
     }
 }
 
-__device__ __forceinline__ bool commit_wave(const Topo &t, const State &st, int u, int cpu_i, int ram_i, int P,
-                                            const Smem &sm, int *code_out, int lane) {
-    if (st.cpu[u] < cpu_i || st.ram[u] < ram_i) return false;
+// Commit of container s on server u with its P placed peers (servers and
+// minimum demands in the LDS peer list, ascending container index): route
+// each remote peer on its widest shortest path under the current residuals,
+// failing when a bottleneck is below the minimum demand (Eqs. (4)-(5)).  A
+// container runs with anything in its demand interval and its utility
+// (Eqs. (1)-(2)) grows with what it gets, so each peer pair takes
+// min(max, bottleneck) of its path, and CPU and RAM min(max, residual) of
+// the server; a peer on the same server needs no link and gets its maximum.
+// On failure every change is undone.  Run by one whole wave; lane 0 writes
+// the server's resources, lane p peer p's route code and allocation.
+// pbmax[p]: peer p's maximum demand (LDS or global).
+__device__ __forceinline__ bool commit_wave(const Topo &t, const State &st, const Batch &b, int u, const StepIn &s,
+                                            int P, const Smem &sm, const int *pbmax, int lane) {
+    const int pmax = lane < P ? pbmax[lane] : 0;
+    if (st.cpu[u] < s.cpu || st.ram[u] < s.ram) return false;
     const int eu = fdiv(u, t.rh), pu = fdiv(u, t.rhh);
-    int routed = 0, mycode = -1;       // lane p keeps peer p's path choice
+    int routed = 0, mycode = -1, mine = pmax;   // lane p keeps peer p's path choice and allocation
     bool ok = true;
     for (int p = 0; p < P; ++p) {
         const int4 pk = sm.pk[p];
@@ -279,34 +295,45 @@ __device__ __forceinline__ bool commit_wave(const Topo &t, const State &st, int 
             continue;
         }
         const unsigned best = widest_wave(t, st, u, v, eu, pu, pk.y & 0xffff, pk.y >> 16, lane);
-        const int b = static_cast<int>(best >> 10);
+        const int bn = static_cast<int>(best >> 10);
         const int c = 1023 - static_cast<int>(best & 1023u);
-        if (b < pk.z) { ok = false; break; }
-        path_apply_lanes<false>(t, st, u, v, c, -pk.z, lane);
+        if (bn < pk.z) { ok = false; break; }
+        const int a = min(max(__builtin_amdgcn_readlane(pmax, p), pk.z), bn);
+        path_apply_lanes<false>(t, st, u, v, c, -a, lane);
         mycode = lane == p ? c : mycode;
+        mine = lane == p ? a : mine;
         __threadfence_block();
         routed = p + 1;
     }
     if (!ok) {
         for (int p = routed - 1; p >= 0; --p) {
             const int4 pk = sm.pk[p];
-            if (pk.x != u) path_apply_lanes<false>(t, st, u, pk.x, __builtin_amdgcn_readlane(mycode, p), pk.z, lane);
+            if (pk.x != u)
+                path_apply_lanes<false>(t, st, u, pk.x, __builtin_amdgcn_readlane(mycode, p),
+                                        __builtin_amdgcn_readlane(mine, p), lane);
             __threadfence_block();
         }
         return false;
     }
-    if (lane < P) code_out[lane] = mycode;
+    if (lane < P) {
+        b.code[s.p0 + lane] = mycode;
+        b.pbwa[s.p0 + lane] = mine;
+    }
     if (lane == 0) {
-        st.cpu[u] -= cpu_i;
-        st.ram[u] -= ram_i;
+        const int ca = max(s.cpu, min(s.cmax, st.cpu[u])), ra = max(s.ram, min(s.rmax, st.ram[u]));
+        st.cpu[u] -= ca;
+        st.ram[u] -= ra;
         st.npl[u] += 1;
+        b.cpua[s.g] = ca;
+        b.rama[s.g] = ra;
     }
     __threadfence_block();
     return true;
 }
 
-// Gives back containers [0, upto) of request r: CPU, RAM, placed count and
-// the demand of every routed peer pair.  Block-wide, with atomics.
+// Gives back containers [0, upto) of request r: the CPU and RAM they were
+// given, the placed count and the allocation of every routed peer pair.
+// Block-wide, with atomics.
 template <int BS>
 __device__ void give_back(const Topo &t, const State &st, const Batch &b, int r, int upto) {
     const int g0 = b.coff[r];
@@ -321,12 +348,12 @@ __device__ void give_back(const Topo &t, const State &st, const Batch &b, int r,
         const int u = b.host[lo];
         const int v = b.host[g0 + b.pj[q]];
         const int c = b.code[q];
-        if (u != v && c >= 0) path_apply<true>(t, st, u, v, c, b.pbw[q]);
+        if (u != v && c >= 0) path_apply<true>(t, st, u, v, c, b.pbwa[q]);
     }
     for (int i = threadIdx.x; i < upto; i += BS) {
         const int u = b.host[g0 + i];
-        atomicAdd(st.cpu + u, b.cpu[g0 + i]);
-        atomicAdd(st.ram + u, b.ram[g0 + i]);
+        atomicAdd(st.cpu + u, b.cpua[g0 + i]);
+        atomicAdd(st.ram + u, b.rama[g0 + i]);
         atomicSub(st.npl + u, 1);
     }
 }
@@ -419,7 +446,7 @@ __device__ __forceinline__ void load_peers(const Topo &t, const State &st, const
         const int v = rv.hosts[rv.pj[p]];
         const int bw = rv.pbw[p];
         sm.ph[p] = v;
-        sm.pbw[p] = bw;
+        sm.pbw[p] = rv.pbmax[p];
         sm.pk[p] = make_int4(v, fdiv(v, t.rh) | (fdiv(v, t.rhh) << 16), bw, st.up[v]);
     }
     if (threadIdx.x < 6) sm.misc[M_DH0 + threadIdx.x] = (threadIdx.x & 1) ? -1 : kBig;
@@ -741,9 +768,10 @@ __device__ __forceinline__ int trace_slot(const Trace &tr, int inst, int rid, in
 // Routing after the last unit of request r is placed (section V-D, with
 // Method::route_end): every routed pair's widest minimum-hop path is chosen
 // on the residuals the placement left, all pairs independently (one wave per
-// unit's pairs); then every demand is taken off its links at once.  If a
-// link goes negative the request does not fit: everything it took is given
-// back and it is rejected with failed_at = n.  host(g) is the server of unit
+// unit's pairs), each asking min(max, bottleneck) but at least its minimum;
+// then all of it is taken off the links at once.  If a link goes negative
+// the request does not fit: everything it took is given back and it is
+// rejected with failed_at = n.  host(g) is the server of unit
 // g (u for the unit just placed).  Returns true when the request was
 // accepted.
 template <int BS, class HostFn>
@@ -759,12 +787,16 @@ __device__ bool route_request_end(const Topo &t, const State &st, const Batch &b
         const int u = host(g), eu = fdiv(u, t.rh), pu = fdiv(u, t.rhh);
         for (int x = b.poff[s.g0 + g]; x < b.poff[s.g0 + g + 1]; ++x) {
             const int v = host(b.pj[x]);
-            int c = -1;
+            int c = -1, a = b.pbmax[x];
             if (v != u) {
                 const unsigned best = widest_wave(t, st, u, v, eu, pu, fdiv(v, t.rh), fdiv(v, t.rhh), lane);
                 c = 1023 - static_cast<int>(best & 1023u);
+                a = max(b.pbw[x], min(a, static_cast<int>(best >> 10)));
             }
-            if (lane == 0) b.code[x] = c;
+            if (lane == 0) {
+                b.code[x] = c;
+                b.pbwa[x] = a;
+            }
         }
     }
     __threadfence();
@@ -773,7 +805,7 @@ __device__ bool route_request_end(const Topo &t, const State &st, const Batch &b
         const int u = host(g);
         for (int x = b.poff[s.g0 + g]; x < b.poff[s.g0 + g + 1]; ++x) {
             const int c = b.code[x];
-            if (c >= 0) path_apply_lanes<true>(t, st, u, host(b.pj[x]), c, -b.pbw[x], lane);
+            if (c >= 0) path_apply_lanes<true>(t, st, u, host(b.pj[x]), c, -b.pbwa[x], lane);
         }
     }
     __threadfence();
@@ -847,7 +879,7 @@ __device__ bool select_commit(const Topo &t, const State &st, const Batch &b, co
         }
         const int u = static_cast<int>(~static_cast<unsigned>(kb & 0xffffffffu));
         if (threadIdx.x < kWave) {
-            const bool ok = commit_wave(t, st, u, s.cpu, s.ram, m_route_end ? 0 : s.P, sm, b.code + s.p0, lane);
+            const bool ok = commit_wave(t, st, b, u, s, m_route_end ? 0 : s.P, sm, sm.pbw, lane);
             if (lane == 0) {
                 sm.misc[M_OK] = ok;
                 if (ok) {

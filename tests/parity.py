@@ -42,13 +42,15 @@ def check_scores(gpu, ref, tol=TOL, where=""):
 
 
 def lockstep(o, sched, ids, reqs, results, tol=TOL, trace=None, check_paths=False, state_every=False,
-             instance=0, final_state=True):
+             instance=0, final_state=True, check_alloc=False):
     """Replays `reqs` (submitted to `sched` with ids `ids`, results keyed by
     id) on oracle `o` in lockstep, one step per pod (per container without
     pods).  trace: optional dict (request id -> list of (step, gpu score
     vector)).  state_every: compare the
     integer state after each request (only meaningful when the GPU has
     scheduled exactly these requests so far, one schedule call each).
+    check_alloc: what each accepted request's containers and edges were
+    given must equal the oracle's allocations bit for bit.
     Returns statistics."""
     st = dict(requests=0, accepted=0, rejected=0, steps=0, near_tie=0, scored_steps=0, rec_ids=[])
     for pos, (rid, req) in enumerate(zip(ids, reqs)):
@@ -85,6 +87,11 @@ def lockstep(o, sched, ids, reqs, results, tol=TOL, trace=None, check_paths=Fals
             assert got.shape == want.shape
             for a, b in zip(got, want):
                 assert sorted(a.tolist()) == sorted(b.tolist())
+        if check_alloc and g.status == 1:
+            ca, ra, ba = sched.alloc(rid, req.n, req.m)
+            np.testing.assert_array_equal(ca, ref["cpu_a"], err_msg=f"request {pos}: cpu allocation")
+            np.testing.assert_array_equal(ra, ref["ram_a"], err_msg=f"request {pos}: ram allocation")
+            np.testing.assert_array_equal(ba, ref["bw_a"], err_msg=f"request {pos}: bandwidth allocation")
         if state_every:
             np.testing.assert_array_equal(sched.state(instance), o.state(), err_msg=f"after request {pos}")
         st["rec_ids"].append(ref["rec_id"])

@@ -243,6 +243,8 @@ CONFIGS = {
     # the maxima
     "tiny_ranges": dict(k=4, caps=(32, 256, 5000, 5000, 5000), background=0.0,
                         n_req=(20, 20), n=(2, 6), instances=1, ranges="widen"),
+    "tiny_ranges_pods": dict(k=4, caps=(32, 256, 5000, 5000, 5000), background=0.0,
+                             n_req=(20, 20), n=(2, 6), instances=1, pod_frac=0.5, ranges="widen"),
     "ranges":  dict(k=16, caps=(32, 256, 40000, 100000, 100000), background=0.7,
                     n_req=(2000, 2000), n=(2, 32), instances=1, pod_frac=0.5, ranges="widen"),
 }
