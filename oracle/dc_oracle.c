@@ -457,15 +457,27 @@ int or_step_scores(or_dc *d, const or_method *m, int cpu_i, int ram_i, int P,
 /* (4)-(5)).                                                               */
 /*                                                                          */
 /* Demand intervals (section II-A): a container runs with any amount in    */
-/* [min, max] and its utility (Eqs. (1)-(2)) grows with the amount, so a   */
-/* placement takes as much as the server has left, up to the maximum:      */
-/* min(max, residual) of CPU and of RAM, and min(max, bottleneck) on each   */
-/* peer path.  A peer on the same server needs no link and gets its max.   */
-/* Fixed demands are the case min = max.                                    */
+/* [min, max] and its utility (Eqs. (1)-(2)) grows with the amount.  The   */
+/* commit first fits every minimum as above (so whether a server fits does */
+/* not depend on the maxima); then CPU and RAM take min(max, residual), and */
+/* each routed peer path, in peer order, tops its pair up by what the path */
+/* still has, to at most the maximum.  A peer on the same server needs no  */
+/* link and gets its maximum.  Fixed demands are the case min = max.       */
 /* ------------------------------------------------------------------ */
 typedef struct { int nl; int link[6]; int64_t bw; } or_path;
 
 static int64_t min64(int64_t a, int64_t b) { return a < b ? a : b; }
+
+/* Tops path p up from its minimum towards its maximum with what its most
+ * loaded link still has. */
+static void top_up(or_dc *d, or_path *pp, int64_t max) {
+    if (pp->nl == 0 || pp->bw >= max) return;
+    int64_t room = max - pp->bw;
+    for (int l = 0; l < pp->nl; ++l) room = min64(room, d->link_res[pp->link[l]]);
+    if (room <= 0) return;
+    for (int l = 0; l < pp->nl; ++l) d->link_res[pp->link[l]] -= room;
+    pp->bw += room;
+}
 
 static int try_commit(or_dc *d, int u, int cpu_i, int cpu_x, int ram_i, int ram_x, int P, const int *ph,
                       const int *pbw, const int *pbx, or_path *paths, int *cpu_a, int *ram_a) {
@@ -478,7 +490,7 @@ static int try_commit(or_dc *d, int u, int cpu_i, int cpu_x, int ram_i, int ram_
         or_widest_enum(d, u, ph[p], &b, links, &hops);
         if (b < pbw[p]) { ok = 0; break; }
         paths[p].nl = hops;
-        paths[p].bw = min64(pbx[p], b);
+        paths[p].bw = pbw[p];
         for (int l = 0; l < hops; ++l) { paths[p].link[l] = links[l]; d->link_res[links[l]] -= paths[p].bw; }
         routed = p + 1;
     }
@@ -487,6 +499,7 @@ static int try_commit(or_dc *d, int u, int cpu_i, int cpu_x, int ram_i, int ram_
             for (int l = 0; l < paths[p].nl; ++l) d->link_res[paths[p].link[l]] += paths[p].bw;
         return 0;
     }
+    for (int p = 0; p < P; ++p) top_up(d, paths + p, pbx[p]);
     *cpu_a = (int)min64(cpu_x, d->cpu_res[u]);
     *ram_a = (int)min64(ram_x, d->ram_res[u]);
     d->cpu_res[u] -= *cpu_a; d->ram_res[u] -= *ram_a; d->nplaced[u] += 1;
@@ -604,10 +617,9 @@ int or_run_request(or_dc *d, const or_method *m, int n, const int32_t *cpu, cons
     }
     if (status == 1 && m->route_end) {
         /* every pair's widest minimum-hop path on the residuals the placement
-         * left, each pair on its own, taking min(max, bottleneck) but at
-         * least the minimum; then all of it at once, and the request fits
-         * only if no link goes negative (a pair whose bottleneck is below
-         * its minimum drives that link negative) */
+         * left, each pair on its own; then all minima at once, and the
+         * request fits only if no link goes negative; then each pair, in
+         * order, is topped up towards its maximum */
         for (int i = 0; i < n; ++i) {
             int P = 0;
             for (int j = 0; j < i; ++j) {
@@ -618,7 +630,7 @@ int or_run_request(or_dc *d, const or_method *m, int n, const int32_t *cpu, cons
                     int64_t b; int32_t links[6], hops;
                     or_widest_enum(d, host[i], host[j], &b, links, &hops);
                     pp->nl = hops;
-                    pp->bw = b < bwm[(size_t)i * n + j] ? bwm[(size_t)i * n + j] : min64(b, bwx[(size_t)i * n + j]);
+                    pp->bw = bwm[(size_t)i * n + j];
                     for (int l = 0; l < hops; ++l) pp->link[l] = links[l];
                 }
                 P++;
@@ -633,6 +645,12 @@ int or_run_request(or_dc *d, const or_method *m, int n, const int32_t *cpu, cons
             }
         for (int e = 0; e < 3 * N; ++e) if (d->link_res[e] < 0) fits = 0;
         if (!fits) { status = 0; fail_i = n; }
+        else
+            for (int i = 0; i < n; ++i) {
+                int P = 0;
+                for (int j = 0; j < i; ++j)
+                    if (bwm[(size_t)i * n + j]) top_up(d, paths + (size_t)i * n + P++, bwx[(size_t)i * n + j]);
+            }
     }
     if (status != 1) {
         for (int i = fail_i - 1; i >= 0; --i)

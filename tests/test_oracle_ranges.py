@@ -1,8 +1,9 @@
 """Pins for the oracle's demand intervals (section II-A: every container and
 container pair asks for a minimum and a maximum; the utilities U(i), U(ij)
 of Eqs. (1)-(2) measure what it is given).  Reading: feasibility and every
-capacity check use the minima; a placement gives as much as the chosen
-server or path has left, up to the maximum.  Everything here runs on the
+capacity check use the minima; once the minima fit, a placement gives as
+much as the chosen server has left, up to the maximum, and tops each routed
+path up in peer order the same way.  Everything here runs on the
 CPU and checks the oracle against hand cases, the reduction to fixed demands
 and invariants computed independently of it."""
 import numpy as np
@@ -104,13 +105,17 @@ def test_hand_bandwidth(oracle_lib):
         assert x["status"] == 1 and x["bw_a"].tolist() == [600]
 
 
-def test_hand_route_end_takes_maxima_independently(oracle_lib):
+def test_hand_route_end_minima_then_top_ups(oracle_lib):
     """k=4: containers 1 and 2 on server 4 each ask [600, 1400] Mbps to
     container 0 on server 0; core (0, 0)'s aggregation-core links hold 1500,
     the other cores' 1000.  Routed at each placement, the first pair takes
-    1400 over core (0, 0) and the second 1000 over core (0, 1).  Routed at
-    the end, both pairs see 1500 over core (0, 0), take 1400 each and
-    overdraw it: rejected with failed_at = n, nothing taken."""
+    its 600 over core (0, 0) and tops up to 1400; the second then finds core
+    (0, 1) widest (1000), takes 600 and tops up by the 400 left: 1000.
+    Routed at the end, both pairs pick core (0, 0) on the residuals the
+    placement left; the two minima (1200) fit its 1500, and the top-ups in
+    order give the first pair the 300 left: 900 and 600.  With minima of
+    800 each (1600 > 1500) the request is rejected with failed_at = n and
+    nothing taken."""
     inst = make_instance(4, 32, 256, 40000, 10000, 1000)
     r = _req([1, 1, 1], [1, 1, 1], [[0, 1, 600], [0, 2, 600]], bw_max=[1400, 1400])
     for route_end in (False, True):
@@ -119,15 +124,26 @@ def test_hand_route_end_takes_maxima_independently(oracle_lib):
         o.set_link(2 * 16 + 4, 1500)
         s0 = o.state().copy()
         x = o.run_request(r, follow=np.array([0, 4, 4], np.int32))
+        assert x["status"] == 1
+        links, bws = o.paths(x["rec_id"])
+        got = [sorted(int(l) for l in p if l >= 0) for p in links]
         if not route_end:
-            assert x["status"] == 1 and x["bw_a"].tolist() == [1400, 1000]
-            links, bws = o.paths(x["rec_id"])
-            assert [sorted(int(l) for l in p if l >= 0) for p in links] == [[0, 4, 16, 20, 32, 36],
-                                                                             [0, 4, 16, 20, 33, 37]]
-            assert bws.tolist() == [1400, 1000]
+            assert x["bw_a"].tolist() == [1400, 1000] and bws.tolist() == [1400, 1000]
+            assert got == [[0, 4, 16, 20, 32, 36], [0, 4, 16, 20, 33, 37]]
         else:
+            assert x["bw_a"].tolist() == [900, 600] and bws.tolist() == [900, 600]
+            assert got == [[0, 4, 16, 20, 32, 36], [0, 4, 16, 20, 32, 36]]
+            assert o.state()[5][0] == 0 and o.state()[5][4] == 0
+        o2 = O.Oracle(inst, O.method(route_end=route_end))
+        o2.set_link(2 * 16 + 0, 1500)
+        o2.set_link(2 * 16 + 4, 1500)
+        x = o2.run_request(_req([1, 1, 1], [1, 1, 1], [[0, 1, 800], [0, 2, 800]], bw_max=[1400, 1400]),
+                           follow=np.array([0, 4, 4], np.int32))
+        if route_end:
             assert x["status"] == 0 and x["failed_at"] == 3
-            np.testing.assert_array_equal(o.state(), s0)
+            np.testing.assert_array_equal(o2.state(), s0)
+        else:
+            assert x["status"] == 1 and x["bw_a"].tolist() == [1400, 1000]
 
 
 def test_pod_split_in_container_order(oracle_lib):
