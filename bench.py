@@ -53,11 +53,16 @@ WORKLOADS = {
                       text="k=16 fat-tree (1024 hosts), 2000 FCFS requests of 2-32 containers, 0-70% background, "
                            "TOPSIS, links routed after each request's last container (one wave per pair on the "
                            "residuals the placement left), plain form (one launch per container step)"),
+    "ranges": dict(preset="ranges", mode="plain", method="topsis",
+                   text="k=16 fat-tree (1024 hosts), 2000 FCFS requests of 2-32 containers with up to half in pods "
+                        "and demands as [min, 2 x min] intervals (each placement given up to the maximum), 0-70% "
+                        "background, TOPSIS, plain form (one launch per pod step)"),
     "paper_e2": dict(preset=None, mode="events", method="topsis",
                      text="the paper's GPU evaluation shape (section VI-A): k=20 fat-tree (2000 servers of 24 cores / "
-                          "256 GB, 1 Gbps links), 6000 requests of 4 containers (up to half in pods, up to 50 Mbps "
-                          "per pair) arriving over 250 of 500 events and running 1-250 events; discrete-event "
-                          "replay, waiting requests retried in FCFS order at every event; TOPSIS (Flat), plain form"),
+                          "256 GB, 1 Gbps links), 6000 requests of 4 containers (up to half in pods, demands as "
+                          "intervals up to 2 cores, 4 GB and 50 Mbps per pair) arriving over 250 of 500 events and "
+                          "running 1-250 events; discrete-event replay, waiting requests retried in FCFS order at "
+                          "every event; TOPSIS (Flat), plain form"),
     "paper_e2_ahp": dict(preset=None, mode="events", method="ahp",
                          text="as paper_e2 with AHP (Saaty 1-9, Flat weights)"),
     "tiles": dict(preset=None, mode="tiles", method="topsis",
@@ -335,7 +340,8 @@ def run_tiles(args, wl):
 
 # Table V of the paper (TOPSIS / AHP, Flat weights): runtime for the whole
 # 6000-request workload on its (unnamed) GPU, and simulation events needed.
-PAPER_TABLE5 = {"topsis": {"runtime_s": 3.67, "events": 894}, "ahp": {"runtime_s": 9.45, "events": 949}}
+PAPER_TABLE5 = {"topsis": {"runtime_s": 3.67, "events": 894, "U_ij": 1.0, "U_i": 0.9885},
+                "ahp": {"runtime_s": 9.45, "events": 949, "U_ij": 1.0, "U_i": 0.9822}}
 
 
 def run_events(args, wl):
@@ -343,8 +349,10 @@ def run_events(args, wl):
     their resources, the arrivals join the waiting queue, and every waiting
     request is submitted in FCFS order; the ones that do not fit wait for
     the next event.  Reports the events needed to place every request, the
-    provisioning delay, and the server / link fragmentation (share of active
-    servers and of links carrying traffic) averaged over the events."""
+    provisioning delay, the server / link fragmentation (share of active
+    servers and of links carrying traffic) averaged over the events, and the
+    mean utilities U(i), U(ij) (Eqs. (1)-(2)) of what the requests were
+    given, read after the timed replay."""
     import numpy as np
     import torch
     import paper_1909_07673_amd as dc
@@ -358,6 +366,7 @@ def run_events(args, wl):
     cap_links = np.array([inst.bw_host_edge, inst.bw_edge_agg, inst.bw_agg_core], np.int64)[:, None]
     buf = np.zeros(len(reqs), dc.RESULT_DTYPE)
     placed = np.full(len(reqs), -1)
+    acc_id = np.full(len(reqs), -1, np.int64)
     queue, ends = [], {}
     nxt = ev = steps = tries = 0
     frag_s, frag_l = [], []
@@ -378,6 +387,7 @@ def run_events(args, wl):
                 steps += _pod_steps(reqs[q], int(r["status"]), int(r["failed_at"]))
                 if r["status"] == 1:
                     placed[q] = ev
+                    acc_id[q] = rid
                     ends.setdefault(ev + int(dur[q]), []).append(rid)
                 else:
                     still.append(q)
@@ -389,6 +399,14 @@ def run_events(args, wl):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     delay = placed - arrive
+    u_i, u_ij = [], []
+    for q, req in enumerate(reqs):
+        ca, ra, ba = s.alloc(int(acc_id[q]), req.n, req.m)
+        cx = req.cpu if req.cpu_max is None else req.cpu_max
+        rx = req.ram if req.ram_max is None else req.ram_max
+        bx = req.edges[:, 2] if req.bw_max is None else req.bw_max
+        u_i.extend(((ca / cx + ra / rx) / 2).tolist())
+        u_ij.extend((ba / bx).tolist())
     s.close()
     out = {
         "metric": METRIC, "value": steps * N / wall, "unit": "host-scores/s", "n_gpus": 1, "steps": 1,
@@ -400,7 +418,8 @@ def run_events(args, wl):
         "delay_events": {"mean": float(delay.mean()), "p99": float(np.percentile(delay, 99)),
                          "max": int(delay.max())},
         "fragmentation": {"servers": float(np.mean(frag_s)), "links": float(np.mean(frag_l))},
-        "utility": {"U_i": 1.0, "U_ij": 1.0, "note": "single-valued demands: each container gets its maximum"},
+        "utility": {"U_i": float(np.mean(u_i)), "U_ij": float(np.mean(u_ij)),
+                    "note": "mean over containers / container pairs of allocated over maximum"},
         "paper_table5": dict(PAPER_TABLE5[wl["method"]], hardware="unnamed GPU, CUDA 10.1; runtime includes "
                                                                    "the paper's simulator"),
     }

@@ -271,15 +271,16 @@ __device__ __forceinline__ void path_apply_lanes(const Topo &t, const State &st,
 
 // Commit of container s on server u with its P placed peers (servers and
 // minimum demands in the LDS peer list, ascending container index): route
-// each remote peer on its widest shortest path under the current residuals,
-// failing when a bottleneck is below the minimum demand (Eqs. (4)-(5)).  A
-// container runs with anything in its demand interval and its utility
-// (Eqs. (1)-(2)) grows with what it gets, so each peer pair takes
-// min(max, bottleneck) of its path, and CPU and RAM min(max, residual) of
-// the server; a peer on the same server needs no link and gets its maximum.
-// On failure every change is undone.  Run by one whole wave; lane 0 writes
-// the server's resources, lane p peer p's route code and allocation.
-// pbmax[p]: peer p's maximum demand (LDS or global).
+// each remote peer's minimum on its widest shortest path under the current
+// residuals, failing when a bottleneck is below it (Eqs. (4)-(5)); on
+// failure every change is undone.  A container runs with anything in its
+// demand interval and its utility (Eqs. (1)-(2)) grows with what it gets,
+// so once the minima fit, each routed path in peer order is topped up by
+// what its most loaded link still has, to at most the pair's maximum, and
+// CPU and RAM take min(max, residual) of the server; a peer on the same
+// server needs no link and gets its maximum.  Run by one whole wave; lane 0
+// writes the server's resources, lane p peer p's route code and
+// allocation.  pbmax[p]: peer p's maximum demand (LDS or global).
 __device__ __forceinline__ bool commit_wave(const Topo &t, const State &st, const Batch &b, int u, const StepIn &s,
                                             int P, const Smem &sm, const int *pbmax, int lane) {
     const int pmax = lane < P ? pbmax[lane] : 0;
@@ -298,22 +299,35 @@ __device__ __forceinline__ bool commit_wave(const Topo &t, const State &st, cons
         const int bn = static_cast<int>(best >> 10);
         const int c = 1023 - static_cast<int>(best & 1023u);
         if (bn < pk.z) { ok = false; break; }
-        const int a = min(max(__builtin_amdgcn_readlane(pmax, p), pk.z), bn);
-        path_apply_lanes<false>(t, st, u, v, c, -a, lane);
+        path_apply_lanes<false>(t, st, u, v, c, -pk.z, lane);
         mycode = lane == p ? c : mycode;
-        mine = lane == p ? a : mine;
+        mine = lane == p ? pk.z : mine;
         __threadfence_block();
         routed = p + 1;
     }
     if (!ok) {
         for (int p = routed - 1; p >= 0; --p) {
             const int4 pk = sm.pk[p];
-            if (pk.x != u)
-                path_apply_lanes<false>(t, st, u, pk.x, __builtin_amdgcn_readlane(mycode, p),
-                                        __builtin_amdgcn_readlane(mine, p), lane);
+            if (pk.x != u) path_apply_lanes<false>(t, st, u, pk.x, __builtin_amdgcn_readlane(mycode, p), pk.z, lane);
             __threadfence_block();
         }
         return false;
+    }
+    // top-ups, only over the routed peers with room (none for fixed
+    // demands); a lane always reads the links it alone writes (slot x of
+    // every path from u is a link in the same role)
+    const int4 mypk = lane < P ? sm.pk[lane] : make_int4(u, 0, 0, 0);
+    for (unsigned long long todo = __ballot(mypk.x != u && pmax > mypk.z); todo; todo &= todo - 1) {
+        const int p = __builtin_ctzll(todo);
+        const int v = __builtin_amdgcn_readlane(mypk.x, p);
+        const int room = __builtin_amdgcn_readlane(pmax, p) - __builtin_amdgcn_readlane(mypk.z, p);
+        const int c = __builtin_amdgcn_readlane(mycode, p);
+        const int *l = lane < 6 ? path_link(t, st, u, v, c, lane) : nullptr;
+        const int add = min(room, wave_min(l ? *l : kBig));
+        if (add <= 0) continue;
+        path_apply_lanes<false>(t, st, u, v, c, -add, lane);
+        mine = lane == p ? mine + add : mine;
+        __threadfence_block();
     }
     if (lane < P) {
         b.code[s.p0 + lane] = mycode;
@@ -768,10 +782,11 @@ __device__ __forceinline__ int trace_slot(const Trace &tr, int inst, int rid, in
 // Routing after the last unit of request r is placed (section V-D, with
 // Method::route_end): every routed pair's widest minimum-hop path is chosen
 // on the residuals the placement left, all pairs independently (one wave per
-// unit's pairs), each asking min(max, bottleneck) but at least its minimum;
-// then all of it is taken off the links at once.  If a link goes negative
-// the request does not fit: everything it took is given back and it is
-// rejected with failed_at = n.  host(g) is the server of unit
+// unit's pairs); then every minimum demand is taken off its links at once.
+// If a link goes negative the request does not fit: everything it took is
+// given back and it is rejected with failed_at = n.  Otherwise wave 0 tops
+// each pair up, in pair order, by what its most loaded link still has, to
+// at most the pair's maximum.  host(g) is the server of unit
 // g (u for the unit just placed).  Returns true when the request was
 // accepted.
 template <int BS, class HostFn>
@@ -787,15 +802,14 @@ __device__ bool route_request_end(const Topo &t, const State &st, const Batch &b
         const int u = host(g), eu = fdiv(u, t.rh), pu = fdiv(u, t.rhh);
         for (int x = b.poff[s.g0 + g]; x < b.poff[s.g0 + g + 1]; ++x) {
             const int v = host(b.pj[x]);
-            int c = -1, a = b.pbmax[x];
+            int c = -1;
             if (v != u) {
                 const unsigned best = widest_wave(t, st, u, v, eu, pu, fdiv(v, t.rh), fdiv(v, t.rhh), lane);
                 c = 1023 - static_cast<int>(best & 1023u);
-                a = max(b.pbw[x], min(a, static_cast<int>(best >> 10)));
             }
             if (lane == 0) {
                 b.code[x] = c;
-                b.pbwa[x] = a;
+                b.pbwa[x] = c >= 0 ? b.pbw[x] : b.pbmax[x];
             }
         }
     }
@@ -821,7 +835,27 @@ __device__ bool route_request_end(const Topo &t, const State &st, const Batch &b
         }
     }
     __syncthreads();
-    if (*lds_ok) return true;
+    if (*lds_ok) {
+        if (wid == 0)
+            for (int g = 0; g < s.n; ++g) {
+                const int u = host(g);
+                for (int x = b.poff[s.g0 + g]; x < b.poff[s.g0 + g + 1]; ++x) {
+                    const int c = b.code[x], room = b.pbmax[x] - b.pbw[x];
+                    if (c < 0 || room <= 0) continue;
+                    const int v = host(b.pj[x]);
+                    const int *l = lane < 6 ? path_link(t, st, u, v, c, lane) : nullptr;
+                    const int left = l ? __hip_atomic_load(l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kBig;
+                    const int add = min(room, wave_min(left));
+                    if (add <= 0) continue;
+                    path_apply_lanes<true>(t, st, u, v, c, -add, lane);
+                    if (lane == 0) b.pbwa[x] = b.pbw[x] + add;
+                    __threadfence();
+                }
+            }
+        __threadfence();
+        __syncthreads();
+        return true;
+    }
     give_back<BS>(t, st, b, s.r, s.n);          // all units and their routes
     __syncthreads();
     if (threadIdx.x == 0) {
