@@ -21,7 +21,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 CRIT_CPU, CRIT_RAM, CRIT_ACTIVE, CRIT_PATHBW, CRIT_UPLINK, CRIT_HOPS = range(6)
 TOPSIS, AHP = 0, 1
-SAATY9, RATIO = 0, 1
+SAATY9, RATIO, DIFF = 0, 1, 2
 
 
 def build(force: bool = True) -> str:
@@ -77,6 +77,8 @@ def lib():
         L.or_ahp.argtypes = [C.c_int, C.c_int, f64p, f64p, i32p, C.c_int, f64p, P, P]
         L.or_saaty.restype = C.c_double
         L.or_saaty.argtypes = [C.c_double, C.c_double]
+        L.or_diff.restype = C.c_double
+        L.or_diff.argtypes = [C.c_double, C.c_double]
         L.or_step_scores.argtypes = [P, C.POINTER(Method), C.c_int, C.c_int, C.c_int, i32p, i32p,
                                      f64p, i32p, f64p]
         L.or_run_request.argtypes = [P, C.POINTER(Method), C.c_int, i32p, i32p, C.c_int, P, P, P, P, P,
@@ -131,6 +133,10 @@ def units(n, pod=None):
 
 def saaty(p, q) -> float:
     return lib().or_saaty(float(p), float(q))
+
+
+def diff(p, q) -> float:
+    return lib().or_diff(float(p), float(q))
 
 
 class Oracle:

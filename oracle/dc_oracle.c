@@ -39,7 +39,7 @@
 
 enum { CRIT_CPU = 0, CRIT_RAM = 1, CRIT_ACTIVE = 2, CRIT_PATHBW = 3, CRIT_UPLINK = 4, CRIT_HOPS = 5 };
 enum { M_TOPSIS = 0, M_AHP = 1 };
-enum { AHP_SAATY9 = 0, AHP_RATIO = 1 };
+enum { AHP_SAATY9 = 0, AHP_RATIO = 1, AHP_DIFF = 2 };
 
 typedef struct {
     int32_t method, ahp_scale, ncrit;
@@ -333,8 +333,19 @@ double or_saaty(double p, double q) {
     return s;
 }
 
+/* The pairwise rule as section V-B states it, on differences: the larger
+ * value's entry is the difference, equal values give 1, and the smaller
+ * value's entry is the reciprocal of the difference.  The printed rule puts
+ * the (negative) difference itself under the reciprocal; its absolute value
+ * is taken so that a(j, i) = 1 / a(i, j), as in every AHP comparison
+ * matrix. */
+double or_diff(double p, double q) {
+    if (p == q) return 1.0;
+    return p > q ? p - q : 1.0 / (q - p);
+}
+
 static double compare(int scale, double p, double q) {
-    return scale == AHP_RATIO ? p / q : or_saaty(p, q);
+    return scale == AHP_RATIO ? p / q : scale == AHP_DIFF ? or_diff(p, q) : or_saaty(p, q);
 }
 
 /* Local rank of a pairwise matrix A (n x n, row-major): normalise each
