@@ -60,7 +60,15 @@ enum dc_status {
 };
 
 enum dc_method { DC_TOPSIS = 0, DC_AHP = 1 };
-enum dc_ahp_scale { DC_AHP_SAATY9 = 0, DC_AHP_RATIO = 1 };
+/* Pairwise comparison scale of AHP (section V-B) for values p (row server)
+ * and q (column server):
+ *   DC_AHP_SAATY9: Saaty's 1-9 scale of p / q (rounded half up, clamped to
+ *                  9; q = 0 gives 9; p < q gives the reciprocal);
+ *   DC_AHP_RATIO:  p / q (a test mode: priorities are then v / sum(v));
+ *   DC_AHP_DIFF:   the differences of section V-B's rule: p - q when p > q,
+ *                  1 when equal, 1 / (q - p) when p < q.
+ * A cost criterion compares q with p instead. */
+enum dc_ahp_scale { DC_AHP_SAATY9 = 0, DC_AHP_RATIO = 1, DC_AHP_DIFF = 2 };
 enum dc_mode { DC_MODE_PLAIN = 0, DC_MODE_BATCHED = 1, DC_MODE_SERVING = 2 };
 enum dc_routing { DC_ROUTE_EACH = 0, DC_ROUTE_END = 1 };
 

@@ -6,7 +6,7 @@ release) runs in the HIP kernels of ``libdcsched.so`` behind the C ABI of
 """
 from .binding import (Scheduler, Result, RESULT_DTYPE, DcError, topsis_tiles, lib, strerror, LIB_PATH,
                       DC_OK, DC_EINVAL, DC_ENOMEM, DC_EAGAIN, DC_ENOENT, DC_EDEVICE, DC_ESTATE,
-                      DC_TOPSIS, DC_AHP, DC_AHP_SAATY9, DC_AHP_RATIO,
+                      DC_TOPSIS, DC_AHP, DC_AHP_SAATY9, DC_AHP_RATIO, DC_AHP_DIFF,
                       DC_MODE_PLAIN, DC_MODE_BATCHED, DC_MODE_SERVING, DC_ROUTE_EACH, DC_ROUTE_END,
                       DC_CRIT_CPU, DC_CRIT_RAM, DC_CRIT_ACTIVE, DC_CRIT_PATHBW, DC_CRIT_UPLINK,
                       DC_CRIT_HOPS, DEFAULT_CRIT, DC_MAX_CONTAINERS)

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libdcsched.so")
 
 DC_OK, DC_EINVAL, DC_ENOMEM, DC_EAGAIN, DC_ENOENT, DC_EDEVICE, DC_ESTATE = 0, -1, -2, -3, -4, -5, -6
 DC_TOPSIS, DC_AHP = 0, 1
-DC_AHP_SAATY9, DC_AHP_RATIO = 0, 1
+DC_AHP_SAATY9, DC_AHP_RATIO, DC_AHP_DIFF = 0, 1, 2
 DC_MODE_PLAIN, DC_MODE_BATCHED, DC_MODE_SERVING = 0, 1, 2
 DC_ROUTE_EACH, DC_ROUTE_END = 0, 1
 DC_CRIT_CPU, DC_CRIT_RAM, DC_CRIT_ACTIVE, DC_CRIT_PATHBW, DC_CRIT_UPLINK, DC_CRIT_HOPS = range(6)

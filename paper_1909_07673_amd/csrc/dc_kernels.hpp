@@ -19,7 +19,7 @@ struct Params {
     int *state_base;
     long long state_stride;
     // AHP
-    int *colpart;    // [nc][nI][N]
+    int *colpart;    // [nc][nI][N] (doubles on the difference scale)
     float *rowpart;  // [nc][nJ][N]
     int ti, tj, nI, nJ;
     StepIn s;        // the container step of a plain launch
@@ -144,21 +144,32 @@ __device__ __forceinline__ float saaty2520(float p, float q, float rp, float rq)
     return rintf(2520.f * (ge ? s : __builtin_amdgcn_rcpf(s)));
 }
 
+// Difference scale (section V-B's rule on differences): the larger value's
+// entry is p - q, equal values 1, the smaller value's 1 / (q - p).  Values
+// are integers below 2^22, so p - q is exact in FP32; the reciprocal comes
+// from the hardware (within 1 ulp).
+__device__ __forceinline__ float diff_scale(float p, float q) {
+    return p > q ? p - q : (p < q ? __builtin_amdgcn_rcpf(q - p) : 1.f);
+}
+
 // Pass A: column sums colsum_c[j] = sum_i a_c(i, j), never storing the
 // N x N matrix.  Grid (ceil(N/256), nI, nc): thread = column j, block y =
 // chunk of ti rows.  Saaty sums are exact integers (x2520); the ratio scale
-// sums floats.  Partials per row chunk, reduced in pass B in fixed order.
+// sums floats; the difference scale sums in FP64 (its integer entries,
+// up to 2^22 each, stay exact).  Partials per row chunk (one int each, two
+// on the difference scale), reduced in pass B in fixed order.
 __global__ __launch_bounds__(kAhpBlock) void k_ahp_colsum(Params p) {
     if (p.b.status[p.s.r] == 0) return;
     __shared__ float sx[kAhpTile], sr[kAhpTile];
     const int N = p.t.N, c = blockIdx.z, ib = blockIdx.y;
     const int j = blockIdx.x * kAhpBlock + threadIdx.x;
     const int *x = p.xs + (size_t)c * N;
-    const bool cost = p.m.cost[c] != 0, ratio = p.m.scale == 1;
+    const bool cost = p.m.cost[c] != 0, ratio = p.m.scale == 1, diff = p.m.scale == 2;
     const float q = j < N ? static_cast<float>(x[j]) : 0.f;
     const float rq = rcp2(q);
     int acci = 0;
     float accf = 0.f;
+    double accd = 0.0;
     const int i0 = ib * p.ti, i1 = min(N, i0 + p.ti);
     for (int base = i0; base < i1; base += kAhpTile) {
         const int cnt = min(kAhpTile, i1 - base);
@@ -172,13 +183,20 @@ __global__ __launch_bounds__(kAhpBlock) void k_ahp_colsum(Params p) {
         if (ratio) {
             if (cost) for (int t = 0; t < cnt; ++t) accf += q / sx[t];
             else for (int t = 0; t < cnt; ++t) accf += sx[t] / q;
+        } else if (diff) {
+            if (cost) for (int t = 0; t < cnt; ++t) accd += static_cast<double>(diff_scale(q, sx[t]));
+            else for (int t = 0; t < cnt; ++t) accd += static_cast<double>(diff_scale(sx[t], q));
         } else if (cost) {
             for (int t = 0; t < cnt; ++t) acci += static_cast<int>(saaty2520(q, sx[t], rq, sr[t]));
         } else {
             for (int t = 0; t < cnt; ++t) acci += static_cast<int>(saaty2520(sx[t], q, sr[t], rq));
         }
     }
-    if (j < N) p.colpart[((size_t)c * p.nI + ib) * N + j] = ratio ? __float_as_int(accf) : acci;
+    if (j < N) {
+        const size_t at = ((size_t)c * p.nI + ib) * N + j;
+        if (diff) reinterpret_cast<double *>(p.colpart)[at] = accd;
+        else p.colpart[at] = ratio ? __float_as_int(accf) : acci;
+    }
 }
 
 // Pass B: row sums of the column-normalised matrix,
@@ -191,9 +209,11 @@ __global__ __launch_bounds__(kAhpBlock) void k_ahp_rowsum(Params p) {
     const int N = p.t.N, c = blockIdx.z, jb = blockIdx.y;
     const int i = blockIdx.x * kAhpBlock + threadIdx.x;
     const int *x = p.xs + (size_t)c * N;
-    const bool cost = p.m.cost[c] != 0, ratio = p.m.scale == 1;
+    const bool cost = p.m.cost[c] != 0, ratio = p.m.scale == 1, diff = p.m.scale == 2;
     const float pv = i < N ? static_cast<float>(x[i]) : 0.f;
     const float rp = rcp2(pv);
+    const int *cp = p.colpart + (size_t)c * p.nI * N;
+    const double *cpd = reinterpret_cast<const double *>(p.colpart) + (size_t)c * p.nI * N;
     float acc[kAhpAcc];
 #pragma unroll
     for (int a = 0; a < kAhpAcc; ++a) acc[a] = 0.f;
@@ -208,11 +228,15 @@ __global__ __launch_bounds__(kAhpBlock) void k_ahp_rowsum(Params p) {
             sr[t] = rcp2(v);
             if (ratio) {
                 float s = 0.f;
-                for (int ib = 0; ib < p.nI; ++ib) s += __int_as_float(p.colpart[((size_t)c * p.nI + ib) * N + j]);
+                for (int ib = 0; ib < p.nI; ++ib) s += __int_as_float(cp[(size_t)ib * N + j]);
                 sinv[t] = 1.f / s;
+            } else if (diff) {
+                double s = 0.0;
+                for (int ib = 0; ib < p.nI; ++ib) s += cpd[(size_t)ib * N + j];
+                sinv[t] = static_cast<float>(1.0 / s);
             } else {
                 long long s = 0;
-                for (int ib = 0; ib < p.nI; ++ib) s += p.colpart[((size_t)c * p.nI + ib) * N + j];
+                for (int ib = 0; ib < p.nI; ++ib) s += cp[(size_t)ib * N + j];
                 sinv[t] = static_cast<float>(1.0 / static_cast<double>(s));
             }
         }
@@ -224,6 +248,12 @@ __global__ __launch_bounds__(kAhpBlock) void k_ahp_rowsum(Params p) {
                 for (int a = 0; a < kAhpAcc; ++a)
                     acc[a] = fmaf(cost ? sx[t + a] / pv : pv / sx[t + a], sinv[t + a], acc[a]);
             for (; t < cnt; ++t) acc[0] = fmaf(cost ? sx[t] / pv : pv / sx[t], sinv[t], acc[0]);
+        } else if (diff) {
+            for (; t + kAhpAcc <= cnt; t += kAhpAcc)
+#pragma unroll
+                for (int a = 0; a < kAhpAcc; ++a)
+                    acc[a] = fmaf(cost ? diff_scale(sx[t + a], pv) : diff_scale(pv, sx[t + a]), sinv[t + a], acc[a]);
+            for (; t < cnt; ++t) acc[0] = fmaf(cost ? diff_scale(sx[t], pv) : diff_scale(pv, sx[t]), sinv[t], acc[0]);
         } else if (cost) {
             for (; t + kAhpAcc <= cnt; t += kAhpAcc)
 #pragma unroll

@@ -321,7 +321,9 @@ int check_config(const dc_config *c) {
     if (c->n_instances < 1 || c->n_instances > 65536) return DC_EINVAL;
     if (c->mode < DC_MODE_PLAIN || c->mode > DC_MODE_SERVING) return DC_EINVAL;
     if (c->method != DC_TOPSIS && c->method != DC_AHP) return DC_EINVAL;
-    if (c->method == DC_AHP && c->ahp_scale != DC_AHP_SAATY9 && c->ahp_scale != DC_AHP_RATIO) return DC_EINVAL;
+    if (c->method == DC_AHP && c->ahp_scale != DC_AHP_SAATY9 && c->ahp_scale != DC_AHP_RATIO &&
+        c->ahp_scale != DC_AHP_DIFF)
+        return DC_EINVAL;
     if (c->method == DC_AHP && c->mode != DC_MODE_PLAIN) return DC_EINVAL;
     const int caps[5] = {c->host_cpu, c->host_ram, c->bw_host_edge, c->bw_edge_agg, c->bw_agg_core};
     for (int v : caps)
@@ -1040,7 +1042,7 @@ int dc_create(const dc_config *cfg, dc_ctx **out) {
         c->nI = std::max(1, std::min(bx * 4, (2048 + bx * nc - 1) / (bx * nc)));
         c->ti = (N + c->nI - 1) / c->nI;
         c->nI = (N + c->ti - 1) / c->ti;
-        if (hipMalloc(&c->d_colpart, (size_t)nc * c->nI * N * sizeof(int)) != hipSuccess ||
+        if (hipMalloc(&c->d_colpart, (size_t)nc * c->nI * N * sizeof(long long)) != hipSuccess ||
             hipMalloc(&c->d_rowpart, (size_t)nc * c->nJ * N * sizeof(float)) != hipSuccess) {
             dc_destroy(ctx.release());
             return DC_ENOMEM;

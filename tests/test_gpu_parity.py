@@ -106,6 +106,47 @@ def test_ahp_ratio_scale_priorities():
     lockstep(o, s, ids[0], reqs[0], res, trace=trace_by_request(s))
 
 
+def test_ahp_difference_scale_tiny_lockstep():
+    """AHP on the difference scale of section V-B's rule: k=4, with and
+    without pods, every step and score vector against the oracle."""
+    tot = dict(steps=0, accepted=0)
+    for seed in range(12):
+        for preset in ("tiny", "tiny_pods"):
+            insts, reqs = make_config(preset, seed=seed)
+            s = dc.Scheduler(insts, method=dc.DC_AHP, ahp_scale=dc.DC_AHP_DIFF, trace_stride=1, trace_cap=4096)
+            o = O.Oracle(insts[0], O.method(kind=O.AHP, scale=O.DIFF))
+            for req in reqs[0]:
+                rid = s.submit(req)
+                res = {r.req_id: r for r in s.schedule()}
+                st = lockstep(o, s, [rid], [req], res, trace=trace_by_request(s), check_paths=True)
+                assert st["scored_steps"] == st["steps"]
+                for k in tot:
+                    tot[k] += st[k]
+            s.close()
+    assert tot["steps"] > 500 and tot["accepted"] > 100
+
+
+def test_ahp_difference_scale_k16_and_k32():
+    """Difference scale at k=16 (every step of a prefix, 0-70 % background)
+    and at the k=32 five-criteria shape with hops as a cost (one request)."""
+    insts, reqs = make_config("plain", seed=8, n_req=10)
+    s, ids, res = _run(insts, reqs, method=dc.DC_AHP, ahp_scale=dc.DC_AHP_DIFF, trace_stride=1, trace_cap=1024)
+    o = O.Oracle(insts[0], O.method(kind=O.AHP, scale=O.DIFF))
+    st = lockstep(o, s, ids[0], reqs[0], res, trace=trace_by_request(s), check_paths=True)
+    assert st["scored_steps"] == st["steps"] > 20
+    s.close()
+    insts, reqs = make_config("ahp", seed=1, n_req=1)
+    req = reqs[0][0]
+    req = Request(req.cpu[:5].copy(), req.ram[:5].copy(),
+                  np.array([e for e in req.edges if e[0] < 5 and e[1] < 5], np.int32).reshape(-1, 3))
+    s, ids, res = _run(insts, [[req]], method=dc.DC_AHP, ahp_scale=dc.DC_AHP_DIFF, crit=C5, cost=C5_COST,
+                       trace_stride=1, trace_cap=64)
+    o = O.Oracle(insts[0], O.method(kind=O.AHP, crit=C5, cost=list(C5_COST), scale=O.DIFF))
+    st = lockstep(o, s, ids[0], [req], res, trace=trace_by_request(s), check_paths=True)
+    assert st["scored_steps"] == st["steps"] >= 1
+    s.close()
+
+
 def test_topsis_five_criteria_with_cost():
     insts, reqs = make_config("plain", seed=4, n_req=80)
     s, ids, res = _run(insts, reqs, crit=C5, cost=C5_COST, trace_stride=3, trace_cap=4096)
