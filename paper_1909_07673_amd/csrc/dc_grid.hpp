@@ -417,6 +417,7 @@ __global__ __launch_bounds__(BS) void k_serve_grid(Params p, ServeArgs a, GridCt
     int *rq_host = grid_req_lds(dsm, p.t.h, p.t.hh, p.m.nc);
     int *rq_cpu = rq_host + kMaxN, *rq_ram = rq_cpu + kMaxN, *rq_poff = rq_ram + kMaxN;
     int *rq_pj = rq_poff + kMaxN + 4, *rq_pbw = rq_pj + kMaxPairs, *rq_pbmax = rq_pbw + kMaxPairs;
+    int *rq_cmax = rq_pbmax + kMaxPairs, *rq_rmax = rq_cmax + kMaxN;
     const bool lead = blockIdx.x == 0;
     int pos = a.start;
     long long idle0 = dev_clock();
@@ -465,6 +466,8 @@ __global__ __launch_bounds__(BS) void k_serve_grid(Params p, ServeArgs a, GridCt
                 if (x < n) {
                     rq_cpu[x] = stg[L.cpu + x];
                     rq_ram[x] = stg[L.ram + x];
+                    rq_cmax[x] = stg[L.cmax + x];
+                    rq_rmax[x] = stg[L.rmax + x];
                     rq_host[x] = -1;
                     if (lead) {
                         sb[L.host + x] = -1;
@@ -485,7 +488,7 @@ __global__ __launch_bounds__(BS) void k_serve_grid(Params p, ServeArgs a, GridCt
             __syncthreads();
             for (int i = 0; i < n; ++i) {
                 const int q0 = rq_poff[i];
-                const StepIn s{0, i, n, 0, i, q0, rq_poff[i + 1] - q0, rq_cpu[i], rq_ram[i], b.cmax[i], b.rmax[i]};
+                const StepIn s{0, i, n, 0, i, q0, rq_poff[i + 1] - q0, rq_cpu[i], rq_ram[i], rq_cmax[i], rq_rmax[i]};
                 const ReqView rv{rq_pj + q0, rq_pbw + q0, rq_host, rq_host, rq_pbmax + q0};
                 if (!grid_topsis_step<BS>(p.t, p.st, p.m, b, sm, g, timeout, s, rv, p.tr)) {
                     fault = __hip_atomic_load(g.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;

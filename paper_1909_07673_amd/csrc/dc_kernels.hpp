@@ -75,6 +75,12 @@ __device__ __forceinline__ void stage_out(int *g, const int *lds, int n) {
 // ---------------------------------------------------------------- plain form
 // The plain form passes the container's peer list in the kernel arguments,
 // so only the peers' servers are read from memory.
+//
+// The persistent kernels (batched, serving) read the Batch pointers from an
+// LDS copy: fields are then loaded when used, after each barrier, instead of
+// holding some forty scalar registers across their request loops, which
+// pushes the compiler into spilling scalars through vector lanes.  A plain
+// launch runs one step, and keeps them in registers.
 __device__ __forceinline__ ReqView plain_view(const Params &p) {
     return ReqView{p.pj, p.pbw, p.b.host + p.s.g0, nullptr, p.pbmax};
 }
@@ -342,8 +348,8 @@ __global__ __launch_bounds__(BS) void k_ahp_select(Params p) {
 // ---------------------------------------------------------------- batched form
 // LDS ints of the request prefetch of the batched form: hosts, cpu, ram
 // (kMaxN each), relative peer offsets (kMaxN + 4), peers, minimum and
-// maximum demands (kMaxPairs each).
-__host__ __device__ inline size_t req_lds_ints() { return 4 * (size_t)kMaxN + 4 + 3 * (size_t)kMaxPairs; }
+// maximum demands (kMaxPairs each), maximum cpu and ram (kMaxN each).
+__host__ __device__ inline size_t req_lds_ints() { return 6 * (size_t)kMaxN + 4 + 3 * (size_t)kMaxPairs; }
 
 // One persistent workgroup per data-center instance: the instance's state,
 // the per-server scratch and the request being scheduled live in LDS for
@@ -360,9 +366,13 @@ __global__ __launch_bounds__(BS) void k_topsis_batched(Params p) {
     int *rq_host = ls + 6 * (size_t)N;
     int *rq_cpu = rq_host + kMaxN, *rq_ram = rq_cpu + kMaxN, *rq_poff = rq_ram + kMaxN;
     int *rq_pj = rq_poff + kMaxN + 4, *rq_pbw = rq_pj + kMaxPairs, *rq_pbmax = rq_pbw + kMaxPairs;
+    int *rq_cmax = rq_pbmax + kMaxPairs, *rq_rmax = rq_cmax + kMaxN;
     const State gs = state_at(p.state_base, p.state_stride, inst, N);
     stage_in<BS>(ls, gs.cpu, 6 * N);
     const State st{ls, ls + N, ls + 2 * N, ls + 3 * N, ls + 4 * N, ls + 5 * N};
+    __shared__ Batch lb;
+    if (threadIdx.x == 0) lb = p.b;
+    __syncthreads();
     const int r0 = p.b.iroff[inst], r1 = p.b.iroff[inst + 1];
     for (int r = r0; r < r1; ++r) {
         const int g0 = p.b.coff[r], n = p.b.coff[r + 1] - g0;
@@ -372,6 +382,8 @@ __global__ __launch_bounds__(BS) void k_topsis_batched(Params p) {
             if (x < n) {
                 rq_cpu[x] = p.b.cpu[g0 + x];
                 rq_ram[x] = p.b.ram[g0 + x];
+                rq_cmax[x] = p.b.cmax[g0 + x];
+                rq_rmax[x] = p.b.rmax[g0 + x];
                 rq_host[x] = -1;
             }
         }
@@ -384,10 +396,10 @@ __global__ __launch_bounds__(BS) void k_topsis_batched(Params p) {
         for (int i = 0; i < n; ++i) {
             const int q0 = rq_poff[i];
             const StepIn s{r, i, n, g0, g0 + i, pb + q0, rq_poff[i + 1] - q0, rq_cpu[i], rq_ram[i],
-                           p.b.cmax[g0 + i], p.b.rmax[g0 + i]};
+                           rq_cmax[i], rq_rmax[i]};
             const ReqView rv{rq_pj + q0, rq_pbw + q0, rq_host, rq_host, rq_pbmax + q0};
             // one server per thread at 1024 threads keeps the loop in registers
-            if (!topsis_step<BS, BS >= 1024 ? 1 : host_group(BS), true>(p.t, st, p.m, p.b, sm, xs, p.pc_cap, p.tr, inst,
+            if (!topsis_step<BS, BS >= 1024 ? 1 : host_group(BS), true>(p.t, st, p.m, lb, sm, xs, p.pc_cap, p.tr, inst,
                                                                   s, rv))
                 break;
         }

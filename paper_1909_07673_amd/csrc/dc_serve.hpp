@@ -103,6 +103,7 @@ __global__ __launch_bounds__(BS) void k_serve(Params p, ServeArgs a) {
     int *rq_host = lds_after_tables(dsm, p.pc_cap, p.t.nsw);
     int *rq_cpu = rq_host + kMaxN, *rq_ram = rq_cpu + kMaxN, *rq_poff = rq_ram + kMaxN;
     int *rq_pj = rq_poff + kMaxN + 4, *rq_pbw = rq_pj + kMaxPairs, *rq_pbmax = rq_pbw + kMaxPairs;
+    int *rq_cmax = rq_pbmax + kMaxPairs, *rq_rmax = rq_cmax + kMaxN;
     __shared__ int cmdv[8];
     int pos = a.start;
     long long idle0 = dev_clock();
@@ -136,6 +137,8 @@ __global__ __launch_bounds__(BS) void k_serve(Params p, ServeArgs a) {
         int *sb = a.arena + cmdv[3];
         const SlotLayout L = slot_layout(n, P);
         const Batch b = slot_batch(sb, L);
+        __shared__ Batch lb;                  // the steps read the slot's pointers from LDS
+        if (threadIdx.x == 0) lb = b;         // (read after the copy loops' barrier)
         const long long t_admit = dev_clock();
         if (type == CMD_SUBMIT) {
             // copy the request into its device slot and into LDS
@@ -146,6 +149,8 @@ __global__ __launch_bounds__(BS) void k_serve(Params p, ServeArgs a) {
                 if (x < n) {
                     rq_cpu[x] = stg[L.cpu + x];
                     rq_ram[x] = stg[L.ram + x];
+                    rq_cmax[x] = stg[L.cmax + x];
+                    rq_rmax[x] = stg[L.rmax + x];
                     rq_host[x] = -1;
                     sb[L.host + x] = -1;
                     sb[L.score + x] = 0;
@@ -164,9 +169,9 @@ __global__ __launch_bounds__(BS) void k_serve(Params p, ServeArgs a) {
             __syncthreads();
             for (int i = 0; i < n; ++i) {
                 const int q0 = rq_poff[i];
-                const StepIn s{0, i, n, 0, i, q0, rq_poff[i + 1] - q0, rq_cpu[i], rq_ram[i], b.cmax[i], b.rmax[i]};
+                const StepIn s{0, i, n, 0, i, q0, rq_poff[i + 1] - q0, rq_cpu[i], rq_ram[i], rq_cmax[i], rq_rmax[i]};
                 const ReqView rv{rq_pj + q0, rq_pbw + q0, rq_host, rq_host, rq_pbmax + q0};
-                if (!topsis_step<BS, BS >= 1024 ? 1 : host_group(BS)>(p.t, p.st, p.m, b, sm, p.xs, p.pc_cap, p.tr, 0,
+                if (!topsis_step<BS, BS >= 1024 ? 1 : host_group(BS)>(p.t, p.st, p.m, lb, sm, p.xs, p.pc_cap, p.tr, 0,
                                                                       s, rv))
                     break;
             }
