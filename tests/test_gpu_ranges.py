@@ -141,3 +141,28 @@ def test_ranges_invalid():
     with pytest.raises(dc.DcError):
         s.alloc(rid + 1, 2, 1)
     s.close()
+
+
+def test_ranges_k48_cooperative_serving_and_plain():
+    """k=48 (27,648 servers), pods and intervals: the cooperative serving
+    kernel and the single-workgroup plain form give the same servers,
+    scores, allocations and state; plain in lockstep with the oracle."""
+    insts, reqs = make_config("ranges", seed=2, n_req=12, k=48)
+    p, pids, pres = _run(insts, reqs, trace_stride=9, trace_cap=64)
+    o = O.Oracle(insts[0], O.method(kind=O.TOPSIS))
+    st = lockstep(o, p, pids[0], reqs[0], pres, trace=trace_by_request(p), check_paths=True, check_alloc=True)
+    assert st["accepted"] >= 2 and st["scored_steps"] >= 1
+    sv = dc.Scheduler(insts, mode=dc.DC_MODE_SERVING)
+    sids = [sv.submit(r) for r in reqs[0]]
+    sres = {r.req_id: r for r in sv.drain()}
+    for x, y, req in zip(pids[0], sids, reqs[0]):
+        assert sres[y].status == pres[x].status and sres[y].failed_at == pres[x].failed_at
+        np.testing.assert_array_equal(sres[y].hosts, pres[x].hosts)
+        np.testing.assert_array_equal(sres[y].scores.view(np.uint32), pres[x].scores.view(np.uint32))
+        if pres[x].status == 1:
+            np.testing.assert_array_equal(sv.paths(y), p.paths(x))
+            for a, b in zip(sv.alloc(y, req.n, req.m), p.alloc(x, req.n, req.m)):
+                np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(sv.state(0), p.state(0))
+    sv.close()
+    p.close()
