@@ -495,15 +495,18 @@ def _ft_link_hops(paths):
     return int((paths >= 0).sum())
 
 
-@pytest.mark.parametrize("wl", ["ahp", "plain", "pods", "pods_route_end"])
+@pytest.mark.parametrize("wl", ["ahp", "plain", "pods", "pods_route_end", "ranges"])
 def test_full_size_accounting(wl):
     """The measured configurations at full size (AHP k=32 with 500 requests,
-    TOPSIS k=16 with 2,000 requests, with and without pods, and with pods
-    and links routed at each request's end), checked by
-    properties that hold at any size: the state change equals the accepted
-    placements (CPU, RAM, placed counts per server) and their routes (link
-    usage = summed demand x hops), nothing goes negative, and releasing every
-    accepted request restores the initial state bit-exactly."""
+    TOPSIS k=16 with 2,000 requests, with and without pods, with pods and
+    links routed at each request's end, and with pods and demand
+    intervals), checked by properties that hold at any size: the state
+    change equals the accepted placements (CPU, RAM, placed counts per
+    server) and their routes (link usage = summed demand x hops; with
+    intervals, what was given, each within [min, max], and short of the
+    maximum only where the server's resource ran out), nothing goes
+    negative, and releasing every accepted request restores the initial
+    state bit-exactly."""
     kw = {}
     if wl == "pods_route_end":
         wl = "pods"
@@ -522,15 +525,22 @@ def test_full_size_accounting(wl):
     ram = np.zeros(N, np.int64)
     npl = np.zeros(N, np.int64)
     hops_bw = 0
-    acc = []
+    acc, short_c, short_r = [], [], []
     for rid, req in zip(ids, reqs[0]):
         r = res[rid]
         if r.status != 1:
             assert np.all(r.hosts == -1)
             continue
         acc.append(rid)
-        np.add.at(cpu, r.hosts, req.cpu)
-        np.add.at(ram, r.hosts, req.ram)
+        ca, ra, ba = req.cpu, req.ram, req.edges[:, 2]
+        if req.cpu_max is not None:
+            ca, ra, ba = s.alloc(rid, req.n, req.m)
+            assert np.all((req.cpu <= ca) & (ca <= req.cpu_max)) and np.all((req.ram <= ra) & (ra <= req.ram_max))
+            assert np.all((req.edges[:, 2] <= ba) & (ba <= req.bw_max))
+            short_c.extend(r.hosts[ca < req.cpu_max].tolist())
+            short_r.extend(r.hosts[ra < req.ram_max].tolist())
+        np.add.at(cpu, r.hosts, ca)
+        np.add.at(ram, r.hosts, ra)
         if getattr(req, "pod", None) is None:
             np.add.at(npl, r.hosts, 1)
         else:
@@ -541,7 +551,7 @@ def test_full_size_accounting(wl):
         # demand per routed pair, in the paths' order
         unit, first = O.units(req.n, getattr(req, "pod", None))
         dem = {}
-        for a, b, bw in req.edges:
+        for (a, b, _), bw in zip(req.edges, ba):
             ua, ub = unit[a], unit[b]
             if ua != ub:
                 key = (max(ua, ub), min(ua, ub))
@@ -555,6 +565,9 @@ def test_full_size_accounting(wl):
     np.testing.assert_array_equal(s0[1] - s1[1], ram)
     np.testing.assert_array_equal(s1[2] - s0[2], npl)
     assert int((s0[3:] - s1[3:]).sum()) == hops_bw
+    assert np.all(s1[0][short_c] == 0) and np.all(s1[1][short_r] == 0)
+    if wl == "ranges":
+        assert len(short_c) + len(short_r) > 0
     for rid in acc:
         assert s.release(rid) == dc.DC_OK
     np.testing.assert_array_equal(s.state(0), s0)
