@@ -88,7 +88,7 @@ typedef struct dc_config {
     int32_t k;              /* fat-tree arity, even, 4..64                          */
     int32_t n_instances;    /* independent data centers (batched form), >= 1        */
     int32_t mode;           /* dc_mode                                              */
-    int32_t method;         /* dc_method                                            */
+    int32_t method;         /* dc_method; AHP runs in the plain form only           */
     int32_t ahp_scale;      /* dc_ahp_scale (AHP only)                              */
     int32_t host_cpu, host_ram;                     /* per-server capacity          */
     int32_t bw_host_edge, bw_edge_agg, bw_agg_core; /* per-level link capacity      */
