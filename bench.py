@@ -105,6 +105,20 @@ def step_count_array(res, reqs=None):
     return sum(_pod_steps(q, int(r["status"]), int(r["failed_at"])) for q, r in zip(reqs, res))
 
 
+def host_cpu():
+    """The host's CPU model and the logical CPUs this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}, {len(os.sched_getaffinity(0))} logical CPUs available"
+
+
 def cpu_baseline(insts, reqs, budget_s, meth):
     """The FP64 oracle, as it stands, on a bounded prefix of the same
     workload (single thread): the requests of instance 0 in FCFS order, then
@@ -129,7 +143,7 @@ def cpu_baseline(insts, reqs, budget_s, meth):
     where = "the same workload" if n_inst == 1 else f"the first {n_inst} instances of the same workload"
     return dict(value=steps * N / dt, unit="host-scores/s", cores=1, kind="oracle",
                 sample=f"first {n_req} requests ({steps} scoring steps) of {where} on one host "
-                       f"thread, {dt:.1f} s")
+                       f"thread, {dt:.1f} s", host=host_cpu())
 
 
 def percentiles(x):
@@ -349,7 +363,8 @@ def run_tiles(args, wl):
             done += 1
         el = time.perf_counter() - t1
         out["cpu_baseline"] = {"value": done * N / el, "unit": "host-scores/s", "cores": 1, "kind": "oracle",
-                               "sample": f"first {done} of the {T} matrices, FP64 oracle TOPSIS, one thread"}
+                               "sample": f"first {done} of the {T} matrices, FP64 oracle TOPSIS, one thread",
+                               "host": host_cpu()}
         out["cpu_baseline"]["vs_gpu"] = out["value"] / out["cpu_baseline"]["value"]
     return out
 
