@@ -133,17 +133,18 @@ __global__ __launch_bounds__(BS) void k_criteria_plain(Params p) {
 // exact quotient; its floor is then at most one below s wherever s < 11,
 // and one test of the exact remainder num - s * 2 lo (all integers below
 // 2^24) corrects it; larger quotients are clamped to 9 anyway.  lo = 0
-// makes rl = +inf: hi > 0 gives +inf, clamped to 9; hi = 0 gives NaN, which
-// max(., 0) turns into 0 and the remainder test (0 >= 0) into 1.
+// makes rl = 2^100: hi > 0 gives a quotient far above 9, clamped to 9;
+// hi = 0 gives 0, which the remainder test (0 >= 0) turns into 1.  hi and
+// lo are selected by the comparison already made, not by fmax / fmin.
 __device__ __forceinline__ float rcp2(float v) {
-    return v > 0.f ? __builtin_amdgcn_rcpf(2.f * v) * (1.0f - 0x1p-21f) : __builtin_inff();
+    return v > 0.f ? __builtin_amdgcn_rcpf(2.f * v) * (1.0f - 0x1p-21f) : 0x1p100f;
 }
 
 __device__ __forceinline__ float saaty2520(float p, float q, float rp, float rq) {
     const bool ge = p >= q;
-    const float hi = fmaxf(p, q), lo = fminf(p, q), rl = ge ? rq : rp;
+    const float hi = ge ? p : q, lo = ge ? q : p, rl = ge ? rq : rp;
     const float num = fmaf(2.f, hi, lo), two_lo = lo + lo;
-    float s = floorf(fmaxf(num * rl, 0.f));
+    float s = floorf(num * rl);
     const float rem = fmaf(-s, two_lo, num);
     s = rem >= two_lo ? s + 1.f : s;
     s = fminf(s, 9.f);
