@@ -258,8 +258,8 @@ def run_batch(args, wl):
 
 
 # VALU instructions per Saaty pair evaluation in the AHP passes, counted in
-# the compiled inner loops (20.8 in k_ahp_colsum, 20.1-21.2 in k_ahp_rowsum).
-AHP_PAIR_OPS = 21
+# the compiled inner loops (18.75 in k_ahp_colsum, 18.1 in k_ahp_rowsum).
+AHP_PAIR_OPS = 18.4
 
 
 TILE_T, TILE_C, TILE_N = 32768, 4, 1024
