@@ -153,10 +153,13 @@ __device__ __forceinline__ float saaty2520(float p, float q, float rp, float rq)
 
 // Difference scale (section V-B's rule on differences): the larger value's
 // entry is p - q, equal values 1, the smaller value's 1 / (q - p).  Values
-// are integers below 2^22, so p - q is exact in FP32; the reciprocal comes
-// from the hardware (within 1 ulp).
+// are integers below 2^22, so |p - q| is exact in FP32 and at least 1 when
+// they differ; the reciprocal of max(|p - q|, 1) is then 1 / (q - p), or
+// exactly 1 for equal values (hardware reciprocal, within 1 ulp), with no
+// branch.
 __device__ __forceinline__ float diff_scale(float p, float q) {
-    return p > q ? p - q : (p < q ? __builtin_amdgcn_rcpf(q - p) : 1.f);
+    const float d = fabsf(p - q);
+    return p > q ? d : __builtin_amdgcn_rcpf(fmaxf(d, 1.f));
 }
 
 // Pass A: column sums colsum_c[j] = sum_i a_c(i, j), never storing the
