@@ -37,20 +37,26 @@ __device__ __forceinline__ int *cmd_flags(const GridCtl &g, int pos) { return g.
 // Grid barrier over gridDim.x co-resident workgroups with agent-scope
 // release / acquire.  A wait longer than `timeout` device ticks sets *err;
 // every barrier returns false once *err is set, so all workgroups leave.
+// Ordering: each arrival's fetch_add releases the workgroup's writes (after
+// the block barrier) and acquires the earlier arrivals'; the last arrival
+// publishes the next generation with a release store; the others poll it
+// with relaxed loads and take one acquire fence once it has changed.  The
+// generation is read before arriving, which the release of the fetch_add
+// keeps in place.  No other fence is needed, and on a device of several
+// XCDs each one costs a second-level cache writeback or invalidation.
 __device__ __forceinline__ bool grid_sync(const GridCtl &g, int *lds_flag, long long timeout) {
     __syncthreads();
     if (threadIdx.x == 0) {
         int bad = __hip_atomic_load(g.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (!bad) {
-            __threadfence();
-            const unsigned gen = __hip_atomic_load(g.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned gen = __hip_atomic_load(g.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const unsigned arrived = __hip_atomic_fetch_add(g.count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
             if (arrived == gridDim.x - 1) {
                 __hip_atomic_store(g.count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_store(g.gen, gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             } else {
                 const long long t0 = dev_clock();
-                while (__hip_atomic_load(g.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                while (__hip_atomic_load(g.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
                     if (__hip_atomic_load(g.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { bad = 1; break; }
                     if (dev_clock() - t0 > timeout) {
                         __hip_atomic_store(g.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -59,8 +65,8 @@ __device__ __forceinline__ bool grid_sync(const GridCtl &g, int *lds_flag, long 
                     }
                     __builtin_amdgcn_s_sleep(1);
                 }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
-            __threadfence();
         }
         *lds_flag = bad;
     }
