@@ -572,7 +572,7 @@ def main():
                     help="batched form: 0 automatic (graph), 1 direct launch, 2 HIP graph")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
+        print(f"bench.py: the scheduler runs on one GPU only (asked for {args.gpus}); "
               "a data center's container steps are sequential and are not sharded across GPUs", file=sys.stderr)
         sys.exit(2)
     wl = WORKLOADS[args.workload]
