@@ -794,8 +794,11 @@ __device__ bool route_request_end(const Topo &t, const State &st, const Batch &b
                                   HostFn host) {
     constexpr int NW = BS / kWave;
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    // the commit's stores (server, codes) are visible to every wave from here
-    __threadfence();
+    // All waves of the workgroup share one CU and its write-through L1, and
+    // the link updates below are L2 atomics, so ordering inside the routine
+    // needs only workgroup fences; one agent fence at the end of an accepted
+    // request orders its link changes before whatever step comes next.
+    __threadfence_block();
     if (threadIdx.x == 0) *lds_ok = 1;
     __syncthreads();
     for (int g = wid; g < s.n; g += NW) {
@@ -813,7 +816,7 @@ __device__ bool route_request_end(const Topo &t, const State &st, const Batch &b
             }
         }
     }
-    __threadfence();
+    __threadfence_block();
     __syncthreads();
     for (int g = wid; g < s.n; g += NW) {                  // take every demand off its path
         const int u = host(g);
@@ -822,7 +825,7 @@ __device__ bool route_request_end(const Topo &t, const State &st, const Batch &b
             if (c >= 0) path_apply_lanes<true>(t, st, u, host(b.pj[x]), c, -b.pbwa[x], lane);
         }
     }
-    __threadfence();
+    __threadfence_block();
     __syncthreads();
     for (int g = wid; g < s.n; g += NW) {                  // any link overdrawn?
         const int u = host(g);
@@ -849,7 +852,7 @@ __device__ bool route_request_end(const Topo &t, const State &st, const Batch &b
                     if (add <= 0) continue;
                     path_apply_lanes<true>(t, st, u, v, c, -add, lane);
                     if (lane == 0) b.pbwa[x] = b.pbw[x] + add;
-                    __threadfence();
+                    __threadfence_block();
                 }
             }
         __threadfence();
