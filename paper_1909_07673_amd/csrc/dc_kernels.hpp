@@ -22,6 +22,8 @@ struct Params {
     int *colpart;    // [nc][nI][N] (doubles on the difference scale)
     float *rowpart;  // [nc][nJ][N]
     int ti, tj, nI, nJ;
+    int *ysort;      // AHP on the 1-9 scale: [nc][N] criterion values in ascending order
+    double *wsort;   // and 1 / column sum at each sorted position
     StepIn s;        // the container step of a plain launch
     int pj[kMaxN], pbw[kMaxN];   // its placed peers (container index, minimum demand)
     int pbmax[kMaxN];            // and their maximum demands
@@ -30,6 +32,7 @@ struct Params {
 constexpr int kAhpBlock = 256;
 constexpr int kAhpTile = 1024;   // values staged per LDS tile in the AHP passes
 constexpr int kAhpAcc = 8;       // independent partial sums per row in pass B
+constexpr int kAhpSortMax = 8192; // servers up to which the 1-9 scale uses the sorted passes
 
 // Dynamic LDS of the single-workgroup step: fixed part, capacity sums and
 // peer tables, then optionally the criteria scratch xs and the state.
@@ -284,6 +287,208 @@ __global__ __launch_bounds__(kAhpBlock) void k_ahp_rowsum(Params p) {
     if (i < N) p.rowpart[((size_t)c * p.nJ + jb) * N + i] = s;
 }
 
+// ---------------------------------------------------------------- AHP, 1-9 scale, sorted form
+// On the 1-9 scale an entry takes one of 17 values, and which one is fixed
+// by integer thresholds: for p > q > 0 the rounded ratio s = min(9,
+// floor((2p + q) / 2q)) is at least k exactly when 2p >= (2k - 1) q, and a
+// value of 0 against a larger one scores 9.  With a criterion's values
+// sorted, the sum of a(v, y_m) w_m over all servers m (or of a(y_m, v) w_m)
+// is therefore 17 weighted counts, each a binary search: unit weights give
+// the exact column sums, weights 1 / column sum (prefix-summed in FP64)
+// give the row sums of the column-normalised matrix (section V-B,
+// Eqs. (9)-(10)).  The result equals the pairwise passes up to the row
+// sums' rounding; the work is O(C N log N) after an O(C N^2) rank count of
+// two instructions per pair.
+
+// Bucket bounds of value v (>= 0) against the ascending y[0, n): [lv, uv)
+// holds the values equal to v; positions [ai[k], n) hold the larger values
+// whose rounded ratio to v is at least k, and [0, bi[k]) the smaller values
+// whose ratio from v is at least k (k = 1..9; index 10 closes the sums).
+// The 18 lower bounds advance together, one LDS load each per halving.
+struct SaatyBuckets {
+    int lv, uv, ai[11], bi[11];
+};
+
+__device__ __forceinline__ SaatyBuckets saaty_buckets(const int *y, int n, int v) {
+    int t[18], pos[18];
+    t[0] = v;
+    t[1] = v + 1;
+#pragma unroll
+    for (int k = 2; k <= 9; ++k) {
+        t[2 * k - 2] = max(((2 * k - 1) * v + 1) >> 1, v + 1);   // y >= this: ratio y / v rounds to >= k
+        t[2 * k - 1] = (2 * v) / (2 * k - 1) + 1;                 // y < this: ratio v / y rounds to >= k
+    }
+#pragma unroll
+    for (int q = 0; q < 18; ++q) pos[q] = 0;
+    for (int step = 1 << (31 - __builtin_clz(n | 1)); step > 0; step >>= 1) {
+        int val[18];
+#pragma unroll
+        for (int q = 0; q < 18; ++q) val[q] = y[min(pos[q] + step, n) - 1];
+#pragma unroll
+        for (int q = 0; q < 18; ++q) pos[q] = (pos[q] + step <= n && val[q] < t[q]) ? pos[q] + step : pos[q];
+    }
+    SaatyBuckets b;
+    b.lv = pos[0];
+    b.uv = pos[1];
+    b.ai[1] = b.uv;
+    b.bi[1] = b.lv;
+#pragma unroll
+    for (int k = 2; k <= 9; ++k) {
+        b.ai[k] = pos[2 * k - 2];
+        b.bi[k] = min(pos[2 * k - 1], b.lv);
+    }
+    b.ai[10] = n;
+    b.bi[10] = 0;
+    return b;
+}
+
+// Sum over m of 2520 a(v, y_m) w_m (first) or 2520 a(y_m, v) w_m, with
+// W(a, b) the weight of the sorted positions [a, b): the side whose ratio
+// is s contributes 2520 s per position, the other side 2520 / s.
+template <class T, class WFn>
+__device__ __forceinline__ T saaty_sum(const SaatyBuckets &b, int n, bool first, WFn W) {
+    T big = 0, small = 0;
+#pragma unroll
+    for (int k = 1; k <= 9; ++k) {
+        const T a = W(b.ai[k], n), bb = W(0, b.bi[k]);
+        const T da = W(b.ai[k], b.ai[k + 1]), db = W(b.bi[k + 1], b.bi[k]);
+        big += first ? bb : a;
+        small += static_cast<T>(2520 / k) * (first ? da : db);
+    }
+    return static_cast<T>(2520) * (W(b.lv, b.uv) + big) + small;
+}
+
+// Exclusive scan of one value per thread over the BS threads of the block.
+template <int BS, class T, class Op>
+__device__ __forceinline__ T block_excl_scan(T v, T id, T *sh, Op op) {
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < BS; off <<= 1) {
+        const T o = tid >= off ? sh[tid - off] : id;
+        __syncthreads();
+        sh[tid] = op(sh[tid], o);
+        __syncthreads();
+    }
+    const T r = tid ? sh[tid - 1] : id;
+    __syncthreads();
+    return r;
+}
+
+// Pass R: rank of every value, lt[j] = #{i : x_i < x_j}, as partial counts
+// over nI chunks of i.  Grid (ceil(N/256), nI, nc).
+__global__ __launch_bounds__(kAhpBlock) void k_ahp_rank(Params p) {
+    if (p.b.status[p.s.r] == 0) return;
+    __shared__ __align__(16) int sx[kAhpTile];
+    const int N = p.t.N, c = blockIdx.z, ib = blockIdx.y;
+    const int j = blockIdx.x * kAhpBlock + threadIdx.x;
+    const int *x = p.xs + (size_t)c * N;
+    const int q = j < N ? x[j] : 0;
+    int acc = 0;
+    const int i0 = ib * p.ti, i1 = min(N, i0 + p.ti);
+    for (int base = i0; base < i1; base += kAhpTile) {
+        const int cnt = min(kAhpTile, i1 - base);
+        __syncthreads();
+        for (int t = threadIdx.x; t < cnt; t += kAhpBlock) sx[t] = x[base + t];
+        __syncthreads();
+        // sixteen values per round, four 16-byte LDS reads in flight
+        int t = 0;
+        for (; t + 16 <= cnt; t += 16) {
+            const int4 a = *reinterpret_cast<const int4 *>(sx + t), b = *reinterpret_cast<const int4 *>(sx + t + 4);
+            const int4 e = *reinterpret_cast<const int4 *>(sx + t + 8), f = *reinterpret_cast<const int4 *>(sx + t + 12);
+            acc += (a.x < q) + (a.y < q) + (a.z < q) + (a.w < q) + (b.x < q) + (b.y < q) + (b.z < q) + (b.w < q);
+            acc += (e.x < q) + (e.y < q) + (e.z < q) + (e.w < q) + (f.x < q) + (f.y < q) + (f.z < q) + (f.w < q);
+        }
+        for (; t < cnt; ++t) acc += sx[t] < q;
+    }
+    if (j < N) p.colpart[((size_t)c * p.nI + ib) * N + j] = acc;
+}
+
+// Pass S: the sorted values of criterion c.  Each value goes to its rank
+// (equal values to the same slot), then a running maximum fills the rest of
+// each run of equal values.  Grid (1, 1, nc).
+constexpr int kAhpSortBlock = 1024;
+
+__global__ __launch_bounds__(kAhpSortBlock) void k_ahp_sort_build(Params p) {
+    if (p.b.status[p.s.r] == 0) return;
+    __shared__ int y[kAhpSortMax];
+    __shared__ int sh[kAhpSortBlock];
+    const int N = p.t.N, c = blockIdx.z, tid = threadIdx.x;
+    const int *x = p.xs + (size_t)c * N;
+    const int *lt = p.colpart + (size_t)c * p.nI * N;
+    for (int m = tid; m < N; m += kAhpSortBlock) y[m] = -1;
+    __syncthreads();
+    for (int j = tid; j < N; j += kAhpSortBlock) {
+        int r = 0;
+        for (int ib = 0; ib < p.nI; ++ib) r += lt[(size_t)ib * N + j];
+        y[r] = x[j];
+    }
+    __syncthreads();
+    const int E = (N + kAhpSortBlock - 1) / kAhpSortBlock, m0 = min(N, tid * E), m1 = min(N, m0 + E);
+    int run = -1;
+    for (int m = m0; m < m1; ++m) run = max(run, y[m]);
+    run = block_excl_scan<kAhpSortBlock>(run, -1, sh, op_max);
+    for (int m = m0; m < m1; ++m) {
+        run = max(run, y[m]);
+        y[m] = run;
+    }
+    __syncthreads();
+    for (int m = tid; m < N; m += kAhpSortBlock) p.ysort[(size_t)c * N + m] = y[m];
+}
+
+// Pass C: exact column sums at every sorted position, stored as 1 / sum
+// (FP64).  Grid (ceil(N/256), 1, nc).
+__global__ __launch_bounds__(kAhpBlock) void k_ahp_sort_col(Params p) {
+    if (p.b.status[p.s.r] == 0) return;
+    __shared__ int y[kAhpSortMax];
+    const int N = p.t.N, c = blockIdx.z;
+    for (int m = threadIdx.x; m < N; m += kAhpBlock) y[m] = p.ysort[(size_t)c * N + m];
+    __syncthreads();
+    const int m = blockIdx.x * kAhpBlock + threadIdx.x;
+    if (m < N) {
+        // column j compares every row i against it: a(x_i, x_j), or
+        // a(x_j, x_i) for a cost criterion
+        const SaatyBuckets b = saaty_buckets(y, N, y[m]);
+        const long long s = saaty_sum<long long>(b, N, p.m.cost[c] != 0,
+                                                 [](int a, int e) { return static_cast<long long>(e - a); });
+        p.wsort[(size_t)c * N + m] = 1.0 / static_cast<double>(s);
+    }
+}
+
+// Pass D: row sums of the column-normalised matrix, L_c[i] * N =
+// sum_j a(i, j) / colsum[j], from prefix sums of 1 / colsum in sorted
+// order.  One partial per row (nJ = 1).  Grid (ceil(N/256), 1, nc).
+__global__ __launch_bounds__(kAhpBlock) void k_ahp_sort_row(Params p) {
+    if (p.b.status[p.s.r] == 0) return;
+    __shared__ int y[kAhpSortMax];
+    __shared__ double P[kAhpSortMax + 1];
+    __shared__ double sh[kAhpBlock];
+    const int N = p.t.N, c = blockIdx.z, tid = threadIdx.x;
+    for (int m = tid; m < N; m += kAhpBlock) {
+        y[m] = p.ysort[(size_t)c * N + m];
+        P[m + 1] = p.wsort[(size_t)c * N + m];
+    }
+    if (tid == 0) P[0] = 0.0;
+    __syncthreads();
+    const int E = (N + kAhpBlock - 1) / kAhpBlock, m0 = min(N, tid * E), m1 = min(N, m0 + E);
+    double run = 0.0;
+    for (int m = m0; m < m1; ++m) run += P[m + 1];
+    run = block_excl_scan<kAhpBlock>(run, 0.0, sh, [](double a, double b) { return a + b; });
+    for (int m = m0; m < m1; ++m) {
+        run += P[m + 1];
+        P[m + 1] = run;
+    }
+    __syncthreads();
+    const int i = blockIdx.x * kAhpBlock + tid;
+    if (i < N) {
+        // row i compares against every column j: a(x_i, x_j), or a(x_j, x_i)
+        // for a cost criterion
+        const SaatyBuckets b = saaty_buckets(y, N, p.xs[(size_t)c * N + i]);
+        const double r = saaty_sum<double>(b, N, p.m.cost[c] == 0, [&](int a, int e) { return P[e] - P[a]; });
+        p.rowpart[(size_t)c * N + i] = static_cast<float>(r);
+    }
+}
+
 // Local rank of the criteria-level ratio matrix W[a] / W[b] (column sums,
 // then row means of the normalised matrix); equal to W when the weights sum
 // to 1.  Kept as FP32 values, widened to FP64 for the sums that use them.
@@ -306,9 +511,9 @@ __device__ __forceinline__ void ahp_p1(const Method &m, double *p1) {
 }
 
 // AHP step, stage 4: global priority of every server, PG[u] = sum_c P1[c] *
-// L2_c[u], summing the row partials of pass B in fixed order.  Written as
-// FP32 into xs row nc + 1 (free once the criteria stage is done), and into
-// the trace when this step is recorded.
+// L2_c[u], summing the row partials in fixed order.  Written as FP32 into
+// xs row nc + 1 (free once the criteria stage is done), and into the trace
+// when this step is recorded.
 __global__ __launch_bounds__(kAhpBlock) void k_ahp_pg(Params p) {
     if (p.b.status[p.s.r] == 0) return;
     const int N = p.t.N, nc = p.m.nc;

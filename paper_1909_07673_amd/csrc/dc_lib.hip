@@ -274,6 +274,10 @@ struct dc_ctx {
     int *d_colpart = nullptr;      // AHP [nc][nI][N]
     float *d_rowpart = nullptr;    // AHP [nc][nJ][N]
     int ti = 0, tj = 0, nI = 0, nJ = 0;
+    bool ahp_sorted = false;       // AHP on the 1-9 scale through the sorted passes
+    int *d_ysort = nullptr;        // [nc][N]
+    double *d_wsort = nullptr;     // [nc][N]
+    int ti_rank = 0, nI_rank = 0;  // row chunks of the rank pass
     int *d_tmeta = nullptr, *d_tcount = nullptr;
     float *d_tscore = nullptr;
     int plain_bs = 1024, batched_bs = 1024;
@@ -390,6 +394,8 @@ Params base_params(dc_ctx *ctx, const DevBatch &b, int inst) {
     p.state_stride = 6LL * ctx->N;
     p.colpart = ctx->d_colpart;
     p.rowpart = ctx->d_rowpart;
+    p.ysort = ctx->d_ysort;
+    p.wsort = ctx->d_wsort;
     p.ti = ctx->ti; p.tj = ctx->tj; p.nI = ctx->nI; p.nJ = ctx->nJ;
     return p;
 }
@@ -537,11 +543,25 @@ void launch_plain_step(dc_ctx *ctx, const Params &p) {
     } else {
         const int bx = (ctx->N + kAhpBlock - 1) / kAhpBlock;
         hipLaunchKernelGGL((k_criteria_plain<BS>), dim3(1), dim3(BS), ctx->lds_plain, ctx->stream, p);
-        hipLaunchKernelGGL(k_ahp_colsum, dim3(bx, ctx->nI, ctx->m.nc), dim3(kAhpBlock), 0, ctx->stream, p);
-        hipLaunchKernelGGL(k_ahp_rowsum, dim3(bx, ctx->nJ, ctx->m.nc), dim3(kAhpBlock), 0, ctx->stream, p);
-        hipLaunchKernelGGL(k_ahp_pg, dim3(bx), dim3(kAhpBlock), 0, ctx->stream, p);
-        hipLaunchKernelGGL((k_ahp_select<BS>), dim3(1), dim3(BS), ctx->lds_select, ctx->stream, p);
-        ctx->last_launches += 5;
+        if (ctx->ahp_sorted) {
+            Params q = p;
+            q.ti = ctx->ti_rank;
+            q.nI = ctx->nI_rank;
+            q.nJ = 1;
+            hipLaunchKernelGGL(k_ahp_rank, dim3(bx, q.nI, ctx->m.nc), dim3(kAhpBlock), 0, ctx->stream, q);
+            hipLaunchKernelGGL(k_ahp_sort_build, dim3(1, 1, ctx->m.nc), dim3(kAhpSortBlock), 0, ctx->stream, q);
+            hipLaunchKernelGGL(k_ahp_sort_col, dim3(bx, 1, ctx->m.nc), dim3(kAhpBlock), 0, ctx->stream, q);
+            hipLaunchKernelGGL(k_ahp_sort_row, dim3(bx, 1, ctx->m.nc), dim3(kAhpBlock), 0, ctx->stream, q);
+            hipLaunchKernelGGL(k_ahp_pg, dim3(bx), dim3(kAhpBlock), 0, ctx->stream, q);
+            hipLaunchKernelGGL((k_ahp_select<BS>), dim3(1), dim3(BS), ctx->lds_select, ctx->stream, q);
+            ctx->last_launches += 7;
+        } else {
+            hipLaunchKernelGGL(k_ahp_colsum, dim3(bx, ctx->nI, ctx->m.nc), dim3(kAhpBlock), 0, ctx->stream, p);
+            hipLaunchKernelGGL(k_ahp_rowsum, dim3(bx, ctx->nJ, ctx->m.nc), dim3(kAhpBlock), 0, ctx->stream, p);
+            hipLaunchKernelGGL(k_ahp_pg, dim3(bx), dim3(kAhpBlock), 0, ctx->stream, p);
+            hipLaunchKernelGGL((k_ahp_select<BS>), dim3(1), dim3(BS), ctx->lds_select, ctx->stream, p);
+            ctx->last_launches += 5;
+        }
     }
 }
 
@@ -1042,8 +1062,17 @@ int dc_create(const dc_config *cfg, dc_ctx **out) {
         c->nI = std::max(1, std::min(bx * 4, (2048 + bx * nc - 1) / (bx * nc)));
         c->ti = (N + c->nI - 1) / c->nI;
         c->nI = (N + c->ti - 1) / c->ti;
-        if (hipMalloc(&c->d_colpart, (size_t)nc * c->nI * N * sizeof(long long)) != hipSuccess ||
-            hipMalloc(&c->d_rowpart, (size_t)nc * c->nJ * N * sizeof(float)) != hipSuccess) {
+        // the 1-9 scale takes the sorted passes while a criterion's sorted
+        // values and their prefix sums fit one workgroup's LDS
+        c->ahp_sorted = cfg->ahp_scale == DC_AHP_SAATY9 && N <= kAhpSortMax;
+        c->nI_rank = std::max(1, std::min(8, (512 + bx * nc - 1) / (bx * nc)));
+        c->ti_rank = (N + c->nI_rank - 1) / c->nI_rank;
+        c->nI_rank = (N + c->ti_rank - 1) / c->ti_rank;
+        const size_t colpart = std::max((size_t)c->nI * sizeof(long long), (size_t)c->nI_rank * sizeof(int));
+        if (hipMalloc(&c->d_colpart, (size_t)nc * N * colpart) != hipSuccess ||
+            hipMalloc(&c->d_rowpart, (size_t)nc * c->nJ * N * sizeof(float)) != hipSuccess ||
+            (c->ahp_sorted && (hipMalloc(&c->d_ysort, (size_t)nc * N * sizeof(int)) != hipSuccess ||
+                               hipMalloc(&c->d_wsort, (size_t)nc * N * sizeof(double)) != hipSuccess))) {
             dc_destroy(ctx.release());
             return DC_ENOMEM;
         }
@@ -1521,10 +1550,12 @@ void dc_destroy(dc_ctx *ctx) {
     if (quiet) {
         for (auto &b : ctx->batches)
             if (b->dmem) (void)hipFree(b->dmem);
-        int *ptrs[] = {ctx->d_state, ctx->d_init, ctx->d_xs, ctx->d_colpart, ctx->d_tmeta, ctx->d_tcount, ctx->d_grid};
+        int *ptrs[] = {ctx->d_state, ctx->d_init, ctx->d_xs, ctx->d_colpart, ctx->d_tmeta, ctx->d_tcount, ctx->d_grid,
+                       ctx->d_ysort};
         for (int *p : ptrs)
             if (p) (void)hipFree(p);
         if (ctx->d_rowpart) (void)hipFree(ctx->d_rowpart);
+        if (ctx->d_wsort) (void)hipFree(ctx->d_wsort);
         if (ctx->d_tscore) (void)hipFree(ctx->d_tscore);
     } else {
         std::fprintf(stderr, "libdcsched: the device did not finish this context's work; its memory is left allocated\n");

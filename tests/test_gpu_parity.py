@@ -96,6 +96,24 @@ def test_ahp_k32_five_criteria_sampled():
     assert st["scored_steps"] == st["steps"] >= 1
 
 
+@pytest.mark.parametrize("k", [20, 34])
+def test_ahp_saaty_sorted_and_pairwise_sizes(k):
+    """The 1-9 scale through both forms of the column and row sums: k=20
+    (2,000 hosts, not a multiple of the 256-thread block) takes the sorted
+    passes; k=34 (9,826 hosts) is beyond their LDS limit of 8,192 hosts and
+    takes the pairwise passes.  One request of three containers (two at
+    k=34, where the oracle takes about 5 s per step), every step and score
+    vector against the oracle."""
+    insts, reqs = make_config("ahp", seed=3, n_req=1, k=k)
+    req, n = reqs[0][0], 3 if k == 20 else 2
+    req = Request(req.cpu[:n].copy(), req.ram[:n].copy(),
+                  np.array([e for e in req.edges if e[0] < n and e[1] < n], np.int32).reshape(-1, 3))
+    s, ids, res = _run(insts, [[req]], method=dc.DC_AHP, crit=C5, cost=C5_COST, trace_stride=1, trace_cap=8)
+    o = O.Oracle(insts[0], _omethod(O.AHP, crit=C5, cost=C5_COST))
+    st = lockstep(o, s, ids[0], [req], res, trace=trace_by_request(s), check_paths=True)
+    assert st["scored_steps"] == st["steps"] >= 1
+
+
 def test_ahp_ratio_scale_priorities():
     """Ratio-scale AHP (consistent matrices): PG equals sum_c w_c v_c / sum(v_c)."""
     insts, reqs = make_config("tiny", seed=9)
