@@ -44,7 +44,7 @@ WORKLOADS = {
                          "per instance, TOPSIS, batched form (one persistent launch)"),
     "ahp": dict(preset="ahp", mode="plain", method="ahp",
                 text="k=32 fat-tree (8192 hosts), 500 FCFS requests of 8-64 containers, 0-70% background, AHP "
-                     "(Saaty 1-9) on CPU/RAM/uplink/path-bw/hops(cost), five launches per container step"),
+                     "(Saaty 1-9) on CPU/RAM/uplink/path-bw/hops(cost), seven launches per container step"),
     "pods": dict(preset="pods", mode="plain", method="topsis",
                  text="k=16 fat-tree (1024 hosts), 2000 FCFS requests of 2-32 containers with up to half of each "
                       "request's containers in pods of 2-4 (one placement per pod), 0-70% background, TOPSIS, "
@@ -239,15 +239,21 @@ def run_batch(args, wl):
             out["scoring_kernel_roofline"] = dict(
                 tile_timing(20, 2)[3], workload=WORKLOADS["tiles"]["text"])
     else:
-        # AHP: the pairwise passes dominate; 2*C*N^2 pair evaluations per
-        # container step, at PAIR_OPS VALU lane-instructions each
         C = 5
-        pairs = 2.0 * C * N * N * steps
-        out["roofline"] = {"bound": "alu", "kernel": "k_ahp_colsum+k_ahp_rowsum", "unit": "pair-evals/s",
-                           "achieved": pairs * args.steps / (kern_ms / 1e3),
-                           "peak": VALU_LANE_OPS / AHP_PAIR_OPS,
-                           "frac": pairs * args.steps / (kern_ms / 1e3) / (VALU_LANE_OPS / AHP_PAIR_OPS),
-                           "traffic": None, "pair_ops": AHP_PAIR_OPS}
+        if N <= AHP_SORT_MAX:
+            # AHP on the 1-9 scale through the sorted passes: the only
+            # O(C N^2) work is the rank count, one compare per pair and
+            # criterion at RANK_OPS VALU lane-instructions; the rate is taken
+            # over the whole step's kernel time (all seven launches)
+            pairs, ops, kname, unit = 1.0 * C * N * N * steps, AHP_RANK_OPS, "k_ahp_rank", "pair-compares/s"
+        else:
+            # pairwise passes: 2*C*N^2 Saaty evaluations per container step
+            pairs, ops, kname, unit = 2.0 * C * N * N * steps, AHP_PAIR_OPS, "k_ahp_colsum+k_ahp_rowsum", "pair-evals/s"
+        rate = pairs * args.steps / (kern_ms / 1e3)
+        out["roofline"] = {"bound": "alu", "kernel": kname, "unit": unit, "achieved": rate,
+                           "peak": VALU_LANE_OPS / ops, "frac": rate / (VALU_LANE_OPS / ops),
+                           "traffic": None, "pair_ops": ops, "basis": "whole AHP step kernel time",
+                           "avg_launch_us": avg_launch_s * 1e6, "launches_per_step": per_step_launches}
         meth = oracle.method(kind=oracle.AHP, crit=(oracle.CRIT_CPU, oracle.CRIT_RAM, oracle.CRIT_UPLINK,
                                                    oracle.CRIT_PATHBW, oracle.CRIT_HOPS), cost=[0, 0, 0, 0, 1])
     if not args.no_cpu_baseline:
@@ -257,9 +263,13 @@ def run_batch(args, wl):
     return out
 
 
-# VALU instructions per Saaty pair evaluation in the AHP passes, counted in
-# the compiled inner loops (18.75 in k_ahp_colsum, 18.1 in k_ahp_rowsum).
+# VALU instructions per Saaty pair evaluation in the pairwise AHP passes,
+# counted in the compiled inner loops (18.75 in k_ahp_colsum, 18.1 in
+# k_ahp_rowsum), and per compare in the rank pass of the sorted form (33 per
+# 16 values), which the 1-9 scale takes up to AHP_SORT_MAX servers.
 AHP_PAIR_OPS = 18.4
+AHP_RANK_OPS = 33 / 16
+AHP_SORT_MAX = 8192
 
 
 TILE_T, TILE_C, TILE_N = 32768, 4, 1024
