@@ -375,6 +375,17 @@ __device__ __forceinline__ T block_excl_scan(T v, T id, T *sh, Op op) {
     return r;
 }
 
+// n int32 from global memory into LDS (16-byte aligned), four 16-byte loads
+// in flight per thread when the source allows it.
+template <int BS>
+__device__ __forceinline__ void lds_load_i32(int *lds, const int *g, int n) {
+    if ((reinterpret_cast<uintptr_t>(g) & 15) == 0 && (n & 3) == 0) {
+        stage_in<BS>(lds, g, n);
+    } else {
+        for (int x = threadIdx.x; x < n; x += BS) lds[x] = g[x];
+    }
+}
+
 // Pass R: rank of every value, lt[j] = #{i : x_i < x_j}, as partial counts
 // over nI chunks of i.  Grid (ceil(N/256), nI, nc).
 __global__ __launch_bounds__(kAhpBlock) void k_ahp_rank(Params p) {
@@ -440,9 +451,9 @@ __global__ __launch_bounds__(kAhpSortBlock) void k_ahp_sort_build(Params p) {
 // (FP64).  Grid (ceil(N/256), 1, nc).
 __global__ __launch_bounds__(kAhpBlock) void k_ahp_sort_col(Params p) {
     if (p.b.status[p.s.r] == 0) return;
-    __shared__ int y[kAhpSortMax];
+    __shared__ __align__(16) int y[kAhpSortMax];
     const int N = p.t.N, c = blockIdx.z;
-    for (int m = threadIdx.x; m < N; m += kAhpBlock) y[m] = p.ysort[(size_t)c * N + m];
+    lds_load_i32<kAhpBlock>(y, p.ysort + (size_t)c * N, N);
     __syncthreads();
     const int m = blockIdx.x * kAhpBlock + threadIdx.x;
     if (m < N) {
@@ -460,13 +471,33 @@ __global__ __launch_bounds__(kAhpBlock) void k_ahp_sort_col(Params p) {
 // order.  One partial per row (nJ = 1).  Grid (ceil(N/256), 1, nc).
 __global__ __launch_bounds__(kAhpBlock) void k_ahp_sort_row(Params p) {
     if (p.b.status[p.s.r] == 0) return;
-    __shared__ int y[kAhpSortMax];
+    __shared__ __align__(16) int y[kAhpSortMax];
     __shared__ double P[kAhpSortMax + 1];
     __shared__ double sh[kAhpBlock];
     const int N = p.t.N, c = blockIdx.z, tid = threadIdx.x;
-    for (int m = tid; m < N; m += kAhpBlock) {
-        y[m] = p.ysort[(size_t)c * N + m];
-        P[m + 1] = p.wsort[(size_t)c * N + m];
+    lds_load_i32<kAhpBlock>(y, p.ysort + (size_t)c * N, N);
+    const double *w = p.wsort + (size_t)c * N;
+    if (N & 1) {
+        for (int m = tid; m < N; m += kAhpBlock) P[m + 1] = w[m];
+    } else {
+        // with N even every criterion's row is 16-byte aligned
+        const int n2 = N >> 1;
+        int x = tid;
+        for (; x + 3 * kAhpBlock < n2; x += 4 * kAhpBlock) {
+            double2 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = reinterpret_cast<const double2 *>(w)[x + u * kAhpBlock];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                P[2 * (x + u * kAhpBlock) + 1] = v[u].x;
+                P[2 * (x + u * kAhpBlock) + 2] = v[u].y;
+            }
+        }
+        for (; x < n2; x += kAhpBlock) {
+            const double2 v = reinterpret_cast<const double2 *>(w)[x];
+            P[2 * x + 1] = v.x;
+            P[2 * x + 2] = v.y;
+        }
     }
     if (tid == 0) P[0] = 0.0;
     __syncthreads();
