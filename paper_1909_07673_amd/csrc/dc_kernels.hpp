@@ -471,14 +471,19 @@ __global__ __launch_bounds__(kAhpBlock) void k_ahp_sort_col(Params p) {
 // order.  One partial per row (nJ = 1).  Grid (ceil(N/256), 1, nc).
 __global__ __launch_bounds__(kAhpBlock) void k_ahp_sort_row(Params p) {
     if (p.b.status[p.s.r] == 0) return;
+    // prefix sums P[0..N] in LDS with one pad slot after every E of them, E
+    // the power-of-two chunk each thread scans, so the threads' chunks start
+    // in different banks
     __shared__ __align__(16) int y[kAhpSortMax];
-    __shared__ double P[kAhpSortMax + 1];
+    __shared__ double P[kAhpSortMax + kAhpBlock + 2];
     __shared__ double sh[kAhpBlock];
     const int N = p.t.N, c = blockIdx.z, tid = threadIdx.x;
+    const int e = max((N + kAhpBlock - 1) / kAhpBlock, 1), lgE = e > 1 ? 32 - __builtin_clz(e - 1) : 0, E = 1 << lgE;
+    auto at = [lgE](int q) { return q + (q >> lgE); };
     lds_load_i32<kAhpBlock>(y, p.ysort + (size_t)c * N, N);
     const double *w = p.wsort + (size_t)c * N;
     if (N & 1) {
-        for (int m = tid; m < N; m += kAhpBlock) P[m + 1] = w[m];
+        for (int m = tid; m < N; m += kAhpBlock) P[at(m + 1)] = w[m];
     } else {
         // with N even every criterion's row is 16-byte aligned
         const int n2 = N >> 1;
@@ -489,25 +494,25 @@ __global__ __launch_bounds__(kAhpBlock) void k_ahp_sort_row(Params p) {
             for (int u = 0; u < 4; ++u) v[u] = reinterpret_cast<const double2 *>(w)[x + u * kAhpBlock];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                P[2 * (x + u * kAhpBlock) + 1] = v[u].x;
-                P[2 * (x + u * kAhpBlock) + 2] = v[u].y;
+                P[at(2 * (x + u * kAhpBlock) + 1)] = v[u].x;
+                P[at(2 * (x + u * kAhpBlock) + 2)] = v[u].y;
             }
         }
         for (; x < n2; x += kAhpBlock) {
             const double2 v = reinterpret_cast<const double2 *>(w)[x];
-            P[2 * x + 1] = v.x;
-            P[2 * x + 2] = v.y;
+            P[at(2 * x + 1)] = v.x;
+            P[at(2 * x + 2)] = v.y;
         }
     }
     if (tid == 0) P[0] = 0.0;
     __syncthreads();
-    const int E = (N + kAhpBlock - 1) / kAhpBlock, m0 = min(N, tid * E), m1 = min(N, m0 + E);
+    const int m0 = min(N, tid * E), m1 = min(N, m0 + E);
     double run = 0.0;
-    for (int m = m0; m < m1; ++m) run += P[m + 1];
+    for (int m = m0; m < m1; ++m) run += P[at(m + 1)];
     run = block_excl_scan<kAhpBlock>(run, 0.0, sh, [](double a, double b) { return a + b; });
     for (int m = m0; m < m1; ++m) {
-        run += P[m + 1];
-        P[m + 1] = run;
+        run += P[at(m + 1)];
+        P[at(m + 1)] = run;
     }
     __syncthreads();
     const int i = blockIdx.x * kAhpBlock + tid;
@@ -515,7 +520,8 @@ __global__ __launch_bounds__(kAhpBlock) void k_ahp_sort_row(Params p) {
         // row i compares against every column j: a(x_i, x_j), or a(x_j, x_i)
         // for a cost criterion
         const SaatyBuckets b = saaty_buckets(y, N, p.xs[(size_t)c * N + i]);
-        const double r = saaty_sum<double>(b, N, p.m.cost[c] == 0, [&](int a, int e) { return P[e] - P[a]; });
+        const double r =
+            saaty_sum<double>(b, N, p.m.cost[c] == 0, [&](int a, int e) { return P[at(e)] - P[at(a)]; });
         p.rowpart[(size_t)c * N + i] = static_cast<float>(r);
     }
 }
