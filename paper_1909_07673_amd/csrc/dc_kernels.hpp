@@ -427,13 +427,29 @@ __global__ __launch_bounds__(kAhpSortBlock) void k_ahp_sort_build(Params p) {
     const int N = p.t.N, c = blockIdx.z, tid = threadIdx.x;
     const int *x = p.xs + (size_t)c * N;
     const int *lt = p.colpart + (size_t)c * p.nI * N;
+    // each thread's values and their ranks, with all loads of one chunk of
+    // partial counts in flight together
+    constexpr int PER = kAhpSortMax / kAhpSortBlock;
+    int xv[PER], rk[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int j = tid + u * kAhpSortBlock;
+        xv[u] = j < N ? x[j] : 0;
+        rk[u] = 0;
+    }
+    for (int ib = 0; ib < p.nI; ++ib) {
+        const int *l = lt + (size_t)ib * N;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int j = tid + u * kAhpSortBlock;
+            rk[u] += j < N ? l[j] : 0;
+        }
+    }
     for (int m = tid; m < N; m += kAhpSortBlock) y[m] = -1;
     __syncthreads();
-    for (int j = tid; j < N; j += kAhpSortBlock) {
-        int r = 0;
-        for (int ib = 0; ib < p.nI; ++ib) r += lt[(size_t)ib * N + j];
-        y[r] = x[j];
-    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u)
+        if (tid + u * kAhpSortBlock < N) y[rk[u]] = xv[u];
     __syncthreads();
     const int E = (N + kAhpSortBlock - 1) / kAhpSortBlock, m0 = min(N, tid * E), m1 = min(N, m0 + E);
     int run = -1;
