@@ -293,12 +293,12 @@ __global__ __launch_bounds__(kAhpBlock) void k_ahp_rowsum(Params p) {
 // floor((2p + q) / 2q)) is at least k exactly when 2p >= (2k - 1) q, and a
 // value of 0 against a larger one scores 9.  With a criterion's values
 // sorted, the sum of a(v, y_m) w_m over all servers m (or of a(y_m, v) w_m)
-// is therefore 17 weighted counts, each a binary search: unit weights give
-// the exact column sums, weights 1 / column sum (prefix-summed in FP64)
-// give the row sums of the column-normalised matrix (section V-B,
-// Eqs. (9)-(10)).  The result equals the pairwise passes up to the row
-// sums' rounding; the work is O(C N log N) after an O(C N^2) rank count of
-// two instructions per pair.
+// is therefore a weighted count over 17 buckets, whose bounds are 18 binary
+// searches: unit weights give the exact column sums, weights 1 / column sum
+// (prefix-summed in FP64) give the row sums of the column-normalised matrix
+// (section V-B, Eqs. (9)-(10)).  The result equals the pairwise passes up to
+// the row sums' rounding; the work is O(C N log N) after an O(C N^2) rank
+// count of two instructions per pair.
 
 // Bucket bounds of value v (>= 0) against the ascending y[0, n): [lv, uv)
 // holds the values equal to v; positions [ai[k], n) hold the larger values
