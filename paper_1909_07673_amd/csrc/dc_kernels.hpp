@@ -112,15 +112,16 @@ __global__ __launch_bounds__(BS) void k_topsis_plain(Params p) {
     stage_out<BS>(p.st.cpu, ls, 6 * N);
 }
 
-// AHP step, stage 1: criteria of every server into the global xs rows.
+// AHP step, stage 1: criteria of every server into the global xs rows,
+// spread over ceil(N / (G * BS)) workgroups.
 template <int BS>
 __global__ __launch_bounds__(BS) void k_criteria_plain(Params p) {
     extern __shared__ __align__(16) char dsm[];
     if (p.b.status[p.s.r] == 0) return;
-    if (p.s.i == 0 && threadIdx.x == 0) p.b.tsb[p.s.r] = dev_clock();
+    if (p.s.i == 0 && blockIdx.x == 0 && threadIdx.x == 0) p.b.tsb[p.s.r] = dev_clock();
     Smem sm = carve(dsm, p.pc_cap, p.t.nsw);
     load_peers<BS, true>(p.t, p.st, plain_view(p), sm, p.s.P);
-    criteria_stage<BS, false>(p.t, p.st, p.m, sm, p.xs, p.s.cpu, p.s.ram, p.s.P, p.pc_cap);
+    criteria_stage<BS, false>(p.t, p.st, p.m, sm, p.xs, p.s.cpu, p.s.ram, p.s.P, p.pc_cap, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------- AHP (section V-B)

@@ -542,7 +542,9 @@ void launch_plain_step(dc_ctx *ctx, const Params &p) {
         ctx->last_launches += 1;
     } else {
         const int bx = (ctx->N + kAhpBlock - 1) / kAhpBlock;
-        hipLaunchKernelGGL((k_criteria_plain<BS>), dim3(1), dim3(BS), ctx->lds_plain, ctx->stream, p);
+        // criteria over several workgroups, each with G * BS servers at a time
+        const int ncw = (ctx->N + host_group(BS) * BS - 1) / (host_group(BS) * BS);
+        hipLaunchKernelGGL((k_criteria_plain<BS>), dim3(ncw), dim3(BS), ctx->lds_plain, ctx->stream, p);
         if (ctx->ahp_sorted) {
             Params q = p;
             q.ti = ctx->ti_rank;

@@ -518,9 +518,11 @@ __device__ __forceinline__ void peer_deficits(const Smem &sm, int P) {
 // satisfies, which spare the commit loop from trying servers bound to fail:
 // the server's uplink, its edge switch's and its pod's uplinks each carry
 // the demand of the peers outside them, and the peer-side deficits.
+// With nwg > 1, workgroup wg of nwg takes every nwg-th group of G * BS
+// servers (the other workgroups build the same peer tables for theirs).
 template <int BS, bool STATS, int G = host_group(BS)>
 __device__ void criteria_stage(const Topo &t, const State &st, const Method &m, const Smem &sm, int *xs,
-                               int cpu_i, int ram_i, int P, int pc_cap) {
+                               int cpu_i, int ram_i, int P, int pc_cap, int wg = 0, int nwg = 1) {
     const int N = t.N, nc = m.nc;
     const int nch = P == 0 ? 1 : (P + pc_cap - 1) / pc_cap;
     unsigned long long s2[kMaxCrit];
@@ -544,7 +546,7 @@ __device__ void criteria_stage(const Topo &t, const State &st, const Method &m, 
         // G servers per thread at a time: one peer record feeds all of
         // them, and their independent chains hide the LDS latency
         constexpr int kHostGroup = G;
-        for (int base = threadIdx.x; base < N; base += kHostGroup * BS) {
+        for (int base = wg * kHostGroup * BS + threadIdx.x; base < N; base += nwg * kHostGroup * BS) {
             int uu[kHostGroup], up_u[kHostGroup], eu[kHostGroup], pu[kHostGroup];
             int pbw_acc[kHostGroup], up_acc[kHostGroup], hop_acc[kHostGroup], feas[kHostGroup];
             int oute[kHostGroup], outp[kHostGroup];
