@@ -28,7 +28,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc into oracle/liboracle.so."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -52,6 +52,16 @@ def method(kind=TOPSIS, crit=(CRIT_CPU, CRIT_RAM, CRIT_ACTIVE, CRIT_PATHBW), cos
     return m
 
 
+def build_variant(src_text: str, out_path: str) -> str:
+    """Compile oracle C source text (a variant of dc_oracle.c with a planted
+    mistake, written by a test) into out_path."""
+    src = out_path + ".c"
+    with open(src, "w") as f:
+        f.write(src_text)
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", out_path, src, "-lm"])
+    return out_path
+
+
 _lib = None
 
 
@@ -60,37 +70,43 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB):
             build(force=False)
-        L = C.CDLL(_LIB)
-        P = C.c_void_p
-        i32p = np.ctypeslib.ndpointer(np.int32, flags="C")
-        f64p = np.ctypeslib.ndpointer(np.float64, flags="C")
-        i64p = np.ctypeslib.ndpointer(np.int64, flags="C")
-        L.or_create.restype = P
-        L.or_create.argtypes = [C.c_int] * 6 + [P, P]
-        L.or_destroy.argtypes = [P]
-        L.or_num_hosts.argtypes = [P]
-        L.or_get_state.argtypes = [P, i32p]
-        L.or_set_link.argtypes = [P, C.c_int, C.c_int64]
-        L.or_widest_from.argtypes = [P, C.c_int, i64p, i32p]
-        L.or_widest_enum.argtypes = [P, C.c_int, C.c_int, C.POINTER(C.c_int64), i32p, C.POINTER(C.c_int32)]
-        L.or_topsis.argtypes = [C.c_int, C.c_int, f64p, f64p, i32p, f64p]
-        L.or_ahp.argtypes = [C.c_int, C.c_int, f64p, f64p, i32p, C.c_int, f64p, P, P]
-        L.or_saaty.restype = C.c_double
-        L.or_saaty.argtypes = [C.c_double, C.c_double]
-        L.or_diff.restype = C.c_double
-        L.or_diff.argtypes = [C.c_double, C.c_double]
-        L.or_step_scores.argtypes = [P, C.POINTER(Method), C.c_int, C.c_int, C.c_int, i32p, i32p,
-                                     f64p, i32p, f64p]
-        L.or_run_request.argtypes = [P, C.POINTER(Method), C.c_int, i32p, i32p, C.c_int, P, P, P, P, P,
-                                     P, P, P, P, P, P, P, P, P, P, P]
-        L.or_run_request_pods.argtypes = [P, C.POINTER(Method), C.c_int, i32p, i32p, C.c_int, P, P, P, P, P,
-                                          P, P, P, P, P, P, P, P, P, P, P, P]
-        L.or_units.argtypes = [C.c_int, P, i32p, i32p]
-        L.or_release.argtypes = [P, C.c_int64]
-        L.or_get_paths.argtypes = [P, C.c_int64, C.c_int, i32p, i64p]
-        L.or_get_hosts.argtypes = [P, C.c_int64, i32p]
-        _lib = L
+        _lib = load(_LIB)
     return _lib
+
+
+def load(path: str):
+    """Load an oracle library and declare its entry points."""
+    L = C.CDLL(path)
+    P = C.c_void_p
+    i32p = np.ctypeslib.ndpointer(np.int32, flags="C")
+    f64p = np.ctypeslib.ndpointer(np.float64, flags="C")
+    i64p = np.ctypeslib.ndpointer(np.int64, flags="C")
+    L.or_create.restype = P
+    L.or_create.argtypes = [C.c_int] * 6 + [P, P]
+    L.or_destroy.argtypes = [P]
+    L.or_num_hosts.argtypes = [P]
+    L.or_get_state.argtypes = [P, i32p]
+    L.or_set_link.argtypes = [P, C.c_int, C.c_int64]
+    L.or_widest_from.argtypes = [P, C.c_int, i64p, i32p]
+    L.or_widest_enum.argtypes = [P, C.c_int, C.c_int, C.POINTER(C.c_int64), i32p, C.POINTER(C.c_int32)]
+    L.or_topsis.argtypes = [C.c_int, C.c_int, f64p, f64p, i32p, f64p]
+    L.or_ahp.argtypes = [C.c_int, C.c_int, f64p, f64p, i32p, C.c_int, f64p, P, P]
+    L.or_saaty.restype = C.c_double
+    L.or_saaty.argtypes = [C.c_double, C.c_double]
+    L.or_diff.restype = C.c_double
+    L.or_diff.argtypes = [C.c_double, C.c_double]
+    L.or_step_scores.argtypes = [P, C.POINTER(Method), C.c_int, C.c_int, C.c_int, i32p, i32p,
+                                 f64p, i32p, f64p]
+    L.or_run_request.argtypes = [P, C.POINTER(Method), C.c_int, i32p, i32p, C.c_int, P, P, P, P, P,
+                                 P, P, P, P, P, P, P, P, P, P, P, P]
+    L.or_run_request_pods.argtypes = [P, C.POINTER(Method), C.c_int, i32p, i32p, C.c_int, P, P, P, P, P,
+                                      P, P, P, P, P, P, P, P, P, P, P, P, P]
+    L.or_units.argtypes = [C.c_int, P, i32p, i32p]
+    L.or_release.argtypes = [P, C.c_int64]
+    L.or_get_paths.argtypes = [P, C.c_int64, C.c_int, i32p, i64p]
+    L.or_get_hosts.argtypes = [P, C.c_int64, i32p]
+    L.or_set_threads.argtypes = [C.c_int]
+    return L
 
 
 def _ptr(a):
@@ -129,6 +145,13 @@ def units(n, pod=None):
     p = None if pod is None else np.ascontiguousarray(pod, dtype=np.int32)
     nu = lib().or_units(n, _ptr(p), unit, first)
     return unit, first[:nu].copy()
+
+
+def set_threads(n: int = 0) -> int:
+    """Threads the AHP comparison matrices are shared out over (0: keep the
+    current count, from OMP_NUM_THREADS or the CPU count); the results do not
+    depend on it.  Returns the count in effect."""
+    return lib().or_set_threads(n)
 
 
 def saaty(p, q) -> float:
@@ -201,7 +224,10 @@ class Oracle:
         rec_id, the allocations cpu_a, ram_a (per container) and bw_a (per
         edge) of an accepted request and, with detail=True, the per-step own
         choice / top score / top-two gap / chosen score (ref_host, ref_top,
-        ref_gap, step_scores).  A step places one pod (one container without
+        ref_gap, step_scores) and, when following, tie_low: per step the
+        lowest-index server below the followed one with identical criteria
+        that is feasible and commits (-1 when none; anything else breaks
+        the lowest-index rule on exact ties).  A step places one pod (one container without
         pods); follow and the per-step outputs are indexed by step.  The
         request's cpu, ram and edge demands are minima; optional cpu_max,
         ram_max and bw_max give the interval maxima (section II-A)."""
@@ -226,6 +252,7 @@ class Oracle:
         rh = np.full(nu, -1, dtype=np.int32) if detail else None
         rt = np.zeros(nu) if detail else None
         rg = np.zeros(nu) if detail else None
+        tl = np.full(nu, -1, dtype=np.int32) if detail else None
         dmp = np.zeros((nu, self.N)) if dump else None
         fa = np.zeros(1, dtype=np.int32)
         rid = np.zeros(1, dtype=np.int64)
@@ -233,17 +260,17 @@ class Oracle:
             st = lib().or_run_request(self.h, C.byref(self.m), n, cpu, ram, req.m, _ptr(edges), _ptr(cx),
                                       _ptr(rx), _ptr(bx), _ptr(fol), _ptr(host), _ptr(score), _ptr(rh),
                                       _ptr(rt), _ptr(rg), _ptr(dmp), _ptr(fa), _ptr(rid), _ptr(cpu_a),
-                                      _ptr(ram_a), _ptr(bw_a))
+                                      _ptr(ram_a), _ptr(bw_a), _ptr(tl))
         else:
             st = lib().or_run_request_pods(self.h, C.byref(self.m), n, cpu, ram, req.m, _ptr(edges), _ptr(cx),
                                            _ptr(rx), _ptr(bx), _ptr(pod), _ptr(fol), _ptr(host), _ptr(score),
                                            _ptr(rh), _ptr(rt), _ptr(rg), _ptr(dmp), _ptr(fa), _ptr(rid),
-                                           _ptr(cpu_a), _ptr(ram_a), _ptr(bw_a))
+                                           _ptr(cpu_a), _ptr(ram_a), _ptr(bw_a), _ptr(tl))
         out = dict(status=st, hosts=host, scores=score, failed_at=int(fa[0]), rec_id=int(rid[0]),
                    cpu_a=cpu_a, ram_a=ram_a, bw_a=bw_a[: req.m])
         if detail:
             unit, first = units(n, pod)
-            out.update(ref_host=rh, ref_top=rt, ref_gap=rg, step_scores=score[first])
+            out.update(ref_host=rh, ref_top=rt, ref_gap=rg, step_scores=score[first], tie_low=tl)
         if dump:
             out["dump"] = dmp
         return out

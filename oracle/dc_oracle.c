@@ -30,6 +30,7 @@
  * "parity unpinned".
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -178,6 +179,13 @@ void or_destroy(or_dc *d) {
 }
 
 int or_num_hosts(const or_dc *d) { return d->N; }
+
+/* Threads the AHP matrices are shared out over (results do not depend on
+ * it); returns the count in effect. */
+int or_set_threads(int n) {
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+}
 int or_num_nodes(const or_dc *d) { return d->n_nodes; }
 
 /* State in the shared SoA order: cpu, ram, nplaced, uplink, edge-agg, agg-core. */
@@ -350,10 +358,17 @@ static double compare(int scale, double p, double q) {
 
 /* Local rank of a pairwise matrix A (n x n, row-major): normalise each
  * column by its sum, then average each row (Eqs. (9)-(10)). */
+/* Threads (OpenMP) share out whole columns and whole rows; each sum still
+ * adds its terms in index order, so the results do not depend on the thread
+ * count. */
 static void local_rank(int n, const double *A, double *L) {
     double *col = (double *)calloc(n, sizeof(double));
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) col[j] += A[(size_t)i * n + j];
+    const int J = 64;
+#pragma omp parallel for schedule(static) if (n >= 1024)
+    for (int j0 = 0; j0 < n; j0 += J)
+        for (int i = 0; i < n; ++i)
+            for (int j = j0; j < j0 + J && j < n; ++j) col[j] += A[(size_t)i * n + j];
+#pragma omp parallel for schedule(static) if (n >= 1024)
     for (int i = 0; i < n; ++i) {
         double s = 0.0;
         for (int j = 0; j < n; ++j) s += A[(size_t)i * n + j] / col[j];
@@ -377,6 +392,7 @@ void or_ahp(int N, int C, const double *X, const double *w, const int32_t *cost,
     double *P2 = (double *)malloc(sizeof(double) * (size_t)C * N);
     for (int c = 0; c < C; ++c) {
         const double *x = X + (size_t)c * N;
+#pragma omp parallel for schedule(static) if (N >= 1024)
         for (int i = 0; i < N; ++i)
             for (int j = 0; j < N; ++j)
                 M2[(size_t)i * N + j] = cost[c] ? compare(scale, x[j], x[i]) : compare(scale, x[i], x[j]);
@@ -542,6 +558,12 @@ static int cmp_cand(const void *x, const void *y) {
 /* Per step outputs (nullable): own choice, its score, the score gap to the */
 /* second commit-successful server, the score of the committed server, and */
 /* the full score vector (n x N).                                          */
+/* tie_low (nullable, per step, lockstep mode): the lowest-index server    */
+/* below the followed one whose criteria are identical to it, which is     */
+/* feasible and whose commit succeeds, or -1.  Such a server has the same  */
+/* score, so the scan in (score desc, index asc) order reaches it first:   */
+/* any other entry than -1 means the followed side broke the exact-tie     */
+/* rule of the decreasing-order selection (section V-C).                   */
 /* Demand intervals (nullable, then max = min): cpu_max, ram_max per       */
 /* container, bw_max per edge (edges hold the minimum).  Allocations       */
 /* (nullable outputs, accepted requests): cpu_a, ram_a per container and    */
@@ -555,7 +577,7 @@ int or_run_request(or_dc *d, const or_method *m, int n, const int32_t *cpu, cons
                    const int32_t *bw_max, const int32_t *follow,
                    int32_t *host_out, double *score_out, int32_t *ref_host, double *ref_top,
                    double *ref_gap, double *dump, int32_t *failed_at, int64_t *rec_id,
-                   int32_t *cpu_a, int32_t *ram_a, int32_t *bw_a) {
+                   int32_t *cpu_a, int32_t *ram_a, int32_t *bw_a, int32_t *tie_low) {
     int N = d->N;
     if (n <= 0) return -1;
     for (int i = 0; i < n; ++i)
@@ -616,6 +638,20 @@ int or_run_request(or_dc *d, const or_method *m, int n, const int32_t *cpu, cons
         if (follow) {
             if ((follow[i] < 0) != (top1 < 0)) { status = -3; fail_i = i; break; }
             take = follow[i];
+        }
+        if (tie_low) {
+            tie_low[i] = -1;
+            for (int v = 0; take >= 0 && v < take && tie_low[i] < 0; ++v) {
+                if (!feas[v]) continue;
+                int same = 1;
+                for (int c = 0; c < m->ncrit; ++c)
+                    if (X[(size_t)c * N + v] != X[(size_t)c * N + take]) same = 0;
+                int c_a, r_a;
+                if (same && try_commit(d, v, cpu[i], cx, ram[i], rx, Pc, ph, pbw, pbx, tmp, &c_a, &r_a)) {
+                    undo_commit(d, v, c_a, r_a, Pc, tmp);
+                    tie_low[i] = v;
+                }
+            }
         }
         if (take < 0) { status = 0; fail_i = i; break; }
         if (!try_commit(d, take, cpu[i], cx, ram[i], rx, Pc, ph, pbw, pbx, paths + (size_t)i * n, ca + i, ra + i)) {
@@ -755,7 +791,7 @@ int or_run_request_pods(or_dc *d, const or_method *m, int n, const int32_t *cpu,
                         const int32_t *bw_max, const int32_t *pod, const int32_t *follow,
                         int32_t *host_out, double *score_out, int32_t *ref_host, double *ref_top,
                         double *ref_gap, double *dump, int32_t *failed_at, int64_t *rec_id,
-                        int32_t *cpu_a, int32_t *ram_a, int32_t *bw_a) {
+                        int32_t *cpu_a, int32_t *ram_a, int32_t *bw_a, int32_t *tie_low) {
     if (n <= 0) return -1;
     int32_t *unit = (int32_t *)malloc(sizeof(int32_t) * n), *first = (int32_t *)malloc(sizeof(int32_t) * n);
     int nu = or_units(n, pod, unit, first);
@@ -803,7 +839,7 @@ int or_run_request_pods(or_dc *d, const or_method *m, int n, const int32_t *cpu,
         }
     }
     st = or_run_request(d, m, nu, cu, ru, mu, ue, cux, rux, uex, follow, hu, su, ref_host, ref_top, ref_gap, dump,
-                        &fu, rec_id, cua, rua, uea);
+                        &fu, rec_id, cua, rua, uea, tie_low);
     for (int i = 0; i < n; ++i) {
         if (host_out) host_out[i] = st == 1 ? hu[unit[i]] : -1;
         if (score_out) score_out[i] = su[unit[i]];

@@ -4,7 +4,8 @@ The oracle replays every request and, at each container step, follows the
 server the GPU chose.  It checks that choice against its own ranking:
 equal to the oracle's best commit-successful server whenever the oracle's
 top-two score gap exceeds the tolerance, otherwise scored within the
-tolerance of the best.  The integer state (CPU, RAM, placed counts, link
+tolerance of the best, and never above a feasible, commit-successful server
+of lower index with identical criteria (exact ties go to the lowest index).  The integer state (CPU, RAM, placed counts, link
 residuals) must then be identical after every request.  Recorded GPU
 score vectors are compared element by element with the oracle's.
 """
@@ -67,6 +68,10 @@ def lockstep(o, sched, ids, reqs, results, tol=TOL, trace=None, check_paths=Fals
                 assert ref["ref_host"][i] < 0, f"request {pos} step {i}: oracle found a server"
                 continue
             top = ref["ref_top"][i]
+            # exact ties (identical criteria) resolve to the lowest index
+            assert ref["tie_low"][i] < 0, (
+                f"request {pos} step {i}: gpu took server {follow[i]}, but server {ref['tie_low'][i]} has "
+                f"identical criteria, is feasible and commits")
             if follow[i] != ref["ref_host"][i]:
                 st["near_tie"] += 1
                 assert ref["ref_gap"][i] <= tol * max(abs(top), 1e-30), (

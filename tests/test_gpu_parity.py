@@ -96,6 +96,32 @@ def test_ahp_k32_five_criteria_sampled():
     assert st["scored_steps"] == st["steps"] >= 1
 
 
+def test_ahp_k32_full_requests_every_step():
+    """The large AHP workload at its full size and in the benchmark's launch
+    configuration: k=32 (8,192 servers, criteria over four workgroups), C=5
+    with hops as a cost, the first two requests whole (52 and 61
+    containers).  Containers with more placed peers than one peer chunk (16
+    at this size) build the path tables in several chunks and carry partial
+    criteria between them; 43 steps here do.  Every step's score vector,
+    placement, path and the state after each request against the oracle
+    (threaded over the comparison matrices)."""
+    insts, reqs = make_config("ahp", seed=0, n_req=2)
+    peers = [sum(1 for e in r.edges if max(e[0], e[1]) == i) for r in reqs[0] for i in range(r.n)]
+    assert sum(p > 16 for p in peers) >= 40
+    O.set_threads(0)
+    s = dc.Scheduler(insts, method=dc.DC_AHP, crit=C5, cost=C5_COST, trace_stride=1, trace_cap=128)
+    o = O.Oracle(insts[0], _omethod(O.AHP, crit=C5, cost=C5_COST))
+    steps = 0
+    for req in reqs[0]:
+        rid = s.submit(req)
+        res = {r.req_id: r for r in s.schedule()}
+        st = lockstep(o, s, [rid], [req], res, trace=trace_by_request(s), check_paths=True)
+        assert st["scored_steps"] == st["steps"]
+        steps += st["steps"]
+    assert steps == len(peers)
+    s.close()
+
+
 @pytest.mark.parametrize("k", [20, 34])
 def test_ahp_saaty_sorted_and_pairwise_sizes(k):
     """The 1-9 scale through both forms of the column and row sums: k=20
@@ -217,6 +243,29 @@ def test_batched_256_instances_sampled():
         lockstep(o, s, ids[i], reqs[i], res, instance=i)
     for i in range(len(insts)):
         assert s.state(i).min() >= 0
+
+
+def test_batched_full_workload_instances():
+    """The batched workload at its full size, in the benchmark's launch
+    configuration (256 instances, every request, autotuned workgroup, HIP
+    graph): the instance with the most container steps, the one with the
+    fewest and two more replayed whole by the oracle in lockstep, with the
+    state after the last request."""
+    insts, reqs = make_config("batched", seed=0)
+    s = dc.Scheduler(insts, mode=dc.DC_MODE_BATCHED)
+    ids = [[s.submit(r, instance=i) for r in rl] for i, rl in enumerate(reqs)]
+    s.autotune()
+    res = {r.req_id: r for r in s.schedule()}
+    steps = np.array([sum(res[q].n if res[q].status == 1 else res[q].failed_at + 1 for q in ids[i])
+                      for i in range(len(insts))])
+    pick = [int(steps.argmax()), int(steps.argmin()), 1, 200]
+    assert steps.max() > 5000
+    for i in pick:
+        o = O.Oracle(insts[i], _omethod(O.TOPSIS))
+        st = lockstep(o, s, ids[i], reqs[i], res, instance=i, check_paths=(i == pick[0]))
+        assert st["steps"] == steps[i] and st["requests"] == len(reqs[i])
+        o.close()
+    s.close()
 
 
 def test_autotune_keeps_results():
@@ -341,10 +390,11 @@ def test_grid_k16_matches_single_workgroup():
 
 
 def test_grid_k48_sampled():
-    """k=48 (27,648 hosts, 48 cooperative workgroups, the default there): a
-    prefix in lockstep, score vectors on sampled steps."""
+    """k=48 (27,648 hosts) on the cooperative step (grid = 2: 48
+    workgroups, one per pod): a prefix in lockstep, score vectors on sampled
+    steps."""
     insts, reqs = make_config("serving", seed=1, n_req=6)
-    s, ids, res = _run(insts, reqs, trace_stride=7, trace_cap=64)
+    s, ids, res = _run(insts, reqs, grid=2, trace_stride=7, trace_cap=64)
     o = O.Oracle(insts[0], _omethod(O.TOPSIS))
     st = lockstep(o, s, ids[0], reqs[0], res, trace=trace_by_request(s), check_paths=True)
     assert st["scored_steps"] >= 1
@@ -642,10 +692,10 @@ def test_route_end_k16_forms_agree():
 
 
 def test_route_end_k48_cooperative_sampled():
-    """k=48 (cooperative step, workgroup 0 routes the request's links):
-    lockstep on a prefix, score vectors sampled."""
+    """k=48 on the cooperative step (grid = 2; workgroup 0 routes the
+    request's links): lockstep on a prefix, score vectors sampled."""
     insts, reqs = make_config("serving", seed=3, n_req=6)
-    s, ids, res = _run(insts, reqs, routing=dc.DC_ROUTE_END, trace_stride=5, trace_cap=64)
+    s, ids, res = _run(insts, reqs, grid=2, routing=dc.DC_ROUTE_END, trace_stride=5, trace_cap=64)
     o = O.Oracle(insts[0], O.method(kind=O.TOPSIS, route_end=True))
     st = lockstep(o, s, ids[0], reqs[0], res, trace=trace_by_request(s), check_paths=True)
     assert st["scored_steps"] >= 1

@@ -7,7 +7,7 @@ import pytest
 
 import oracle as O
 from parity import lockstep, TOL
-from workloads import make_config, make_requests
+from workloads import make_config, make_requests, make_trace
 
 pytestmark = pytest.mark.gpu
 
@@ -144,3 +144,42 @@ def test_serving_k48_sampled():
     res = {r.req_id: r for r in s.drain()}
     o = O.Oracle(insts[0], O.method(kind=O.TOPSIS))
     lockstep(o, s, ids, reqs, res, check_paths=True)
+
+
+def test_serving_k48_trace_prefix_alone_equals_mix_and_oracle():
+    """The serving workload's shape at full size: k=48 (27,648 servers,
+    0-70 % background), the first 120 requests of the Poisson trace (2-64
+    containers), every second one after the 15th followed by the departure
+    of the request 15 before it.  The cooperative serving kernel (one
+    workgroup per pod, the default at this size) with commands in flight
+    against the single-workgroup kernel one command at a time: identical
+    results and state; and the oracle, replaying the same commands, in
+    lockstep with every request and the state at the end."""
+    insts, _ = make_config("serving", seed=0, n_req=1)
+    reqs, _, _ = make_trace(seed=0, duration_s=0.05)
+    reqs = reqs[:120]
+    cmds = _commands(reqs)
+    assert sum(1 for c in cmds if c[0] == "release") >= 50
+    mix = dc.Scheduler(insts, mode=dc.DC_MODE_SERVING)
+    ids_m, res_m = _replay(mix, reqs, cmds, alone=False)
+    alone = dc.Scheduler(insts, mode=dc.DC_MODE_SERVING, grid=1)
+    ids_a, res_a = _replay(alone, reqs, cmds, alone=True)
+    for t in range(len(reqs)):
+        a, b = res_m[ids_m[t]], res_a[ids_a[t]]
+        assert (a.status, a.failed_at) == (b.status, b.failed_at), t
+        np.testing.assert_array_equal(a.hosts, b.hosts)
+        np.testing.assert_array_equal(a.scores.view(np.uint32), b.scores.view(np.uint32))
+    np.testing.assert_array_equal(mix.state(0), alone.state(0))
+    alone.close()
+    o = O.Oracle(insts[0], O.method(kind=O.TOPSIS))
+    rec, steps = {}, 0
+    for kind, t in cmds:
+        if kind == "submit":
+            st = lockstep(o, mix, [ids_m[t]], [reqs[t]], res_m, check_paths=True, final_state=False)
+            rec[t] = st["rec_ids"][0]
+            steps += st["steps"]
+        elif res_m[ids_m[t]].status == 1:
+            assert o.release(rec[t]) == 0
+    np.testing.assert_array_equal(mix.state(0), o.state())
+    assert steps > 3000 and sum(r.status for r in res_m.values()) > 60
+    mix.close()
