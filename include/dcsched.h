@@ -5,7 +5,7 @@
  * (arXiv 1909.07673).
  *
  * Model (section II-A, Table I): a k-ary fat-tree data center G^s(N^s,E^s)
- * (section IV-A) with N = k^3/4 servers, each with available CPU and RAM
+ * (section IV-B) with N = k^3/4 servers, each with available CPU and RAM
  * c^s_u[r], and one available bandwidth bw^s_uv per undirected link (the
  * shared u->v / v->u link of section V-D).  A tenant request Req(N^c,E^c)
  * has n containers with CPU/RAM demands and bandwidth demands between
@@ -134,8 +134,12 @@ typedef struct dc_result {
     float score[DC_MAX_CONTAINERS];   /* score of the chosen server                */
 } dc_result;
 
-/* Create a context: device-resident state for n_instances data centers,
- * with the background load applied.  Returns DC_EINVAL for odd or out of
+/* Create a context: device-resident state for n_instances data centers
+ * G^s(N^s, E^s) (section II-A, Table I), each a k-ary fat-tree of
+ * section IV-B (DC configuration) with the per-server CPU / RAM and
+ * per-level link capacities of cfg, with the background load applied (the
+ * available capacities c^s_u[r] and bw^s_uv of section II-A).  The context
+ * owns all device memory; cfg and its arrays are copied.  Returns DC_EINVAL for odd or out of
  * range k, ncrit out of range, unknown criterion, non-positive weights or
  * weights not summing to 1, DC_ENOMEM, DC_EDEVICE. */
 int dc_create(const dc_config *cfg, dc_ctx **out);
@@ -161,10 +165,12 @@ int dc_submit_request(dc_ctx *ctx, int32_t instance, int32_t n, const int32_t *c
  * (section II-A): a container runs with any CPU and RAM in
  * [cpu_min[i], cpu_max[i]] and [ram_min[i], ram_max[i]], a pair with any
  * bandwidth in [edges[q][2], bw_max[q]].  Every feasibility check uses the
- * minima.  Since the utilities U(i), U(ij) of Eqs. (1)-(2) grow with what is
- * given, a placement takes as much as the chosen server has left, up to the
- * maximum, and each routed pair min(maximum, path bottleneck); a pair on
- * one server (or inside a pod) gets its maximum.  A pod asks for the sums of
+ * minima.  Since the utilities U(i), U(ij) (section II-B, Eqs. (1)-(2))
+ * grow with what is given, once every minimum fits a placement takes as
+ * much CPU and RAM as the chosen server has left, up to the maximum, and
+ * each routed pair, in peer order, is topped up by what its path still has,
+ * up to its maximum; a pair on one server (or inside a pod) gets its
+ * maximum.  A pod asks for the sums of
  * its containers' minima and maxima, and two pods' traffic for the sums of
  * their edges' minima and maxima.  cpu_max, ram_max, bw_max may each be
  * NULL (maximum = minimum, which is dc_submit_request).  DC_EINVAL when a
@@ -176,7 +182,12 @@ int dc_submit_request_ranged(dc_ctx *ctx, int32_t instance, int32_t n, const int
                              const int32_t *ram_max, int32_t m, const int32_t *edges,
                              const int32_t *bw_max, const int32_t *pod, int64_t *req_id);
 
-/* Plain and batched forms: schedule every queued request (FCFS per
+/* The scheduling decision of section II-A (accept or reject each request,
+ * with its mapping M_c) by the selection of section V-C: per container, in
+ * FCFS order, every server scored, servers taken in decreasing score (lowest
+ * index on ties), the first on which the container and its paths fit
+ * (Eqs. (4)-(5)) kept; all or nothing per request.
+ * Plain and batched forms: schedule every queued request (FCFS per
  * instance) and block until done; results of the scheduled requests go to
  * out[0..*n_out) in request id order (at most max_results are written; the
  * rest stay available to the next call).  Serving form: non-blocking poll of
@@ -194,20 +205,22 @@ int dc_submit_request_ranged(dc_ctx *ctx, int32_t instance, int32_t n, const int
  * relaunched by the next call; dc_destroy stops it. */
 int dc_schedule(dc_ctx *ctx, int32_t max_results, dc_result *out, int32_t *n_out);
 
-/* Departure of an accepted request: gives back its CPU, RAM and path
- * bandwidth.  DC_ENOENT for unknown, rejected, pending or released ids. */
+/* Departure of an accepted request (the end of its duration in the event
+ * replay of section VI-A): gives back its CPU, RAM and path bandwidth.  DC_ENOENT for unknown, rejected, pending or released ids. */
 int dc_release(dc_ctx *ctx, int64_t req_id);
 
-/* Links of an accepted request's routed pairs (M_ec): 6 link ids per
+/* Links of an accepted request's routed pairs (the mapping M_ec of section
+ * II-A; each pair's widest shortest path of section V-D): 6 link ids per
  * routed pod pair (a container pair without pods), in the order the pods
  * were placed, then ascending earlier pod, -1 padded (a co-located pair
  * uses no link).  Link id = level*N + index. *n receives the number of
  * pairs; at most cap pairs are written. */
 int dc_get_paths(dc_ctx *ctx, int64_t req_id, int32_t cap, int32_t *link_ids, int32_t *n);
 
-/* What an accepted request was given (section II-A, for the utilities of
- * Eqs. (1)-(2)): cpu[n], ram[n] per container and bw[m] per edge, in
- * submission order (each may be NULL).  A pod's CPU and RAM, and the
+/* What an accepted request was given (the [min, max] demands of section
+ * II-A, for the utilities of section II-B, Eqs. (1)-(2)): cpu[n], ram[n]
+ * per container and bw[m] per edge, in submission order (each may be
+ * NULL).  A pod's CPU and RAM, and the
  * bandwidth between two pods, go back to its containers (edges) in order:
  * each first gets its minimum, then what is left up to each one's maximum in
  * turn.  DC_ENOENT for unknown, pending, rejected or (serving form) released

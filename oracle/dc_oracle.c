@@ -11,7 +11,7 @@
  * What it follows:
  *   - DC graph G^s(N^s,E^s), available capacities c^s_u[r] and available
  *     link bandwidth bw^s_uv:            section II-A, Table I.
- *   - k-ary fat-tree topology:           section IV-A (k^3/4 servers).
+ *   - k-ary fat-tree topology:           section IV-B (k^3/4 servers).
  *   - criteria c^s_u + bw^s_u + f_u:     section V, opening paragraphs.
  *   - AHP (M1, M2, pairwise comparison, normalisation, local ranks L1/L2,
  *     global priority PG):               section V-B, Eqs. (9)-(10).
@@ -21,8 +21,9 @@
  *     with one residual per undirected link: section V-D.
  *   - capacity / bandwidth constraints Eqs. (4)-(5) and the accept/reject
  *     decision with mappings M_c, M_ec: sections II-A and III-B.
- *   - demands given as minimum / maximum intervals and the utilities
- *     U(i), U(ij) of what is allocated: section II-A, Eqs. (1)-(2).
+ *   - demands given as minimum / maximum intervals: section II-A; the
+ *     utilities U(i), U(ij) of what is allocated: section II-B,
+ *     Eqs. (1)-(2).
  * Readings where the paper is silent or garbled are listed beside the code.
  *
  * Parity pins: every function here is pinned by the CPU tests (hand-worked
@@ -76,7 +77,7 @@ typedef struct {
 } or_dc;
 
 /* ------------------------------------------------------------------ */
-/* Explicit fat-tree graph (section IV-A: k-port switches, k^3/4 servers). */
+/* Explicit fat-tree graph (section IV-B: k-port switches, k^3/4 servers). */
 /* Node ids: hosts [0,N), edge switches [N, N+E), aggregation switches     */
 /* [N+E, N+2E), core switches after.  Link ids: level*N + index, with the  */
 /* index conventions of the shared input format.                           */

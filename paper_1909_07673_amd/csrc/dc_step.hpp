@@ -6,12 +6,13 @@
 //
 // Paper references (arXiv 1909.07673):
 //   section II-A / Table I  data-center graph, capacities, requests
-//   section IV-A            k-ary fat-tree
+//   section IV-B            k-ary fat-tree (DC configuration)
 //   section V               criteria c^s_u, bw^s_u, f_u
 //   section V-C             TOPSIS
 //   section V-D             widest shortest path, one residual per undirected link
 //   Eqs. (4)-(5)            capacity and bandwidth constraints
-//   section II-A, Eqs. (1)-(2)  demand intervals [min, max] and their utilities
+//   section II-A            demand intervals [min, max]
+//   section II-B, Eqs. (1)-(2)  their utilities
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>

@@ -6,7 +6,7 @@ traces).  It holds none of the scheduling method's arithmetic, so both the
 FP64 oracle and the GPU library can be fed from it without sharing code.
 
 Shared format (indices are the fat-tree conventions of the paper's DC graph,
-section II-A, with the k-ary fat-tree of section IV-A):
+section II-A, with the k-ary fat-tree of section IV-B):
   * hosts  h = p*(k/2)^2 + e*(k/2) + s        (pod p, edge switch e, slot s)
   * edge switch global index  eg = h // (k/2) = p*(k/2) + e
   * aggregation switch index  ag = p*(k/2) + a
