@@ -253,12 +253,47 @@ int dc_rewind(dc_ctx *ctx);
  * scores[s][N] float.  *n receives the number of recorded steps. */
 int dc_get_trace(dc_ctx *ctx, int32_t cap, int32_t *meta, float *scores, int32_t *n);
 
-/* Plain and batched forms: time every candidate workgroup size (256, 512,
- * 1024 threads) on the queued workload (on a scratch copy of the state),
- * keep the fastest for later dc_schedule calls, and return it in *block.
- * The state and queue are left unchanged.  DC_ESTATE when nothing is
- * queued or in the serving form. */
+/* Launch shape of the scheduling kernel: threads per workgroup, servers
+ * each thread scores together in the criteria and selection loops, and
+ * placed peers whose path tables are built together (a container with more
+ * peers builds them in several chunks).  None of these changes a result:
+ * every shape gives bit-identical scores, placements and state. */
+typedef struct dc_tune {
+    int32_t block;       /* threads per workgroup                                 */
+    int32_t host_group;  /* servers per thread per pass                           */
+    int32_t peer_chunk;  /* peers per path-table chunk                            */
+    int32_t from_cache;  /* 1: read from the cache file, 0: measured              */
+    float ms;            /* device time of one pass over the queued work          */
+    int32_t candidates;  /* shapes timed (0 when read from the cache)             */
+} dc_tune;
+
+/* Plain and batched forms: time every candidate shape on the queued
+ * workload (on a scratch copy of the state, recording no trace), keep the
+ * fastest for later dc_schedule calls, and return it.  Batched form: every
+ * built (block, host_group) pair -- (256|512, 1|2|4) and (1024, 1|2) --
+ * with the largest peer chunk the workgroup's LDS holds, 32 and 16; plain
+ * form: blocks 256, 512, 1024 (not above the server count) with their fixed
+ * grouping.  cache_path (nullable): a text file of JSON objects, one per
+ * line, keyed by device architecture, form, method, server count and
+ * criterion count; a shape found there for this context is taken without
+ * timing, and a measured one is written there (a file that cannot be
+ * written is left as it was).  The state, queue and trace are left
+ * unchanged.  DC_ESTATE when nothing is queued and the cache has no entry,
+ * or in the serving form. */
+int dc_autotune_cached(dc_ctx *ctx, const char *cache_path, dc_tune *out);
+
+/* dc_autotune_cached without a cache; *block receives the chosen workgroup
+ * size. */
 int dc_autotune(dc_ctx *ctx, int32_t *block);
+
+/* Batched form: launch with the given shape from the next dc_schedule on
+ * (from_cache, ms and candidates are ignored).  DC_EINVAL for a shape that
+ * is not built or a peer chunk outside 1..the largest the LDS holds;
+ * DC_ESTATE in the other forms. */
+int dc_set_shape(dc_ctx *ctx, const dc_tune *shape);
+
+/* The shape the next dc_schedule launches with (ms and candidates 0). */
+int dc_get_shape(dc_ctx *ctx, dc_tune *shape);
 
 /* Work not yet decided: in the serving form the commands (requests and
  * departures) published but not completed, otherwise the requests queued

@@ -44,6 +44,14 @@ class dc_result(C.Structure):
                 ("host", C.c_int32 * DC_MAX_CONTAINERS), ("score", C.c_float * DC_MAX_CONTAINERS)]
 
 
+class dc_tune(C.Structure):
+    _fields_ = [("block", C.c_int32), ("host_group", C.c_int32), ("peer_chunk", C.c_int32),
+                ("from_cache", C.c_int32), ("ms", C.c_float), ("candidates", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 # dc_result as a NumPy record (same layout), for bulk result transfer.
 RESULT_DTYPE = np.dtype([("req_id", np.int64), ("instance", np.int32), ("status", np.int32),
                          ("n", np.int32), ("failed_at", np.int32),
@@ -84,6 +92,9 @@ def lib():
         L.dc_rewind.argtypes = [P]
         L.dc_get_trace.argtypes = [P, C.c_int32, i32p, C.POINTER(C.c_float), C.POINTER(C.c_int32)]
         L.dc_autotune.argtypes = [P, C.POINTER(C.c_int32)]
+        L.dc_autotune_cached.argtypes = [P, C.c_char_p, C.POINTER(dc_tune)]
+        L.dc_set_shape.argtypes = [P, C.POINTER(dc_tune)]
+        L.dc_get_shape.argtypes = [P, C.POINTER(dc_tune)]
         L.dc_last_timing.argtypes = [P, C.POINTER(C.c_float), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.dc_pending.argtypes = [P, C.POINTER(C.c_int64)]
         L.dc_topsis_tiles.argtypes = [C.c_int64, C.c_int32, C.c_int32, P, P, i32p, C.POINTER(C.c_float), P, P, P, P]
@@ -288,6 +299,24 @@ class Scheduler:
         b = C.c_int32()
         _check(lib().dc_autotune(self._ctx, C.byref(b)), "dc_autotune")
         return b.value
+
+    def autotune_cached(self, cache_path: Optional[str] = None) -> dict:
+        """dc_autotune_cached: the chosen shape (block, host_group,
+        peer_chunk), whether it came from the cache, its time and the number
+        of shapes timed."""
+        t = dc_tune()
+        path = cache_path.encode() if cache_path else None
+        _check(lib().dc_autotune_cached(self._ctx, path, C.byref(t)), "dc_autotune_cached")
+        return t.as_dict()
+
+    def set_shape(self, block: int, host_group: int, peer_chunk: int):
+        t = dc_tune(block, host_group, peer_chunk, 0, 0.0, 0)
+        _check(lib().dc_set_shape(self._ctx, C.byref(t)), "dc_set_shape")
+
+    def shape(self) -> dict:
+        t = dc_tune()
+        _check(lib().dc_get_shape(self._ctx, C.byref(t)), "dc_get_shape")
+        return {"block": t.block, "host_group": t.host_group, "peer_chunk": t.peer_chunk}
 
     def pending(self) -> int:
         n = C.c_int64()

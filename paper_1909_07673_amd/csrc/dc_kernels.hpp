@@ -617,8 +617,9 @@ __host__ __device__ inline size_t req_lds_ints() { return 6 * (size_t)kMaxN + 4 
 // One persistent workgroup per data-center instance: the instance's state,
 // the per-server scratch and the request being scheduled live in LDS for
 // the whole launch; the workgroup walks its requests in FCFS order and
-// their containers in index order.
-template <int BS>
+// their containers in index order.  Each thread scores G servers together
+// (the autotuner picks BS and G, and the peer chunk p.pc_cap).
+template <int BS, int G>
 __global__ __launch_bounds__(BS) void k_topsis_batched(Params p) {
     extern __shared__ __align__(16) char dsm[];
     const int inst = blockIdx.x;
@@ -661,10 +662,7 @@ __global__ __launch_bounds__(BS) void k_topsis_batched(Params p) {
             const StepIn s{r, i, n, g0, g0 + i, pb + q0, rq_poff[i + 1] - q0, rq_cpu[i], rq_ram[i],
                            rq_cmax[i], rq_rmax[i]};
             const ReqView rv{rq_pj + q0, rq_pbw + q0, rq_host, rq_host, rq_pbmax + q0};
-            // one server per thread at 1024 threads keeps the loop in registers
-            if (!topsis_step<BS, BS >= 1024 ? 1 : host_group(BS), true>(p.t, st, p.m, lb, sm, xs, p.pc_cap, p.tr, inst,
-                                                                  s, rv))
-                break;
+            if (!topsis_step<BS, G, true>(p.t, st, p.m, lb, sm, xs, p.pc_cap, p.tr, inst, s, rv)) break;
         }
         __syncthreads();
     }

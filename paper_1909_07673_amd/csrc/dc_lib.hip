@@ -12,8 +12,11 @@
 #include <cstdio>
 #include <cstring>
 #include <chrono>
+#include <fstream>
 #include <map>
 #include <memory>
+#include <sstream>
+#include <string>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -21,6 +24,22 @@
 using namespace dcs;
 
 namespace {
+
+// Launch shape of the batched kernel: threads per workgroup, servers each
+// thread scores together, peers whose path tables are built together.
+struct Shape {
+    int bs = 1024, g = 1, pc = 1;
+    bool operator==(const Shape &o) const { return bs == o.bs && g == o.g && pc == o.pc; }
+};
+
+// (threads, servers per thread) pairs the batched kernel is built for.
+constexpr int kBatchedShapes[][2] = {{256, 1}, {256, 2}, {256, 4}, {512, 1}, {512, 2}, {512, 4}, {1024, 1}, {1024, 2}};
+
+bool batched_shape_built(int bs, int g) {
+    for (const auto &x : kBatchedShapes)
+        if (x[0] == bs && x[1] == g) return true;
+    return false;
+}
 
 // A request's containers and edges as submitted, kept so that what each
 // unit and unit pair is given can be handed back to them.
@@ -181,7 +200,7 @@ struct DevBatch {
     std::vector<float> score;
     std::vector<long long> tsb, tse;
     hipGraphExec_t gexec = nullptr;    // batched form: captured launch of this batch
-    int gbs = 0;                       // workgroup size it was captured with
+    Shape gshape{0, 0, 0};             // launch shape it was captured with
     int *pinned = nullptr;             // pinned host copy of the outputs, route codes left out
     ~DevBatch() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -280,8 +299,9 @@ struct dc_ctx {
     int ti_rank = 0, nI_rank = 0;  // row chunks of the rank pass
     int *d_tmeta = nullptr, *d_tcount = nullptr;
     float *d_tscore = nullptr;
-    int plain_bs = 1024, batched_bs = 1024;
-    int pc_plain = 1, pc_batched = 1;
+    int plain_bs = 1024;
+    Shape bshape{};                // batched form: current launch shape
+    int pc_plain = 1, pc_batched = 1;  // peer chunk of the plain form; largest the batched LDS holds
     bool plain_res = false;        // plain kernel stages state + scratch in LDS
     size_t lds_plain = 0, lds_select = 0;
     std::vector<std::unique_ptr<DevBatch>> batches;
@@ -594,25 +614,35 @@ int run_plain(dc_ctx *ctx, DevBatch &b) {
     return DC_OK;
 }
 
-size_t batched_lds(const dc_ctx *ctx) {
-    return step_lds_bytes(ctx->pc_batched, ctx->t.nsw, (size_t)xs_rows(ctx->m.nc) * ctx->N,
-                          6 * (size_t)ctx->N + req_lds_ints());
+size_t batched_lds(const dc_ctx *ctx, int pc) {
+    return step_lds_bytes(pc, ctx->t.nsw, (size_t)xs_rows(ctx->m.nc) * ctx->N, 6 * (size_t)ctx->N + req_lds_ints());
 }
 
-void launch_batched(dc_ctx *ctx, DevBatch &b, int bs, hipStream_t stream) {
+template <int BS, int G>
+void launch_batched_k(dc_ctx *ctx, const Params &p, size_t lds, hipStream_t stream) {
+    hipLaunchKernelGGL((k_topsis_batched<BS, G>), dim3(ctx->I), dim3(BS), lds, stream, p);
+}
+
+// sh must be a built shape with 1 <= sh.pc <= ctx->pc_batched (callers check)
+void launch_batched(dc_ctx *ctx, DevBatch &b, const Shape &sh, hipStream_t stream) {
     Params p = base_params(ctx, b, 0);
-    p.pc_cap = ctx->pc_batched;
-    const size_t lds = batched_lds(ctx);
-    switch (bs) {
-    case 256: hipLaunchKernelGGL((k_topsis_batched<256>), dim3(ctx->I), dim3(256), lds, stream, p); break;
-    case 512: hipLaunchKernelGGL((k_topsis_batched<512>), dim3(ctx->I), dim3(512), lds, stream, p); break;
-    default: hipLaunchKernelGGL((k_topsis_batched<1024>), dim3(ctx->I), dim3(1024), lds, stream, p); break;
+    p.pc_cap = sh.pc;
+    const size_t lds = batched_lds(ctx, sh.pc);
+    switch (sh.bs * 10 + sh.g) {
+    case 2561: launch_batched_k<256, 1>(ctx, p, lds, stream); break;
+    case 2562: launch_batched_k<256, 2>(ctx, p, lds, stream); break;
+    case 2564: launch_batched_k<256, 4>(ctx, p, lds, stream); break;
+    case 5121: launch_batched_k<512, 1>(ctx, p, lds, stream); break;
+    case 5122: launch_batched_k<512, 2>(ctx, p, lds, stream); break;
+    case 5124: launch_batched_k<512, 4>(ctx, p, lds, stream); break;
+    case 10242: launch_batched_k<1024, 2>(ctx, p, lds, stream); break;
+    default: launch_batched_k<1024, 1>(ctx, p, lds, stream); break;
     }
 }
 
 // Captures the batch's launch into a graph on a private stream (capture is
 // not allowed on the legacy default stream a caller may have handed in).
-int capture_batched(dc_ctx *ctx, DevBatch &b, int bs) {
+int capture_batched(dc_ctx *ctx, DevBatch &b, const Shape &sh) {
     if (b.gexec) {
         HIPCHK(hipGraphExecDestroy(b.gexec));
         b.gexec = nullptr;
@@ -620,7 +650,7 @@ int capture_batched(dc_ctx *ctx, DevBatch &b, int bs) {
     if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-    launch_batched(ctx, b, bs, ctx->cap_stream);
+    launch_batched(ctx, b, sh, ctx->cap_stream);
     const hipError_t le = hipGetLastError();
     const hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &g);
     HIPCHK(le);
@@ -628,16 +658,16 @@ int capture_batched(dc_ctx *ctx, DevBatch &b, int bs) {
     const hipError_t ie = hipGraphInstantiate(&b.gexec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     HIPCHK(ie);
-    b.gbs = bs;
+    b.gshape = sh;
     return DC_OK;
 }
 
-int run_batched(dc_ctx *ctx, DevBatch &b, int bs) {
+int run_batched(dc_ctx *ctx, DevBatch &b, const Shape &sh) {
     if (ctx->cfg.graph == 1) {
-        launch_batched(ctx, b, bs, ctx->stream);
+        launch_batched(ctx, b, sh, ctx->stream);
     } else {
-        if (!b.gexec || b.gbs != bs) {
-            const int rc = capture_batched(ctx, b, bs);
+        if (!b.gexec || !(b.gshape == sh)) {
+            const int rc = capture_batched(ctx, b, sh);
             if (rc) return rc;
         }
         HIPCHK(hipGraphLaunch(b.gexec, ctx->stream));
@@ -939,6 +969,92 @@ int serve_stop(dc_ctx *ctx) {
 
 }  // namespace
 
+namespace {
+
+// A shape the current context can launch: a built (threads, servers per
+// thread) pair and a peer chunk its LDS holds (batched form), or a plain
+// workgroup size with its fixed grouping and chunk.
+bool shape_ok(const dc_ctx *ctx, const Shape &sh) {
+    if (ctx->cfg.mode == DC_MODE_BATCHED)
+        return batched_shape_built(sh.bs, sh.g) && sh.pc >= 1 && sh.pc <= ctx->pc_batched;
+    return (sh.bs == 64 || sh.bs == 256 || sh.bs == 512 || sh.bs == 1024) && sh.g == host_group(sh.bs) &&
+           sh.pc == ctx->pc_plain;
+}
+
+// Cache key of a tuned shape: device architecture, form, method, servers,
+// criteria.
+std::string tune_key(const dc_ctx *ctx) {
+    std::string arch = "unknown";
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t colon = arch.find(':');
+        if (colon != std::string::npos) arch.resize(colon);
+    }
+    const char *mode = ctx->cfg.mode == DC_MODE_BATCHED ? "batched" : "plain";
+    const char *method = ctx->cfg.method == DC_AHP ? "ahp" : "topsis";
+    return arch + "|" + mode + "|" + method + "|N=" + std::to_string(ctx->N) + "|C=" + std::to_string(ctx->m.nc);
+}
+
+// The cache is a text file of JSON objects, one per line:
+// {"key": "...", "block": B, "host_group": G, "peer_chunk": P, "ms": T}
+bool field_int(const std::string &line, const char *name, int *v) {
+    const std::string pat = std::string("\"") + name + "\": ";
+    const size_t at = line.find(pat);
+    return at != std::string::npos && std::sscanf(line.c_str() + at + pat.size(), "%d", v) == 1;
+}
+
+std::string line_key(const std::string &line) {
+    const std::string pat = "\"key\": \"";
+    const size_t at = line.find(pat);
+    if (at == std::string::npos) return std::string();
+    const size_t end = line.find('"', at + pat.size());
+    return end == std::string::npos ? std::string() : line.substr(at + pat.size(), end - at - pat.size());
+}
+
+bool cache_read(const char *path, const std::string &key, Shape *sh, float *ms) {
+    std::ifstream in(path);
+    std::string line;
+    while (std::getline(in, line)) {
+        if (line_key(line) != key) continue;
+        int bs = 0, g = 0, pc = 0;
+        if (!field_int(line, "block", &bs) || !field_int(line, "host_group", &g) || !field_int(line, "peer_chunk", &pc))
+            return false;
+        const size_t at = line.find("\"ms\": ");
+        *ms = at == std::string::npos ? 0.f : std::strtof(line.c_str() + at + 6, nullptr);
+        *sh = Shape{bs, g, pc};
+        return true;
+    }
+    return false;
+}
+
+// Replaces (or adds) the key's line; written to a temporary file and renamed
+// into place.  A cache that cannot be written is left as it was.
+void cache_write(const char *path, const std::string &key, const Shape &sh, float ms) {
+    std::vector<std::string> lines;
+    {
+        std::ifstream in(path);
+        std::string line;
+        while (std::getline(in, line))
+            if (!line.empty() && line_key(line) != key) lines.push_back(line);
+    }
+    char buf[512];
+    std::snprintf(buf, sizeof(buf), "{\"key\": \"%s\", \"block\": %d, \"host_group\": %d, \"peer_chunk\": %d, \"ms\": %.4f}",
+                  key.c_str(), sh.bs, sh.g, sh.pc, ms);
+    lines.push_back(buf);
+    const std::string tmp = std::string(path) + ".tmp";
+    {
+        std::ofstream o(tmp, std::ios::trunc);
+        if (!o) return;
+        for (const auto &l : lines) o << l << "\n";
+        if (!o) return;
+    }
+    (void)std::rename(tmp.c_str(), path);
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *dc_strerror(int code) {
@@ -1026,7 +1142,8 @@ int dc_create(const dc_config *cfg, dc_ctx **out) {
     }
     // launch shapes
     c->plain_bs = cfg->block ? cfg->block : (N <= 64 ? 64 : N <= 256 ? 256 : 1024);
-    c->batched_bs = cfg->block ? std::max(256, cfg->block) : 1024;
+    c->bshape.bs = cfg->block ? std::max(256, cfg->block) : 1024;
+    c->bshape.g = c->bshape.bs >= 1024 ? 1 : host_group(c->bshape.bs);
     const size_t lds_max = 159 * 1024;   // 160 KiB of LDS, 1 KiB left for static shared memory
     {
         // plain: state + scratch in LDS when they fit with at least 8 peer tables
@@ -1046,9 +1163,15 @@ int dc_create(const dc_config *cfg, dc_ctx **out) {
         const size_t fixed = step_lds_bytes(0, c->t.nsw, (size_t)xs_rows(nc) * N, 6 * (size_t)N + req_lds_ints());
         if (fixed + 8 * (size_t)c->t.nsw > lds_max) { dc_destroy(ctx.release()); return DC_EINVAL; }
         c->pc_batched = (int)std::min<size_t>(kMaxN, (lds_max - fixed) / (8 * (size_t)c->t.nsw));
-        const size_t lb = batched_lds(c);
-        if (set_lds(c, k_topsis_batched<256>, lb) || set_lds(c, k_topsis_batched<512>, lb) ||
-            set_lds(c, k_topsis_batched<1024>, lb)) { dc_destroy(ctx.release()); return DC_EDEVICE; }
+        c->bshape.pc = c->pc_batched;
+        const size_t lb = batched_lds(c, c->pc_batched);
+        if (set_lds(c, k_topsis_batched<256, 1>, lb) || set_lds(c, k_topsis_batched<256, 2>, lb) ||
+            set_lds(c, k_topsis_batched<256, 4>, lb) || set_lds(c, k_topsis_batched<512, 1>, lb) ||
+            set_lds(c, k_topsis_batched<512, 2>, lb) || set_lds(c, k_topsis_batched<512, 4>, lb) ||
+            set_lds(c, k_topsis_batched<1024, 1>, lb) || set_lds(c, k_topsis_batched<1024, 2>, lb)) {
+            dc_destroy(ctx.release());
+            return DC_EDEVICE;
+        }
     }
     if (set_lds(c, k_topsis_plain<64, true>, c->lds_plain) || set_lds(c, k_topsis_plain<64, false>, c->lds_plain) ||
         set_lds(c, k_topsis_plain<256, true>, c->lds_plain) || set_lds(c, k_topsis_plain<256, false>, c->lds_plain) ||
@@ -1161,7 +1284,7 @@ int dc_schedule(dc_ctx *ctx, int32_t max_results, dc_result *out, int32_t *n_out
         HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
         for (int bi : ctx->queued) {
             DevBatch &b = *ctx->batches[bi];
-            rc = ctx->cfg.mode == DC_MODE_BATCHED ? run_batched(ctx, b, ctx->batched_bs) : run_plain(ctx, b);
+            rc = ctx->cfg.mode == DC_MODE_BATCHED ? run_batched(ctx, b, ctx->bshape) : run_plain(ctx, b);
             if (rc) return rc;
         }
         HIPCHK(hipEventRecord(ctx->ev1, ctx->stream));
@@ -1385,31 +1508,68 @@ int dc_get_trace(dc_ctx *ctx, int32_t cap, int32_t *meta, float *scores, int32_t
 }
 
 int dc_autotune(dc_ctx *ctx, int32_t *block) {
+    dc_tune t{};
+    const int rc = dc_autotune_cached(ctx, nullptr, &t);
+    if (rc == DC_OK && block) *block = t.block;
+    return rc;
+}
+
+int dc_autotune_cached(dc_ctx *ctx, const char *cache_path, dc_tune *out) {
     if (!ctx) return DC_EINVAL;
     if (ctx->poisoned) return DC_EDEVICE;
     if (ctx->cfg.mode == DC_MODE_SERVING) return DC_ESTATE;
     const bool batched = ctx->cfg.mode == DC_MODE_BATCHED;
     int rc = upload_pending(ctx);
     if (rc) return rc;
+    const std::string key = tune_key(ctx);
+    if (cache_path && *cache_path) {
+        Shape sh;
+        float ms = 0.f;
+        if (cache_read(cache_path, key, &sh, &ms) && shape_ok(ctx, sh)) {
+            if (batched) ctx->bshape = sh; else ctx->plain_bs = sh.bs;
+            if (out) *out = dc_tune{sh.bs, sh.g, sh.pc, 1, ms, 0};
+            return DC_OK;
+        }
+    }
     if (ctx->queued.empty()) return DC_ESTATE;
+    std::vector<Shape> cand;
+    if (batched) {
+        std::vector<int> pcs{ctx->pc_batched};
+        for (int pc : {32, 16})
+            if (pc < ctx->pc_batched) pcs.push_back(pc);
+        for (const auto &x : kBatchedShapes)
+            for (int pc : pcs) cand.push_back(Shape{x[0], x[1], pc});
+    } else {
+        for (int bs : {256, 512, 1024})
+            if (bs == 256 || bs <= ctx->N) cand.push_back(Shape{bs, host_group(bs), ctx->pc_plain});   // no idle waves
+    }
+    // tuning runs record no trace and leave the state, the queue, the trace
+    // counters and the current shape as they were
+    struct Restore {
+        dc_ctx *c;
+        int stride, plain_bs;
+        int *saved = nullptr;
+        ~Restore() {
+            c->cfg.trace_stride = stride;
+            c->plain_bs = plain_bs;
+            if (saved) (void)hipFree(saved);
+        }
+    } guard{ctx, ctx->cfg.trace_stride, ctx->plain_bs};
+    ctx->cfg.trace_stride = 0;
     const size_t sbytes = (size_t)ctx->I * 6 * ctx->N * sizeof(int);
-    int *saved = nullptr;
-    HIPCHK(hipMalloc(&saved, sbytes));
-    HIPCHK(hipMemcpyAsync(saved, ctx->d_state, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
-    const int cand[3] = {256, 512, 1024};
+    HIPCHK(hipMalloc(&guard.saved, sbytes));
+    HIPCHK(hipMemcpyAsync(guard.saved, ctx->d_state, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
     float best_ms = 1e30f;
-    int best = batched ? ctx->batched_bs : ctx->plain_bs;
-    const int keep_plain = ctx->plain_bs;
-    for (int bs : cand) {
-        if (!batched && bs > ctx->N && bs != cand[0]) continue;   // no idle waves beyond the servers
+    Shape best = batched ? ctx->bshape : Shape{ctx->plain_bs, host_group(ctx->plain_bs), ctx->pc_plain};
+    for (const Shape &sh : cand) {
         for (int rep = 0; rep < 2; ++rep) {   // first run warms up
-            HIPCHK(hipMemcpyAsync(ctx->d_state, saved, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
+            HIPCHK(hipMemcpyAsync(ctx->d_state, guard.saved, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
             for (int bi : ctx->queued) if ((rc = reset_outputs(ctx, *ctx->batches[bi]))) return rc;
             HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
-            ctx->plain_bs = bs;
+            ctx->plain_bs = sh.bs;
             for (int bi : ctx->queued) {
                 if (batched) {
-                    launch_batched(ctx, *ctx->batches[bi], bs, ctx->stream);   // timed eagerly
+                    launch_batched(ctx, *ctx->batches[bi], sh, ctx->stream);   // timed eagerly
                     HIPCHK(hipGetLastError());
                 } else if ((rc = run_plain(ctx, *ctx->batches[bi]))) {
                     return rc;
@@ -1419,16 +1579,33 @@ int dc_autotune(dc_ctx *ctx, int32_t *block) {
             HIPCHK(hipEventSynchronize(ctx->ev1));
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-            if (rep == 1 && ms < best_ms) { best_ms = ms; best = bs; }
+            if (rep == 1 && ms < best_ms) { best_ms = ms; best = sh; }
         }
     }
-    HIPCHK(hipMemcpyAsync(ctx->d_state, saved, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->d_state, guard.saved, sbytes, hipMemcpyDeviceToDevice, ctx->stream));
     for (int bi : ctx->queued) if ((rc = reset_outputs(ctx, *ctx->batches[bi]))) return rc;
     HIPCHK(hipStreamSynchronize(ctx->stream));
-    HIPCHK(hipFree(saved));
-    ctx->plain_bs = keep_plain;
-    if (batched) ctx->batched_bs = best; else ctx->plain_bs = best;
-    if (block) *block = best;
+    if (batched) ctx->bshape = best; else guard.plain_bs = best.bs;
+    if (cache_path && *cache_path) cache_write(cache_path, key, best, best_ms);
+    if (out) *out = dc_tune{best.bs, best.g, best.pc, 0, best_ms, (int32_t)cand.size()};
+    return DC_OK;
+}
+
+int dc_set_shape(dc_ctx *ctx, const dc_tune *shape) {
+    if (!ctx || !shape) return DC_EINVAL;
+    if (ctx->poisoned) return DC_EDEVICE;
+    if (ctx->cfg.mode != DC_MODE_BATCHED) return DC_ESTATE;
+    const Shape sh{shape->block, shape->host_group, shape->peer_chunk};
+    if (!shape_ok(ctx, sh)) return DC_EINVAL;
+    ctx->bshape = sh;
+    return DC_OK;
+}
+
+int dc_get_shape(dc_ctx *ctx, dc_tune *shape) {
+    if (!ctx || !shape) return DC_EINVAL;
+    const Shape sh = ctx->cfg.mode == DC_MODE_BATCHED ? ctx->bshape
+                                                       : Shape{ctx->plain_bs, host_group(ctx->plain_bs), ctx->pc_plain};
+    *shape = dc_tune{sh.bs, sh.g, sh.pc, 0, 0.f, 0};
     return DC_OK;
 }
 

@@ -129,22 +129,19 @@ def _random_connected_edges(n: int, density: float, rng: np.random.Generator,
     if n < 2:
         return np.zeros((0, 3), dtype=np.int32)
     target = max(n - 1, int(math.ceil(density * n * (n - 1) / 2)))
-    pairs = []
-    present = set()
-    for t in range(1, n):
-        parent = int(rng.integers(0, t))
-        pairs.append((parent, t))
-        present.add((parent, t))
-    if target > len(pairs):
-        rest = [(i, j) for i in range(n) for j in range(i + 1, n) if (i, j) not in present]
-        pick = rng.choice(len(rest), size=target - len(pairs), replace=False)
-        for p in sorted(int(x) for x in pick):
-            pairs.append(rest[p])
-    bw = rng.integers(bw_lo, bw_hi + 1, size=len(pairs))
-    out = np.empty((len(pairs), 3), dtype=np.int32)
-    for e, (i, j) in enumerate(pairs):
-        out[e] = (i, j, bw[e])
-    return out
+    parent = rng.integers(0, np.arange(1, n)).astype(np.int64)   # node t joins a uniform earlier node
+    pi, pj = parent, np.arange(1, n, dtype=np.int64)
+    if target > n - 1:
+        # the pairs (i < j) not in the tree, in row-major order
+        iu, ju = np.triu_indices(n, 1)
+        in_tree = np.zeros((n, n), dtype=bool)
+        in_tree[pi, pj] = True
+        keep = ~in_tree[iu, ju]
+        ri, rj = iu[keep], ju[keep]
+        pick = np.sort(rng.choice(ri.shape[0], size=target - (n - 1), replace=False))
+        pi, pj = np.concatenate([pi, ri[pick]]), np.concatenate([pj, rj[pick]])
+    bw = rng.integers(bw_lo, bw_hi + 1, size=pi.shape[0])
+    return np.stack([pi, pj, bw], axis=1).astype(np.int32)
 
 
 def _random_pods(n: int, frac: float, rng: np.random.Generator) -> np.ndarray:
