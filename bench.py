@@ -7,12 +7,17 @@ and every request is scheduled in FCFS order -- per container: path stage,
 criteria, scoring, selection, commit -- with the results copied back.  The
 requests are uploaded to HBM before the timed region.
 
-Default workload (one JSON line): k=16 fat-tree (1024 hosts), 40 Gbps host
-links, 100 Gbps edge-aggregation / aggregation-core links, 0-70 %
-background load, 2,000 FCFS requests of 2-32 containers, TOPSIS over (CPU,
-RAM, active, path bandwidth), plain form: one kernel launch per container
-step.  Other workloads (--workload) measure the batched form (256
-instances), the large AHP case and the serving form on a Poisson trace.
+Default workload (one JSON line): 256 independent k=16 fat-trees (1,024
+hosts each, 40 Gbps host links, 100 Gbps edge-aggregation /
+aggregation-core links, 0-70 % background load), each with 64-512 FCFS
+requests of 2-48 containers, TOPSIS over (CPU, RAM, active, path
+bandwidth), batched form: one persistent launch per step, replayed from a
+HIP graph, with the autotuned launch shape.  The line also carries the
+plain form on one k=16 data center (one launch per container step), the
+serving form against the plain form on a k=48 Poisson trace, and the
+scoring stage alone over resident matrices.  Other workloads (--workload)
+measure the plain form, the large AHP case, the serving form and the
+paper's event-replay shape on their own.
 """
 import argparse
 import json
@@ -29,11 +34,13 @@ HBM_PEAK_GBS = 8000.0
 # state arrays (CPU, RAM, placed count, uplink, edge-aggregation and
 # aggregation-core residuals) read once per scored host.
 BYTES_PER_HOST_SCORE = 24
-# FP32 vector peak of MI355X, 157.3 TFLOP/s (256 CUs x 2.4 GHz x 128 FMA
-# lanes per clock), as VALU lane-instructions per second: one lane-FMA per
-# issue slot.  The Saaty passes are mostly compares and selects, which do not
-# pack, so this peak is generous to them.
-VALU_LANE_OPS = 157.3e12 / 2
+# VALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13
+# lane-instructions per second without packing.  The AHP passes are compares,
+# selects and integer adds, which do not pack; the published FP32 peak, 157.3
+# TFLOP/s, counts two lanes per packed instruction and two FLOPs per FMA, so
+# it is four times this rate in FLOPs (twice it in lane-instructions).
+VALU_LANE_OPS = 256 * 64 * 2.4e9
+VALU_LANE_OPS_PACKED = 157.3e12 / 2
 
 WORKLOADS = {
     "plain": dict(preset="plain", mode="plain", method="topsis",
@@ -81,19 +88,8 @@ def step_count(results):
 
 
 def _pod_steps(req, status, failed_at):
-    """Steps a request took: one per pod (a container without a pod is a pod
-    of its own), in the order of each pod's first container."""
-    pod = getattr(req, "pod", None)
-    if status == 0 and failed_at >= req.n:      # every pod placed, links did not fit
-        status = 1
-    if pod is None:
-        return req.n if status == 1 else failed_at + 1
-    seen, unit = {}, []
-    for i, p in enumerate(pod):
-        key = ("p", int(p)) if p >= 0 else ("c", i)
-        seen.setdefault(key, len(seen))
-        unit.append(seen[key])
-    return len(seen) if status == 1 else unit[failed_at] + 1
+    from paper_1909_07673_amd.events import unit_steps
+    return unit_steps(req, status, failed_at)
 
 
 def step_count_array(res, reqs=None):
@@ -119,17 +115,17 @@ def host_cpu():
     return f"{model}, {len(os.sched_getaffinity(0))} logical CPUs available"
 
 
-def cpu_baseline(insts, reqs, budget_s, meth):
-    """The FP64 oracle, as it stands, on a bounded prefix of the same
-    workload (single thread): the requests of instance 0 in FCFS order, then
-    those of the next instances, until the time budget is spent."""
+def _oracle_prefix(insts, reqs, meth, budget_s, which):
+    """Runs the FP64 oracle, as it stands, over instances `which` in order
+    (each instance's requests in FCFS order) until budget_s seconds have
+    passed.  Returns (scoring steps, requests, instances touched)."""
     import oracle
     steps = n_req = n_inst = 0
     t0 = time.perf_counter()
-    for inst, rl in zip(insts, reqs):
-        o = oracle.Oracle(inst, meth)
+    for i in which:
+        o = oracle.Oracle(insts[i], meth)
         n_inst += 1
-        for req in rl:
+        for req in reqs[i]:
             res = o.run_request(req)
             steps += _pod_steps(req, res["status"], res["failed_at"])
             n_req += 1
@@ -138,12 +134,52 @@ def cpu_baseline(insts, reqs, budget_s, meth):
         o.close()
         if time.perf_counter() - t0 > budget_s:
             break
-    dt = time.perf_counter() - t0
+    return steps, n_req, n_inst
+
+
+_POOL_ARGS = None
+
+
+def _pool_worker(w):
+    insts, reqs, meth, budget_s, nw = _POOL_ARGS
+    return _oracle_prefix(insts, reqs, meth, budget_s, range(w, len(insts), nw))
+
+
+def cpu_baseline(insts, reqs, budget_s, meth, all_cores=False):
+    """The FP64 oracle timed on this host: one thread on a prefix of the
+    workload (instance 0 first), and with all_cores, one process per
+    logical CPU this process may use, worker w taking instances w, w + W, ...
+    (independent data centers, the fair CPU counterpart of the batched
+    form).  Must run before this process touches the GPU: the workers are
+    forked."""
+    import oracle
+    oracle.set_threads(1)
     N = insts[0].n_hosts
-    where = "the same workload" if n_inst == 1 else f"the first {n_inst} instances of the same workload"
-    return dict(value=steps * N / dt, unit="host-scores/s", cores=1, kind="oracle",
-                sample=f"first {n_req} requests ({steps} scoring steps) of {where} on one host "
-                       f"thread, {dt:.1f} s", host=host_cpu())
+    t0 = time.perf_counter()
+    steps, n_req, n_inst = _oracle_prefix(insts, reqs, meth, budget_s, range(len(insts)))
+    dt = time.perf_counter() - t0
+    where = "the same workload" if n_inst == 1 else f"the first {n_inst} instance(s) of the same workload"
+    one = dict(value=steps * N / dt, unit="host-scores/s", cores=1, kind="oracle",
+               sample=f"first {n_req} requests ({steps} scoring steps) of {where} on one host thread, {dt:.1f} s",
+               host=host_cpu())
+    if not all_cores or len(insts) < 2:
+        return one
+    import multiprocessing as mp
+    global _POOL_ARGS
+    nw = min(len(os.sched_getaffinity(0)), len(insts))
+    _POOL_ARGS = (insts, reqs, meth, budget_s, nw)
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(nw) as pool:
+        parts = pool.map(_pool_worker, range(nw))
+    dt = time.perf_counter() - t0
+    _POOL_ARGS = None
+    steps = sum(p[0] for p in parts)
+    out = dict(value=steps * N / dt, unit="host-scores/s", cores=nw, kind="oracle",
+               sample=f"{nw} processes, one per logical CPU, each running the oracle over its share of the "
+                      f"{len(insts)} instances (instance w, w + {nw}, ...) in FCFS order for {budget_s:.0f} s: "
+                      f"{sum(p[1] for p in parts)} requests, {steps} scoring steps in {dt:.1f} s",
+               host=host_cpu(), one_thread=one)
+    return out
 
 
 def percentiles(x):
@@ -152,17 +188,14 @@ def percentiles(x):
     return {"p50": float(np.percentile(x, 50)), "p99": float(np.percentile(x, 99))} if x.size else None
 
 
-def run_batch(args, wl):
+def run_batch(args, wl, insts, reqs):
     """Plain / batched / AHP: rewind + schedule all requests per step."""
     import numpy as np
     import torch
-    import oracle
     import paper_1909_07673_amd as dc
-    from workloads import make_config
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    insts, reqs = make_config(wl["preset"], seed=0)
     N = insts[0].n_hosts
     kw = {}
     if wl["method"] == "ahp":
@@ -175,16 +208,14 @@ def run_batch(args, wl):
         for r in rl:
             s.submit(r, instance=i)
     s.rewind()                      # uploads the requests; they stay resident in HBM
-    # the batched form autotunes its workgroup size; the plain form keeps the
-    # library's size for its server count (1,024 threads from 257 servers on,
-    # which the autotuner also picks there), so a profiled run times the same
-    # kernel as an unprofiled one
-    if args.block:
-        tuned = args.block
-    elif mode == dc.DC_MODE_BATCHED and wl["method"] == "topsis":
-        tuned = s.autotune()
-    else:
-        tuned = 64 if N <= 64 else 256 if N <= 256 else 1024
+    # the batched form takes its launch shape from the autotuner (through its
+    # cache, so a profiled run times the same kernel as an unprofiled one);
+    # the plain form keeps the library's workgroup size for its server count
+    # (1,024 threads from 257 servers on, which the autotuner also picks)
+    tune = None
+    if mode == dc.DC_MODE_BATCHED and not args.block:
+        tune = s.autotune_cached(args.tune_cache or None)
+    shape = s.shape()
     torch.cuda.synchronize()
     buf = np.zeros(s.pending(), dc.RESULT_DTYPE)
     for _ in range(args.warmup):
@@ -219,25 +250,24 @@ def run_batch(args, wl):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": wl["text"], "k": insts[0].k, "hosts": N, "instances": len(insts),
                    "requests": sum(len(r) for r in reqs), "container_steps": steps,
-                   "form": wl["mode"], "method": wl["method"], "block": tuned, "grid": args.grid,
+                   "form": wl["mode"], "method": wl["method"], "shape": shape, "grid": args.grid,
                    "graph": args.graph,
                    "steps_per_instance": {"mean": float(per_inst.mean()), "max": int(per_inst.max())}},
         "latency_us": dict(percentiles(lat), kind="service (first step start to decision), device clock"),
     }
+    if tune is not None:
+        out["config"]["autotune"] = tune
     if wl["method"] == "topsis":
         kname = ("k_topsis_batched" if mode == dc.DC_MODE_BATCHED else
                  "k_topsis_grid" if args.grid == 2 else "k_topsis_plain")
         bytes_per_launch = BYTES_PER_HOST_SCORE * hs / per_step_launches
         achieved = bytes_per_launch / avg_launch_s / 1e9
+        traffic = counter_traffic(BATCHED_TRAFFIC, shape) if kname == "k_topsis_batched" else None
         out["roofline"] = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                            "avg_launch_us": avg_launch_s * 1e6, "launches_per_step": per_step_launches,
-                           "bytes_per_launch": bytes_per_launch}
-        meth = oracle.method(kind=oracle.TOPSIS, route_end=bool(wl.get("routing", 0)))
-        if not args.no_scoring_kernel:
-            # the scoring stage alone, streaming resident matrices (HBM-bound)
-            out["scoring_kernel_roofline"] = dict(
-                tile_timing(20, 2)[3], workload=WORKLOADS["tiles"]["text"])
+                           "bytes_per_launch": bytes_per_launch,
+                           "bytes_basis": "24 B per host-score: the six int32 state words of each scored server"}
     else:
         C = 5
         if N <= AHP_SORT_MAX:
@@ -252,15 +282,20 @@ def run_batch(args, wl):
         rate = pairs * args.steps / (kern_ms / 1e3)
         out["roofline"] = {"bound": "alu", "kernel": kname, "unit": unit, "achieved": rate,
                            "peak": VALU_LANE_OPS / ops, "frac": rate / (VALU_LANE_OPS / ops),
+                           "frac_of_packed_fp32_peak": rate / (VALU_LANE_OPS_PACKED / ops),
                            "traffic": None, "pair_ops": ops, "basis": "whole AHP step kernel time",
+                           "peak_basis": "256 CUs x 64 lanes x 2.4 GHz VALU lane-instructions/s (no packing)",
                            "avg_launch_us": avg_launch_s * 1e6, "launches_per_step": per_step_launches}
-        meth = oracle.method(kind=oracle.AHP, crit=(oracle.CRIT_CPU, oracle.CRIT_RAM, oracle.CRIT_UPLINK,
-                                                   oracle.CRIT_PATHBW, oracle.CRIT_HOPS), cost=[0, 0, 0, 0, 1])
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(insts, reqs, args.cpu_budget, meth)
-        out["cpu_baseline"]["vs_gpu"] = value / out["cpu_baseline"]["value"]
     s.close()
     return out
+
+
+def oracle_method(wl):
+    import oracle
+    if wl["method"] == "ahp":
+        return oracle.method(kind=oracle.AHP, crit=(oracle.CRIT_CPU, oracle.CRIT_RAM, oracle.CRIT_UPLINK,
+                                                   oracle.CRIT_PATHBW, oracle.CRIT_HOPS), cost=[0, 0, 0, 0, 1])
+    return oracle.method(kind=oracle.TOPSIS, route_end=bool(wl.get("routing", 0)))
 
 
 # VALU instructions per Saaty pair evaluation in the pairwise AHP passes,
@@ -274,34 +309,59 @@ AHP_SORT_MAX = 8192
 
 TILE_T, TILE_C, TILE_N = 32768, 4, 1024
 
-# HBM traffic of the scoring kernel per launch at the shape above, from two
-# rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of
-# `bench.py --workload tiles --copy-ref`, each scaled by what the same
-# counter reads for the run's plain 512 MiB device copy.  Valid only for the
-# kernel sources the counters were taken on (their SHA-256 below); reported
-# as null once those sources change.
+# HBM traffic per launch from two rocprofv3 --pmc passes (FETCH_SIZE, then
+# WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads
+# for the run's plain device copy of copy_kib KiB (which reads and writes
+# copy_kib).  Valid only for the kernel sources the counters were taken on
+# (their SHA-256) and, for the batched kernel, the launch shape; reported as
+# null otherwise.
 TILE_TRAFFIC = {
     "sources": ("paper_1909_07673_amd/csrc/dc_tiles.hpp", "paper_1909_07673_amd/csrc/dc_step.hpp"),
     "sha256": "fe44d0a139b0563055380f40dd70c609f189bdd011f6626bfd62dd65cebe8c27",
-    "fetch_kib": 262216.77, "fetch_copy_kib": 262161.44,     # copy reads 524288 KiB
-    "write_kib": 517.37, "write_copy_kib": 524288.0,         # copy writes 524288 KiB
+    "copy_kib": 524288.0,
+    "fetch_kib": 262216.77, "fetch_copy_kib": 262161.44,
+    "write_kib": 517.37, "write_copy_kib": 524288.0,
 }
+# the batched kernel at the default workload (taken with
+# `bench.py --workload batched --steps 1 --warmup 0 --copy-ref`); None until measured
+BATCHED_TRAFFIC = None
+
+
+def _sources_sha(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counter_traffic(t, shape=None):
+    """Scaled HBM bytes per launch from the counters in t, or None when the
+    sources (or the launch shape) differ from those they were taken on."""
+    if t is None or _sources_sha(t["sources"]) != t["sha256"]:
+        return None
+    if shape is not None and t.get("shape") not in (None, shape):
+        return None
+    fetch = t["fetch_kib"] * (t["copy_kib"] / t["fetch_copy_kib"])
+    write = t["write_kib"] * (t["copy_kib"] / t["write_copy_kib"])
+    return (fetch + write) * 1024.0
 
 
 def tile_traffic():
-    """Scaled HBM bytes per launch of the scoring kernel, or None when its
-    sources differ from those the counters were taken on."""
-    import hashlib
-    h = hashlib.sha256()
-    for f in TILE_TRAFFIC["sources"]:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    if h.hexdigest() != TILE_TRAFFIC["sha256"]:
-        return None
-    t = TILE_TRAFFIC
-    fetch = t["fetch_kib"] * (524288.0 / t["fetch_copy_kib"])
-    write = t["write_kib"] * (524288.0 / t["write_copy_kib"])
-    return (fetch + write) * 1024.0
+    return counter_traffic(TILE_TRAFFIC)
+
+
+def copy_reference(nbytes=512 << 20):
+    """One plain device-to-device copy of nbytes (a reference of known size
+    for scaling HBM byte counters)."""
+    import torch
+    x = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda").fill_(1)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    del x, y
 
 
 def tile_timing(steps, warmup, copy_ref=False):
@@ -321,11 +381,7 @@ def tile_timing(steps, warmup, copy_ref=False):
         dc.topsis_tiles(x, w, stream=stream)
     torch.cuda.synchronize()
     if copy_ref:
-        # a plain device copy of the same bytes, for scaling HBM counters
-        y = torch.empty_like(x)
-        y.copy_(x)
-        torch.cuda.synchronize()
-        del y
+        copy_reference(x.numel() * 4)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record(stream)
@@ -386,17 +442,18 @@ PAPER_TABLE5 = {"topsis": {"runtime_s": 3.67, "events": 894, "U_ij": 1.0, "U_i":
 
 
 def run_events(args, wl):
-    """Discrete-event replay: at every event the departures due release
-    their resources, the arrivals join the waiting queue, and every waiting
-    request is submitted in FCFS order; the ones that do not fit wait for
-    the next event.  Reports the events needed to place every request, the
-    provisioning delay, the server / link fragmentation (share of active
-    servers and of links carrying traffic) averaged over the events, and the
-    mean utilities U(i), U(ij) (Eqs. (1)-(2)) of what the requests were
-    given, read after the timed replay."""
+    """Discrete-event replay (paper_1909_07673_amd.events): at every event
+    the departures due release their resources, the arrivals join the
+    waiting queue, and every waiting request is submitted in FCFS order;
+    the ones that do not fit wait for the next event.  Reports the events
+    needed to place every request, the provisioning delay, the server / link
+    fragmentation F(N^s), F(E^s) averaged over the events, and the mean
+    utilities U(i), U(ij) (section II-B, Eqs. (1)-(2)) of what the requests
+    were given, read after the timed replay."""
     import numpy as np
     import torch
     import paper_1909_07673_amd as dc
+    from paper_1909_07673_amd import events
     from workloads import make_event_workload
 
     torch.cuda.set_device(0)
@@ -404,61 +461,30 @@ def run_events(args, wl):
     N = inst.n_hosts
     kw = dict(method=dc.DC_AHP) if wl["method"] == "ahp" else {}
     s = dc.Scheduler([inst], **kw)
-    cap_links = np.array([inst.bw_host_edge, inst.bw_edge_agg, inst.bw_agg_core], np.int64)[:, None]
-    buf = np.zeros(len(reqs), dc.RESULT_DTYPE)
-    placed = np.full(len(reqs), -1)
-    acc_id = np.full(len(reqs), -1, np.int64)
-    queue, ends = [], {}
-    nxt = ev = steps = tries = 0
-    frag_s, frag_l = [], []
+    caps = (inst.bw_host_edge, inst.bw_edge_agg, inst.bw_agg_core)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    while nxt < len(reqs) or queue:
-        for rid in ends.pop(ev, []):
-            s.release(rid)
-        while nxt < len(reqs) and arrive[nxt] <= ev:
-            queue.append(nxt)
-            nxt += 1
-        if queue:
-            ids = [s.submit(reqs[q]) for q in queue]
-            res = s.schedule_array(buf[:len(queue)])
-            tries += len(queue)
-            still = []
-            for q, rid, r in zip(queue, ids, res):
-                steps += _pod_steps(reqs[q], int(r["status"]), int(r["failed_at"]))
-                if r["status"] == 1:
-                    placed[q] = ev
-                    acc_id[q] = rid
-                    ends.setdefault(ev + int(dur[q]), []).append(rid)
-                else:
-                    still.append(q)
-            queue = still
-        st = s.state(0).astype(np.int64)
-        frag_s.append(float((st[2] > 0).mean()))
-        frag_l.append(float((st[3:] < cap_links).mean()))
-        ev += 1
+    rep = events.replay(s, reqs, arrive, dur, caps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    delay = placed - arrive
     u_i, u_ij = [], []
     for q, req in enumerate(reqs):
-        ca, ra, ba = s.alloc(int(acc_id[q]), req.n, req.m)
-        cx = req.cpu if req.cpu_max is None else req.cpu_max
-        rx = req.ram if req.ram_max is None else req.ram_max
-        bx = req.edges[:, 2] if req.bw_max is None else req.bw_max
-        u_i.extend(((ca / cx + ra / rx) / 2).tolist())
-        u_ij.extend((ba / bx).tolist())
+        ui, uij = events.utilities(req, *s.alloc(int(rep["rid"][q]), req.n, req.m))
+        u_i.extend(ui.tolist())
+        u_ij.extend(uij.tolist())
     s.close()
+    delay = rep["delay"]
     out = {
-        "metric": METRIC, "value": steps * N / wall, "unit": "host-scores/s", "n_gpus": 1, "steps": 1,
+        "metric": METRIC, "value": rep["steps"] * N / wall, "unit": "host-scores/s", "n_gpus": 1, "steps": 1,
         "warmup": 0, "ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": wl["text"], "k": inst.k, "hosts": N, "requests": len(reqs), "form": "plain",
                    "method": wl["method"]},
-        "events": int(placed.max()) + 1, "runtime_s": wall, "scoring_steps": steps, "submissions": tries,
+        "events": rep["events"], "runtime_s": wall, "scoring_steps": rep["steps"],
+        "submissions": rep["submissions"],
         "delay_events": {"mean": float(delay.mean()), "p99": float(np.percentile(delay, 99)),
                          "max": int(delay.max())},
-        "fragmentation": {"servers": float(np.mean(frag_s)), "links": float(np.mean(frag_l))},
+        "fragmentation": {"servers": float(np.mean(rep["frag_s"])), "links": float(np.mean(rep["frag_l"]))},
         "utility": {"U_i": float(np.mean(u_i)), "U_ij": float(np.mean(u_ij)),
                     "note": "mean over containers / container pairs of allocated over maximum"},
         "paper_table5": dict(PAPER_TABLE5[wl["method"]], hardware="unnamed GPU, CUDA 10.1; runtime includes "
@@ -519,7 +545,7 @@ def replay(s, dc, reqs, arr, dep, serving, horizon_s):
     return done, sojourn, wall
 
 
-def run_serving(args, wl):
+def run_serving(args, wl, variants_all=True):
     import numpy as np
     import torch
     import paper_1909_07673_amd as dc
@@ -535,6 +561,8 @@ def run_serving(args, wl):
     # the other two variants for comparison
     variants = (("serving", dc.DC_MODE_SERVING, 0), ("plain", dc.DC_MODE_PLAIN, 0),
                 ("serving_1wg", dc.DC_MODE_SERVING, 1), ("plain_grid", dc.DC_MODE_PLAIN, 2))
+    if not variants_all:
+        variants = variants[:2]
     for name, mode, grid in variants:
         s = dc.Scheduler(insts, mode=mode, grid=grid)
         done, soj, wall = replay(s, dc, reqs, arr, dep, mode == dc.DC_MODE_SERVING, args.trace_s)
@@ -561,23 +589,33 @@ def run_serving(args, wl):
     }
 
 
+def summary(out):
+    """The keys of a workload's line that go into another line as an extra."""
+    keep = ("value", "unit", "ms_per_step", "steps", "warmup", "config", "latency_us", "roofline")
+    return {k: out[k] for k in keep if k in out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="plain", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
+    ap.add_argument("--workload", default="batched", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle work per cpu_baseline leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="batched: only the batched form (no plain, serving or scoring-stage extras)")
     ap.add_argument("--trace-s", type=float, default=2.0, help="serving: seconds of Poisson arrivals")
     ap.add_argument("--grid", type=int, default=0, choices=(0, 1, 2),
                     help="TOPSIS step: 0 automatic, 1 one workgroup, 2 one cooperative workgroup per pod")
     ap.add_argument("--block", type=int, default=0, choices=(0, 256, 512, 1024),
-                    help="plain/batched TOPSIS: workgroup size (0 = autotuned)")
+                    help="plain/batched TOPSIS: workgroup size (0 = library default / autotuned)")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1909_07673_amd", "tune_cache.jsonl"),
+                    help="batched: autotuner cache file ('' = tune every run)")
     ap.add_argument("--no-scoring-kernel", action="store_true",
                     help="plain/batched: skip the separate roofline of the scoring stage alone")
     ap.add_argument("--copy-ref", action="store_true",
-                    help="tiles: also run one plain copy of the matrices (reference for HBM byte counters)")
+                    help="tiles, batched: also run one plain device copy (reference for HBM byte counters)")
     ap.add_argument("--graph", type=int, default=0, choices=(0, 1, 2),
                     help="batched form: 0 automatic (graph), 1 direct launch, 2 HIP graph")
     args = ap.parse_args()
@@ -593,7 +631,36 @@ def main():
     elif wl["mode"] == "events":
         out = run_events(args, wl)
     else:
-        out = run_batch(args, wl)
+        from workloads import make_config
+        insts, reqs = make_config(wl["preset"], seed=0)
+        cpu = None
+        if not args.no_cpu_baseline:
+            # before the GPU is touched: the all-cores leg forks its workers
+            cpu = cpu_baseline(insts, reqs, args.cpu_budget, oracle_method(wl), all_cores=wl["mode"] == "batched")
+        out = run_batch(args, wl, insts, reqs)
+        if cpu is not None:
+            cpu["vs_gpu"] = out["value"] / cpu["value"]
+            if "one_thread" in cpu:
+                cpu["one_thread"]["vs_gpu"] = out["value"] / cpu["one_thread"]["value"]
+            out["cpu_baseline"] = cpu
+        if args.copy_ref:
+            copy_reference()
+        if args.workload == "batched" and not args.no_extras:
+            # the plain per-container-launch path on one k=16 data center
+            # (2,000 requests), the serving form against the plain form on
+            # the k=48 Poisson trace, and the scoring stage alone
+            pa = argparse.Namespace(**vars(args))
+            pa.steps, pa.warmup, pa.block = 3, 1, 0
+            pi, pr = make_config("plain", seed=0)
+            plain = summary(run_batch(pa, WORKLOADS["plain"], pi, pr))
+            out["plain_form"] = plain
+            out["batched_vs_plain"] = {
+                "host_scores_per_s": out["value"] / plain["value"],
+                "p99_service_us": {"batched": out["latency_us"]["p99"], "plain": plain["latency_us"]["p99"]}}
+            sv = run_serving(args, WORKLOADS["serving"], variants_all=False)
+            out["serving_vs_plain_k48"] = {"config": sv["config"], "forms": sv["forms"]}
+            if not args.no_scoring_kernel:
+                out["scoring_kernel_roofline"] = dict(tile_timing(20, 2)[3], workload=WORKLOADS["tiles"]["text"])
     print(json.dumps(out), flush=True)
 
 

@@ -324,8 +324,14 @@ int dc_last_timing(dc_ctx *ctx, float *ms, int64_t *launches, int64_t *steps);
  * step's for the same criteria.  Asynchronous on the stream; the caller
  * keeps the buffers alive until it completes.  DC_EINVAL for T < 0 or
  * T >= 2^31, C outside 1..DC_MAX_CRIT, N outside 1..2^20, a null x, best or
- * weight, or a weight that is not positive; DC_EDEVICE when the launch
- * fails.  16-byte aligned x and scores and N % 4 == 0 take the fast path. */
+ * weight, or a weight that is not positive; DC_ENOMEM when the large-tile
+ * path's partials cannot be allocated; DC_EDEVICE when the launch fails.
+ * 16-byte aligned x and scores and N % 4 == 0 with a tile a wavefront's
+ * registers hold take the fast path (one wavefront per tile); up to 1,024
+ * tiles of at least 4,096 servers are split into slices of 2,048 servers
+ * over several workgroups, with partials in device memory allocated on the
+ * stream for the call (stream-ordered) and freed behind it; other shapes
+ * take one workgroup per tile. */
 int dc_topsis_tiles(int64_t T, int32_t C, int32_t N, const int32_t *x, const uint8_t *feasible,
                     const int32_t *cost, const float *weight, float *scores, int32_t *best, float *best_score,
                     void *stream);

@@ -4,8 +4,10 @@ HIP kernels; there is no CPU fallback, and loading fails loudly when the
 library has not been built."""
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 from typing import Iterable, List, Optional
 
 import numpy as np
@@ -142,6 +144,18 @@ class Result:
         self.scores = np.frombuffer(r.score, dtype=np.float32, count=r.n).copy()
 
 
+# Contexts still open when the interpreter exits are destroyed by an exit
+# hook, while the HIP runtime is whole, rather than by garbage collection
+# during the interpreter's own teardown.
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live():
+    for s in list(_live):
+        s.close()
+
+
 class Scheduler:
     """One libdcsched context (dc_create ... dc_destroy)."""
 
@@ -183,11 +197,13 @@ class Scheduler:
         self.cfg = cfg
         self._ctx = C.c_void_p()
         _check(lib().dc_create(C.byref(cfg), C.byref(self._ctx)), "dc_create")
+        _live.add(self)
 
     def close(self):
         if self._ctx:
             lib().dc_destroy(self._ctx)
             self._ctx = C.c_void_p()
+        _live.discard(self)
 
     def __enter__(self):
         return self

@@ -1055,6 +1055,108 @@ void cache_write(const char *path, const std::string &key, const Shape &sh, floa
 
 }  // namespace
 
+namespace {
+
+// Which kernels score a set of tiles: one wavefront per tile (matrices a
+// wavefront's registers hold), slices of one tile over several workgroups
+// with partials in scratch (few large tiles), or one workgroup per tile.
+enum { TILE_WAVE = 0, TILE_SPLIT = 1, TILE_GEN = 2 };
+struct TilePath {
+    int kind = TILE_GEN, C = 0, V = 0;
+};
+
+int tiles_prepare(int64_t T, int32_t C, int32_t N, const int32_t *x, const uint8_t *feasible, const int32_t *cost,
+                  const float *weight, float *scores, int32_t *best, float *best_score, TileArgs *a, TilePath *path) {
+    if (T < 0 || T > 0x7fffffffLL || C < 1 || C > DC_MAX_CRIT || N < 1 || N > (1 << 20)) return DC_EINVAL;
+    if (T == 0) return DC_OK;
+    if (!x || !best || !weight) return DC_EINVAL;
+    *a = TileArgs{};
+    a->x = x;
+    a->feas = feasible;
+    a->scores = scores;
+    a->best = best;
+    a->best_score = best_score;
+    a->C = C;
+    a->N = N;
+    for (int c = 0; c < C; ++c) {
+        if (!(weight[c] > 0.f) || !std::isfinite(weight[c])) return DC_EINVAL;
+        a->w[c] = weight[c];
+        a->cost[c] = cost ? (cost[c] != 0) : 0;
+    }
+    auto al = [](const void *p, uintptr_t m) { return (reinterpret_cast<uintptr_t>(p) & (m - 1)) == 0; };
+    const bool vec = N % 4 == 0 && al(x, 16) && (!scores || al(scores, 16)) && (!feasible || al(feasible, 4));
+    // four-server groups per lane when one wavefront holds the tile
+    const int V = (N + 4 * kWave - 1) / (4 * kWave);
+    const int Vp = V <= 1 ? 1 : V <= 2 ? 2 : V <= 4 ? 4 : V <= 8 ? 8 : 16;   // 16: too large
+    path->C = C;
+    path->V = Vp;
+    if (vec && Vp <= 8 && C * Vp <= 16) path->kind = TILE_WAVE;
+    else if (N >= 2 * kSplitSlice && T <= kSplitMaxTiles) path->kind = TILE_SPLIT;
+    else path->kind = TILE_GEN;
+    return DC_OK;
+}
+
+// scratch: split_scratch_bytes(T, N, C) device bytes for the split path
+// (unused otherwise).
+int tiles_launch(const TileArgs &a, int64_t T, const TilePath &path, void *scratch, hipStream_t st) {
+    if (path.kind == TILE_WAVE) {
+        // persistent grid: as many workgroups as fit on the device at once,
+        // never more than needed for one wavefront per tile
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return DC_EDEVICE;
+        const dim3 block(kTileBlock);
+        auto pgrid = [&](const void *k) {
+            int per = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, kTileBlock, 0) != hipSuccess || per < 1) per = 1;
+            const long long need = (T + kTileWaves - 1) / kTileWaves;
+            return dim3(static_cast<unsigned>(std::min<long long>(need, (long long)per * cus)));
+        };
+#define DCS_TILES_LAUNCH(CC, VV)                                                                         \
+    hipLaunchKernelGGL((k_topsis_tiles_wave<CC, VV>),                                                    \
+                       pgrid(reinterpret_cast<const void *>(k_topsis_tiles_wave<CC, VV>)), block, 0, st, a, (long long)T)
+        switch (path.C * 100 + path.V) {
+        case 101: DCS_TILES_LAUNCH(1, 1); break;
+        case 102: DCS_TILES_LAUNCH(1, 2); break;
+        case 104: DCS_TILES_LAUNCH(1, 4); break;
+        case 108: DCS_TILES_LAUNCH(1, 8); break;
+        case 201: DCS_TILES_LAUNCH(2, 1); break;
+        case 202: DCS_TILES_LAUNCH(2, 2); break;
+        case 204: DCS_TILES_LAUNCH(2, 4); break;
+        case 208: DCS_TILES_LAUNCH(2, 8); break;
+        case 301: DCS_TILES_LAUNCH(3, 1); break;
+        case 302: DCS_TILES_LAUNCH(3, 2); break;
+        case 304: DCS_TILES_LAUNCH(3, 4); break;
+        case 401: DCS_TILES_LAUNCH(4, 1); break;
+        case 402: DCS_TILES_LAUNCH(4, 2); break;
+        case 404: DCS_TILES_LAUNCH(4, 4); break;
+        case 501: DCS_TILES_LAUNCH(5, 1); break;
+        case 502: DCS_TILES_LAUNCH(5, 2); break;
+        case 601: DCS_TILES_LAUNCH(6, 1); break;
+        case 602: DCS_TILES_LAUNCH(6, 2); break;
+        case 701: DCS_TILES_LAUNCH(7, 1); break;
+        case 702: DCS_TILES_LAUNCH(7, 2); break;
+        case 801: DCS_TILES_LAUNCH(8, 1); break;
+        case 802: DCS_TILES_LAUNCH(8, 2); break;
+        default: return DC_EINVAL;          // unreachable: V <= 8, C * V <= 16
+        }
+#undef DCS_TILES_LAUNCH
+    } else if (path.kind == TILE_SPLIT) {
+        const TileSplit sp = split_carve(scratch, T, a.N, a.C);
+        const dim3 grid(static_cast<unsigned>(sp.S), static_cast<unsigned>(T));
+        hipLaunchKernelGGL(k_tiles_split_stats, grid, dim3(kTileBlock), 0, st, a, sp);
+        hipLaunchKernelGGL(k_tiles_split_score, grid, dim3(kTileBlock), 0, st, a, sp);
+        hipLaunchKernelGGL(k_tiles_split_select, dim3(static_cast<unsigned>(T)), dim3(kWave), 0, st, a, sp);
+    } else {
+        hipLaunchKernelGGL(k_topsis_tiles_gen, dim3(static_cast<unsigned>(T)), dim3(kTileBlock), 0, st, a);
+    }
+    if (hipGetLastError() != hipSuccess) return DC_EDEVICE;
+    return DC_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *dc_strerror(int code) {
@@ -1627,76 +1729,28 @@ int dc_pending(dc_ctx *ctx, int64_t *n) {
 int dc_topsis_tiles(int64_t T, int32_t C, int32_t N, const int32_t *x, const uint8_t *feasible,
                     const int32_t *cost, const float *weight, float *scores, int32_t *best, float *best_score,
                     void *stream) {
-    if (T < 0 || T > 0x7fffffffLL || C < 1 || C > DC_MAX_CRIT || N < 1 || N > (1 << 20)) return DC_EINVAL;
-    if (T == 0) return DC_OK;
-    if (!x || !best || !weight) return DC_EINVAL;
     TileArgs a{};
-    a.x = x;
-    a.feas = feasible;
-    a.scores = scores;
-    a.best = best;
-    a.best_score = best_score;
-    a.C = C;
-    a.N = N;
-    for (int c = 0; c < C; ++c) {
-        if (!(weight[c] > 0.f) || !std::isfinite(weight[c])) return DC_EINVAL;
-        a.w[c] = weight[c];
-        a.cost[c] = cost ? (cost[c] != 0) : 0;
-    }
+    TilePath path{};
+    int rc = tiles_prepare(T, C, N, x, feasible, cost, weight, scores, best, best_score, &a, &path);
+    if (rc || T == 0) return rc;
     const hipStream_t st = static_cast<hipStream_t>(stream);
-    auto al = [](const void *p, uintptr_t m) { return (reinterpret_cast<uintptr_t>(p) & (m - 1)) == 0; };
-    const bool vec = N % 4 == 0 && al(x, 16) && (!scores || al(scores, 16)) && (!feasible || al(feasible, 4));
-    // four-server groups per lane when one wavefront holds the tile
-    const int V = (N + 4 * kWave - 1) / (4 * kWave);
-    const int Vp = V <= 1 ? 1 : V <= 2 ? 2 : V <= 4 ? 4 : V <= 8 ? 8 : 16;   // 16: two passes
-    const dim3 grid(static_cast<unsigned>(T)), block(kTileBlock);
-    if (vec && Vp <= 8 && C * Vp <= 16) {
-        // persistent grid: as many workgroups as fit on the device at once,
-        // never more than needed for one wavefront per tile
-        int dev = 0, cus = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-            return DC_EDEVICE;
-        auto pgrid = [&](const void *k) {
-            int per = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, kTileBlock, 0) != hipSuccess || per < 1) per = 1;
-            const long long need = (T + kTileWaves - 1) / kTileWaves;
-            return dim3(static_cast<unsigned>(std::min<long long>(need, (long long)per * cus)));
-        };
-#define DCS_TILES_LAUNCH(CC, VV)                                                                         \
-    hipLaunchKernelGGL((k_topsis_tiles_wave<CC, VV>),                                                    \
-                       pgrid(reinterpret_cast<const void *>(k_topsis_tiles_wave<CC, VV>)), block, 0, st, a, (long long)T)
-        switch (C * 100 + Vp) {
-        case 101: DCS_TILES_LAUNCH(1, 1); break;
-        case 102: DCS_TILES_LAUNCH(1, 2); break;
-        case 104: DCS_TILES_LAUNCH(1, 4); break;
-        case 108: DCS_TILES_LAUNCH(1, 8); break;
-        case 201: DCS_TILES_LAUNCH(2, 1); break;
-        case 202: DCS_TILES_LAUNCH(2, 2); break;
-        case 204: DCS_TILES_LAUNCH(2, 4); break;
-        case 208: DCS_TILES_LAUNCH(2, 8); break;
-        case 301: DCS_TILES_LAUNCH(3, 1); break;
-        case 302: DCS_TILES_LAUNCH(3, 2); break;
-        case 304: DCS_TILES_LAUNCH(3, 4); break;
-        case 401: DCS_TILES_LAUNCH(4, 1); break;
-        case 402: DCS_TILES_LAUNCH(4, 2); break;
-        case 404: DCS_TILES_LAUNCH(4, 4); break;
-        case 501: DCS_TILES_LAUNCH(5, 1); break;
-        case 502: DCS_TILES_LAUNCH(5, 2); break;
-        case 601: DCS_TILES_LAUNCH(6, 1); break;
-        case 602: DCS_TILES_LAUNCH(6, 2); break;
-        case 701: DCS_TILES_LAUNCH(7, 1); break;
-        case 702: DCS_TILES_LAUNCH(7, 2); break;
-        case 801: DCS_TILES_LAUNCH(8, 1); break;
-        case 802: DCS_TILES_LAUNCH(8, 2); break;
-        default: return DC_EINVAL;          // unreachable: Vp <= 8, C * Vp <= 16
-        }
-#undef DCS_TILES_LAUNCH
-    } else {
-        hipLaunchKernelGGL(k_topsis_tiles_gen, grid, block, 0, st, a);
+    if (path.kind != TILE_SPLIT) return tiles_launch(a, T, path, nullptr, st);
+    // the split path's partials: stream-ordered allocation, freed behind the
+    // launches (or, where the device has no stream-ordered allocator,
+    // allocated and freed around a synchronised launch)
+    void *scr = nullptr;
+    const size_t bytes = split_scratch_bytes(T, N, C);
+    if (hipMallocAsync(&scr, bytes, st) == hipSuccess) {
+        rc = tiles_launch(a, T, path, scr, st);
+        if (hipFreeAsync(scr, st) != hipSuccess) return DC_EDEVICE;
+        return rc;
     }
-    if (hipGetLastError() != hipSuccess) return DC_EDEVICE;
-    return DC_OK;
+    (void)hipGetLastError();
+    if (hipMalloc(&scr, bytes) != hipSuccess) return DC_ENOMEM;
+    rc = tiles_launch(a, T, path, scr, st);
+    const bool done = hipStreamSynchronize(st) == hipSuccess;
+    if (done) (void)hipFree(scr);      // left allocated if the device did not finish
+    return done ? rc : DC_EDEVICE;
 }
 
 int dc_last_timing(dc_ctx *ctx, float *ms, int64_t *launches, int64_t *steps) {

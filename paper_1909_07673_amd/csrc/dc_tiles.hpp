@@ -231,4 +231,155 @@ __global__ __launch_bounds__(kTileBlock) void k_topsis_tiles_gen(TileArgs a) {
     tile_select(a, t, kb, wkey);
 }
 
+// ---------------------------------------------------------------- large tiles
+// A few tiles of many servers (a large data center's matrix) would leave
+// most of the device idle at one workgroup per tile, so each tile is split
+// into slices of kSplitSlice servers, one workgroup each, and the
+// reductions go through partials in scratch memory:
+//   1. per slice, the exact column statistics -> sp.s2, sp.mx, sp.mn;
+//   2. per slice, the tile's totals from all slices (in slice order), the
+//      closeness of the slice's servers and the slice's best key -> sp.key;
+//   3. per tile, the best key over its slices.
+// The totals are exact integers, so the scores are bit-identical to the
+// other paths.
+constexpr int kSplitSlice = 2048;
+constexpr long long kSplitMaxTiles = 1024;   // more tiles fill the device at one workgroup each
+
+struct TileSplit {
+    unsigned long long *s2;   // [T][S][C] slice sums of squares
+    int *mx, *mn;             // [T][S][C] slice maxima / minima
+    unsigned long long *key;  // [T][S] slice best keys
+    int S;                    // slices per tile
+};
+
+// Scratch bytes of the split path for T tiles of N servers and C criteria
+// (each region 256-byte aligned).
+__host__ __device__ inline size_t split_scratch_bytes(long long T, int N, int C) {
+    const long long S = (N + kSplitSlice - 1) / kSplitSlice;
+    auto al = [](long long b) { return static_cast<size_t>((b + 255) & ~255LL); };
+    return al(T * S * C * 8) + 2 * al(T * S * C * 4) + al(T * S * 8);
+}
+
+__host__ __device__ inline TileSplit split_carve(void *base, long long T, int N, int C) {
+    const long long S = (N + kSplitSlice - 1) / kSplitSlice;
+    auto al = [](long long b) { return static_cast<size_t>((b + 255) & ~255LL); };
+    char *p = static_cast<char *>(base);
+    TileSplit sp;
+    sp.S = static_cast<int>(S);
+    sp.s2 = reinterpret_cast<unsigned long long *>(p); p += al(T * S * C * 8);
+    sp.mx = reinterpret_cast<int *>(p); p += al(T * S * C * 4);
+    sp.mn = reinterpret_cast<int *>(p); p += al(T * S * C * 4);
+    sp.key = reinterpret_cast<unsigned long long *>(p);
+    return sp;
+}
+
+// grid (S, T): column statistics of slice blockIdx.x of tile blockIdx.y.
+__global__ __launch_bounds__(kTileBlock) void k_tiles_split_stats(TileArgs a, TileSplit sp) {
+    __shared__ int wst[5 * kMaxCrit * kTileWaves];
+    const int s = blockIdx.x;
+    const long long t = blockIdx.y;
+    const int N = a.N, C = a.C, u0 = s * kSplitSlice, u1 = min(N, u0 + kSplitSlice);
+    const int *x = a.x + static_cast<size_t>(t) * C * N;
+    unsigned long long s2[kMaxCrit];
+    int mx[kMaxCrit], mn[kMaxCrit];
+#pragma unroll
+    for (int c = 0; c < kMaxCrit; ++c) { s2[c] = 0; mx[c] = -kBig - 1; mn[c] = kBig; }
+    for (int u = u0 + threadIdx.x; u < u1; u += kTileBlock) {
+#pragma unroll
+        for (int c = 0; c < kMaxCrit; ++c) {
+            if (c >= C) break;
+            const int e = x[static_cast<size_t>(c) * N + u];
+            s2[c] += static_cast<unsigned long long>(static_cast<long long>(e) * e);
+            mx[c] = max(mx[c], e);
+            mn[c] = min(mn[c], e);
+        }
+    }
+    tile_stats(C, s2, mx, mn, wst);
+    if (threadIdx.x < C) {
+        const int c = threadIdx.x;
+        const size_t o = (static_cast<size_t>(t) * sp.S + s) * C + c;
+#pragma unroll
+        for (int cc = 0; cc < kMaxCrit; ++cc)
+            if (cc == c) { sp.s2[o] = s2[cc]; sp.mx[o] = mx[cc]; sp.mn[o] = mn[cc]; }
+    }
+}
+
+// grid (S, T): closeness of the slice's servers from the tile's totals, and
+// the slice's best feasible key.
+__global__ __launch_bounds__(kTileBlock) void k_tiles_split_score(TileArgs a, TileSplit sp) {
+    __shared__ unsigned long long ts2[kMaxCrit];
+    __shared__ int tmx[kMaxCrit], tmn[kMaxCrit];
+    __shared__ unsigned long long wkey[kTileWaves];
+    const int s = blockIdx.x;
+    const long long t = blockIdx.y;
+    const int N = a.N, C = a.C, u0 = s * kSplitSlice, u1 = min(N, u0 + kSplitSlice);
+    if (threadIdx.x < C) {
+        // tile totals over the slices in slice order (exact integers)
+        const int c = threadIdx.x;
+        unsigned long long v = 0;
+        int hi = -kBig - 1, lo = kBig;
+        for (int x = 0; x < sp.S; ++x) {
+            const size_t o = (static_cast<size_t>(t) * sp.S + x) * C + c;
+            v += sp.s2[o];
+            hi = max(hi, sp.mx[o]);
+            lo = min(lo, sp.mn[o]);
+        }
+        ts2[c] = v;
+        tmx[c] = hi;
+        tmn[c] = lo;
+    }
+    __syncthreads();
+    unsigned long long s2[kMaxCrit];
+    int mx[kMaxCrit], mn[kMaxCrit];
+#pragma unroll
+    for (int c = 0; c < kMaxCrit; ++c) {
+        s2[c] = c < C ? ts2[c] : 0;
+        mx[c] = c < C ? tmx[c] : 0;
+        mn[c] = c < C ? tmn[c] : 0;
+    }
+    float q[kMaxCrit], ap[kMaxCrit], am[kMaxCrit];
+    tile_factors(a, s2, mx, mn, q, ap, am);
+    const int *x = a.x + static_cast<size_t>(t) * C * N;
+    unsigned long long kb = 0;
+    for (int u = u0 + threadIdx.x; u < u1; u += kTileBlock) {
+        int vv[kMaxCrit];
+#pragma unroll
+        for (int c = 0; c < kMaxCrit; ++c) vv[c] = c < C ? x[static_cast<size_t>(c) * N + u] : 0;
+        const float sc = tile_close(C, vv, q, ap, am);
+        if (!a.feas || a.feas[static_cast<size_t>(t) * N + u]) {
+            const unsigned long long k = score_key(sc, u);
+            kb = k > kb ? k : kb;
+        }
+        if (a.scores) a.scores[static_cast<size_t>(t) * N + u] = sc;
+    }
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const unsigned hiw = wave_umax(static_cast<unsigned>(kb >> 32));
+    const unsigned low = wave_umax(static_cast<unsigned>(kb >> 32) == hiw ? static_cast<unsigned>(kb) : 0u);
+    if (lane == 0) wkey[wid] = (static_cast<unsigned long long>(hiw) << 32) | low;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long best = 0;
+#pragma unroll
+        for (int w = 0; w < kTileWaves; ++w) best = wkey[w] > best ? wkey[w] : best;
+        sp.key[static_cast<size_t>(t) * sp.S + s] = best;
+    }
+}
+
+// grid T, one wave: the tile's best key over its slices.
+__global__ __launch_bounds__(kWave) void k_tiles_split_select(TileArgs a, TileSplit sp) {
+    const long long t = blockIdx.x;
+    unsigned long long kb = 0;
+    for (int x = threadIdx.x; x < sp.S; x += kWave) {
+        const unsigned long long k = sp.key[static_cast<size_t>(t) * sp.S + x];
+        kb = k > kb ? k : kb;
+    }
+    const unsigned hiw = wave_umax(static_cast<unsigned>(kb >> 32));
+    const unsigned low = wave_umax(static_cast<unsigned>(kb >> 32) == hiw ? static_cast<unsigned>(kb) : 0u);
+    if (threadIdx.x == 0) {
+        const unsigned long long best = (static_cast<unsigned long long>(hiw) << 32) | low;
+        a.best[t] = best ? static_cast<int>(~low) : -1;
+        if (a.best_score) a.best_score[t] = best ? __uint_as_float(hiw - 1u) : 0.f;
+    }
+}
+
 }  // namespace dcs

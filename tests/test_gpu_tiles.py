@@ -57,18 +57,22 @@ def _run(x, feas, w, cost, scores=True):
 
 SHAPES = [
     # T, C, N, feasible_p, cost     (paths: one wavefront per tile with the
-    # tile in registers, or one workgroup per tile with two passes)
+    # tile in registers; slices of 2,048 servers over several workgroups with
+    # partials in scratch, for up to 1,024 tiles of at least 4,096 servers;
+    # otherwise one workgroup per tile with two passes)
     (9, 4, 1024, None, None),          # wavefront, four groups per lane
     (13, 2, 2048, 0.5, [1, 0]),        # wavefront, eight groups per lane
     (5, 1, 2048, 0.9, None),           # wavefront, eight groups per lane, one criterion
-    (4, 1, 4096, 0.9, None),           # two passes (beyond one wavefront's registers)
+    (4, 1, 4096, 0.9, None),           # split, two slices
     (7, 3, 1000, 0.5, [0, 1, 0]),      # wavefront, ragged last group
     (6, 5, 512, 0.6, [0, 0, 0, 0, 1]), # wavefront, five criteria
     (5, 5, 2048, 0.6, [0, 0, 0, 0, 1]),  # two passes
-    (3, 4, 4096, 0.3, None),           # two passes
-    (4, 8, 3000, 0.5, [0, 1, 0, 0, 1, 0, 0, 0]),   # ragged last group
+    (3, 4, 4096, 0.3, None),           # split
+    (4, 8, 3000, 0.5, [0, 1, 0, 0, 1, 0, 0, 0]),   # two passes, ragged last group
     (3, 3, 54, 0.7, None),             # k=6: N % 4 != 0, two passes
-    (2, 4, 27648, 0.8, None),          # k=48: two passes
+    (2, 4, 27648, 0.8, None),          # k=48: split, 14 slices, the last one half full
+    (1, 5, 8193, 0.5, [0, 0, 0, 0, 1]),  # split, a last slice of one server
+    (1, 4, 1 << 20, 0.9, None),        # the largest N: split, 512 slices
     (3, 1, 16, None, None),            # k=4, one criterion
     (2, 2, 1, 1.0, [1, 0]),
 ]
@@ -123,6 +127,20 @@ def test_tiles_paths_identical():
     assert np.array_equal(b1, b2.cpu().numpy()) and np.array_equal(b1, b3.cpu().numpy())
     assert s1.tobytes() == s2.cpu().numpy().tobytes() == s3.cpu().numpy().tobytes()
     assert sc1.tobytes() == sc2.cpu().numpy().tobytes()
+
+
+def test_tiles_split_equals_two_pass():
+    """1,024 tiles of 4,096 servers take the split path, 1,025 the
+    one-workgroup path: the first 1,024 tiles' results are bit-identical."""
+    T, C, N = 1025, 4, 4096
+    x, feas = make_tiles(seed=9, T=T, N=N, C=C, feasible_p=0.7)
+    w = [0.4, 0.3, 0.2, 0.1]
+    b1, s1, sc1 = _run(x[:1024], feas[:1024], w, [0, 1, 0, 0])
+    b2, s2, sc2 = _run(x, feas, w, [0, 1, 0, 0])
+    assert np.array_equal(b1, b2[:1024])
+    assert s1.tobytes() == s2[:1024].tobytes() and sc1.tobytes() == sc2[:1024].tobytes()
+    for t in (0, 511, 1023):
+        _check_tile(x[t], feas[t], w, [0, 1, 0, 0], sc1[t], b1[t], s1[t])
 
 
 def test_tiles_invalid_arguments():

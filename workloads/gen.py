@@ -273,7 +273,8 @@ def make_config(name: str, seed: int = 0, instances: Optional[int] = None,
 
 
 def make_event_workload(seed: int, k: int = 20, n_req: int = 6000, n: int = 4, total_events: int = 500,
-                        span: int = 250, ranges: Optional[str] = "lower"):
+                        span: int = 250, ranges: Optional[str] = "lower", cpu_hi: int = 2, ram_hi: int = 4,
+                        bw_hi: int = 50):
     """The shape of the paper's GPU evaluation (section VI-A): a k-ary
     fat-tree of 24-core / 256 GB servers with 1 Gbps links and no other
     load; n_req requests of n containers, up to half of them in pods, up to
@@ -281,11 +282,12 @@ def make_event_workload(seed: int, k: int = 20, n_req: int = 6000, n: int = 4, t
     GB per container.  Each request arrives at a uniform event in
     [0, span) and runs for a uniform 1..span events of a total_events run.
     Demands are intervals by default (ranges="lower": those bounds are the
-    maxima, the minima uniform below them).
+    maxima, the minima uniform below them).  cpu_hi, ram_hi, bw_hi: the
+    upper bounds (heavier requests make requests wait on a small k).
     Returns (instance, requests, arrival events, durations)."""
     rng = _rng(np.random.SeedSequence([seed, 6]))
     inst = make_instance(k, 24, 256, 1000, 1000, 1000)
-    reqs = make_requests(n_req, rng, n, n, cpu_lo=1, cpu_hi=2, ram_lo=1, ram_hi=4, bw_lo=1, bw_hi=50,
+    reqs = make_requests(n_req, rng, n, n, cpu_lo=1, cpu_hi=cpu_hi, ram_lo=1, ram_hi=ram_hi, bw_lo=1, bw_hi=bw_hi,
                          pod_frac=0.5, ranges=ranges)
     arrive = np.sort(rng.integers(0, span, size=n_req))
     dur = rng.integers(1, span + 1, size=n_req)
