@@ -507,9 +507,27 @@ static void top_up(or_dc *d, or_path *pp, int64_t max) {
     pp->bw += room;
 }
 
+/* Cut condition at a peer server v != u: every path that ends at v leaves
+ * one of v's links with its demand taken off, so routing all peers held by
+ * v needs the summed residual of v's links to cover their summed demand.
+ * When it does not, the routing below is bound to fail; returning early
+ * gives the same answer without enumerating paths. */
+static int peer_cut_short(const or_dc *d, int u, int P, const int *ph, const int *pbw) {
+    for (int p = 0; p < P; ++p) {
+        const int v = ph[p];
+        if (v == u) continue;
+        int64_t need = 0, cap = 0;
+        for (int q = 0; q < P; ++q) if (ph[q] == v) need += pbw[q];
+        for (int e = d->adj_off[v]; e < d->adj_off[v + 1]; ++e) cap += d->link_res[d->adj_link[e]];
+        if (cap < need) return 1;
+    }
+    return 0;
+}
+
 static int try_commit(or_dc *d, int u, int cpu_i, int cpu_x, int ram_i, int ram_x, int P, const int *ph,
                       const int *pbw, const int *pbx, or_path *paths, int *cpu_a, int *ram_a) {
     if (d->cpu_res[u] < cpu_i || d->ram_res[u] < ram_i) return 0;
+    if (peer_cut_short(d, u, P, ph, pbw)) return 0;
     int routed = 0, ok = 1;
     for (int p = 0; p < P; ++p) {
         paths[p].nl = 0; paths[p].bw = pbx[p];

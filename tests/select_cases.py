@@ -43,3 +43,24 @@ def split_fits():
     inst = loaded()
     inst.link_used[1, 8], inst.link_used[1, 9] = 400, 1000
     return inst
+
+
+def peer_cut(uplink0=500):
+    """k = 4, 1,000 Mbps links.  Residual CPU: server 0 has 32 cores,
+    server 1 14, every other server 10; server 0's uplink has uplink0 Mbps
+    left, every other link is free."""
+    inst = make_instance(4, 32, 256, 1000, 1000, 1000)
+    cpu = np.full(N4, 10, np.int32)
+    cpu[0], cpu[1] = 32, 14
+    hu = np.zeros((2, N4), np.int32)
+    hu[0] = 32 - cpu
+    lu = np.zeros((3, N4), np.int32)
+    lu[0, 0] = 1000 - uplink0
+    inst.host_used, inst.link_used = hu, lu
+    return inst
+
+
+# Containers 0 and 1 need 12 cores (both go to server 0, leaving it 8),
+# container 2 one core and 300 Mbps to each of them.
+REQ_CUT = Request(np.array([12, 12, 1], np.int32), np.array([1, 1, 1], np.int32),
+                  np.array([[0, 2, 300], [1, 2, 300]], np.int32))

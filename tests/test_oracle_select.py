@@ -17,7 +17,8 @@ import pytest
 import oracle as O
 from workloads import Request
 
-from select_cases import N4, REQ, empty as _empty, loaded as _loaded, split_fits as _split_fits
+from select_cases import N4, REQ, REQ_CUT, empty as _empty, loaded as _loaded, peer_cut as _peer_cut, \
+    split_fits as _split_fits
 
 CPU_ONLY = dict(crit=(O.CRIT_CPU,), weight=[1.0])
 
@@ -121,7 +122,44 @@ def check_tie_low():
     o.close()
 
 
-CHECKS = (check_identical_servers, check_topsis_hand_case, check_ahp_hand_case, check_split_fits, check_tie_low)
+def check_peer_cut():
+    """Both peers of container 2 sit on server 0, whose uplink has 500 Mbps
+    left for their 2 x 300.  CPU closeness over min 8 (server 0) and max 14
+    (server 1): server 1 scores 1, servers 2..15 1/3, server 0 0.  Every
+    server but 0 passes the per-peer checks (each path 500 wide) and its own
+    uplink carries 600, but routing the second path finds 200 left on
+    server 0's uplink: all fifteen commits fail, and only server 0, which
+    holds both peers and needs no link, takes the container (score 0, no
+    runner-up).  With 600 left (the control) both paths fit exactly and
+    server 1 takes it."""
+    o = O.Oracle(_peer_cut(500), O.method(kind=O.TOPSIS, **CPU_ONLY))
+    before = o.state()
+    r = o.run_request(REQ_CUT, detail=True)
+    assert r["status"] == 1 and r["hosts"].tolist() == [0, 0, 0], r["hosts"]
+    np.testing.assert_allclose(r["scores"], [1.0, 1.0, 0.0], rtol=0, atol=1e-15)
+    assert r["ref_gap"][2] == np.inf
+    want = before.copy()
+    want[0, 0] -= 25
+    want[1, 0] -= 3
+    want[2, 0] += 3
+    np.testing.assert_array_equal(o.state(), want)     # no link used
+    o.close()
+    o = O.Oracle(_peer_cut(600), O.method(kind=O.TOPSIS, **CPU_ONLY))
+    before = o.state()
+    r = o.run_request(REQ_CUT, detail=True)
+    assert r["status"] == 1 and r["hosts"].tolist() == [0, 0, 1], r["hosts"]
+    assert r["scores"][2] == 1.0 and r["ref_gap"][2] == pytest.approx(2 / 3, abs=1e-15)
+    want = before.copy()
+    want[0, [0, 1]] -= [24, 1]
+    want[1, [0, 1]] -= [2, 1]
+    want[2, [0, 1]] += [2, 1]
+    want[3, [0, 1]] -= 600                              # both paths: up[1], up[0]
+    np.testing.assert_array_equal(o.state(), want)
+    o.close()
+
+
+CHECKS = (check_identical_servers, check_topsis_hand_case, check_ahp_hand_case, check_split_fits, check_tie_low,
+          check_peer_cut)
 
 
 @pytest.mark.parametrize("check", CHECKS, ids=lambda f: f.__name__)
@@ -161,3 +199,73 @@ def test_planted_selection_mistakes_fail_a_pin(oracle_lib, tmp_path, monkeypatch
         except AssertionError:
             caught.append(check.__name__)
     assert caught, f"planted mistake {name} passes every selection pin"
+
+
+def _tight_workload(seed):
+    """k = 4 with 1,000 Mbps links, 0-70 % background and requests of 2-8
+    containers at 100-900 Mbps per pair: many placements leave several peers
+    on one server, so later commits often fail on a peer's uplink."""
+    from workloads import make_instance, make_requests
+    rng = np.random.default_rng(seed)
+    inst = make_instance(4, 32, 256, 1000, 1000, 1000, background=0.7, rng=rng)
+    return inst, make_requests(12, rng, 2, 8, bw_hi=900)
+
+
+def _replay_all(seeds, kind):
+    out = []
+    for seed in seeds:
+        inst, reqs = _tight_workload(seed)
+        o = O.Oracle(inst, O.method(kind=kind))
+        for req in reqs:
+            r = o.run_request(req, detail=True)
+            out.append((r["status"], r["failed_at"], r["hosts"].tolist(), r["ref_host"].tolist()))
+        out.append(o.state().tolist())
+        o.close()
+    return out
+
+
+# The cut pre-check of the commit only answers early what the routing would
+# answer: a copy without it must agree everywhere.  Planted mistakes in it
+# must fail a hand case or that agreement.
+CUT_SITE = "        if (v == u) continue;\n        int64_t need = 0, cap = 0;\n"
+CUT_MUTANTS = {
+    "no_cut": ("    if (peer_cut_short(d, u, P, ph, pbw)) return 0;\n", ""),
+    "cut_counts_own_server": (CUT_SITE, "        int64_t need = 0, cap = 0;\n"),
+    "cut_strict_boundary": ("        if (cap < need) return 1;", "        if (cap <= need) return 1;"),
+    "cut_sums_all_peers": ("for (int q = 0; q < P; ++q) if (ph[q] == v) need += pbw[q];",
+                           "for (int q = 0; q < P; ++q) need += pbw[q];"),
+}
+
+
+def _variant(tmp_path, name):
+    with open(O._SRC) as f:
+        src = f.read()
+    old, new = CUT_MUTANTS[name]
+    assert src.count(old) == 1, f"mutation site of {name} not found once in the oracle source"
+    return O.load(O.build_variant(src.replace(old, new), os.path.join(str(tmp_path), f"liboracle_{name}.so")))
+
+
+def test_peer_cut_changes_no_result(oracle_lib, tmp_path, monkeypatch):
+    seeds = range(40)
+    base = {kind: _replay_all(seeds, kind) for kind in (O.TOPSIS, O.AHP)}
+    rejected = sum(1 for rec in base[O.TOPSIS] if isinstance(rec, tuple) and rec[0] == 0)
+    assert rejected >= 20, rejected
+    monkeypatch.setattr(O, "_lib", _variant(tmp_path, "no_cut"))
+    for kind in (O.TOPSIS, O.AHP):
+        assert _replay_all(seeds, kind) == base[kind], kind
+    check_peer_cut()
+
+
+@pytest.mark.parametrize("name", sorted(set(CUT_MUTANTS) - {"no_cut"}))
+def test_planted_cut_mistakes_fail_a_pin(oracle_lib, tmp_path, monkeypatch, name):
+    seeds = range(40)
+    base = _replay_all(seeds, O.TOPSIS)
+    monkeypatch.setattr(O, "_lib", _variant(tmp_path, name))
+    caught = []
+    try:
+        check_peer_cut()
+    except AssertionError:
+        caught.append("hand case")
+    if _replay_all(seeds, O.TOPSIS) != base:
+        caught.append("agreement")
+    assert caught, f"planted mistake {name} passes the cut pins"
