@@ -11,7 +11,7 @@ import pytest
 
 import oracle as O
 from parity import lockstep, trace_by_request
-from select_cases import REQ, empty, loaded, split_fits
+from select_cases import REQ, REQ_CUT, empty, loaded, peer_cut, split_fits
 from workloads import Request
 
 pytestmark = pytest.mark.gpu
@@ -74,5 +74,24 @@ def test_identical_servers_take_lowest_index(name, method, mode, grid):
     kind = O.AHP if method == dc.DC_AHP else O.TOPSIS
     o = O.Oracle(inst, O.method(kind=kind, crit=(O.CRIT_CPU,), weight=[1.0]))
     st = lockstep(o, s, ids, reqs, res, check_paths=True)
+    assert st["near_tie"] == 0
+    s.close()
+
+
+@pytest.mark.parametrize("name,method,mode,grid", FORMS[:5], ids=[f[0] for f in FORMS[:5]])
+@pytest.mark.parametrize("uplink0,want", [(500, [0, 0, 0]), (600, [0, 0, 1])], ids=["cut_short", "cut_exact"])
+def test_peer_uplink_cut(name, method, mode, grid, uplink0, want):
+    """Both peers of the last container sit on server 0, whose uplink has
+    500 Mbps left for their 2 x 300: no other server can route both paths,
+    so the container goes to server 0 itself, the lowest-scored server
+    (with 600 left both paths fit and the best server, 1, takes it).  In
+    lockstep with the oracle, paths included."""
+    inst = peer_cut(uplink0)
+    s = dc.Scheduler([inst], method=method, mode=mode, grid=grid, **CPU_ONLY)
+    ids, res = _schedule(s, [REQ_CUT], mode)
+    r = res[ids[0]]
+    assert r.status == 1 and r.hosts.tolist() == want, (name, r.status, r.hosts)
+    o = O.Oracle(inst, O.method(kind=O.TOPSIS, crit=(O.CRIT_CPU,), weight=[1.0]))
+    st = lockstep(o, s, ids, [REQ_CUT], res, check_paths=True)
     assert st["near_tie"] == 0
     s.close()
