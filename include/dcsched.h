@@ -56,7 +56,8 @@ enum dc_status {
     DC_EAGAIN = -3,   /* serving admission: memory budget full, retry later   */
     DC_ENOENT = -4,   /* unknown request id, or request not accepted          */
     DC_EDEVICE = -5,  /* a HIP call failed; the context is poisoned           */
-    DC_ESTATE = -6    /* call not valid in this mode / state                  */
+    DC_ESTATE = -6,   /* call not valid in this mode / state                  */
+    DC_ETOOBIG = -7   /* needs more scratch than the static buffer holds      */
 };
 
 enum dc_method { DC_TOPSIS = 0, DC_AHP = 1 };
@@ -335,6 +336,26 @@ int dc_last_timing(dc_ctx *ctx, float *ms, int64_t *launches, int64_t *steps);
 int dc_topsis_tiles(int64_t T, int32_t C, int32_t N, const int32_t *x, const uint8_t *feasible,
                     const int32_t *cost, const float *weight, float *scores, int32_t *best, float *best_score,
                     void *stream);
+
+/* dc_topsis_tiles for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, results (bit-identical) and errors, but it
+ * calls no hipMalloc, hipFree or allocating routine: the large-tile path's
+ * partials live in a static device array of 4 MiB (DC_STATIC_SCRATCH_BYTES),
+ * one per device, held until the process ends.  The first call on a device
+ * resolves that array's address (hipGetSymbolAddress, which may load the
+ * library's code object): make one call, T = 0 will do, before capture.
+ * A call whose large-tile partials need more than 4 MiB returns DC_ETOOBIG
+ * (about T * ceil(N / 2048) * (16 C + 8) bytes: 1,024 tiles of 27,648
+ * servers at C = 8 fit; other shapes use no scratch and have no limit).
+ * Every call on one device shares its array: calls that overlap on one
+ * device (several streams, several host threads) race and must be
+ * serialised by the caller.  The caller passes and owns all inputs and
+ * outputs. */
+#define DC_STATIC_SCRATCH_BYTES (4u << 20)
+int dc_topsis_tiles_noalloc(int64_t T, int32_t C, int32_t N, const int32_t *x, const uint8_t *feasible,
+                            const int32_t *cost, const float *weight, float *scores, int32_t *best,
+                            float *best_score, void *stream);
 
 void dc_destroy(dc_ctx *ctx);
 const char *dc_strerror(int code);

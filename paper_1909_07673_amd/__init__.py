@@ -4,7 +4,8 @@ The scheduling path (criteria, TOPSIS / AHP scoring, selection, commit,
 release) runs in the HIP kernels of ``libdcsched.so`` behind the C ABI of
 ``include/dcsched.h``; this package only marshals arguments to it.
 """
-from .binding import (Scheduler, Result, RESULT_DTYPE, DcError, topsis_tiles, lib, strerror, LIB_PATH,
+from .binding import (Scheduler, Result, RESULT_DTYPE, DcError, topsis_tiles, topsis_tiles_noalloc, lib, strerror,
+                      LIB_PATH, DC_ETOOBIG, DC_STATIC_SCRATCH_BYTES,
                       DC_OK, DC_EINVAL, DC_ENOMEM, DC_EAGAIN, DC_ENOENT, DC_EDEVICE, DC_ESTATE,
                       DC_TOPSIS, DC_AHP, DC_AHP_SAATY9, DC_AHP_RATIO, DC_AHP_DIFF,
                       DC_MODE_PLAIN, DC_MODE_BATCHED, DC_MODE_SERVING, DC_ROUTE_EACH, DC_ROUTE_END,

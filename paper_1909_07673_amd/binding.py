@@ -15,7 +15,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdcsched.so")
 
-DC_OK, DC_EINVAL, DC_ENOMEM, DC_EAGAIN, DC_ENOENT, DC_EDEVICE, DC_ESTATE = 0, -1, -2, -3, -4, -5, -6
+DC_OK, DC_EINVAL, DC_ENOMEM, DC_EAGAIN, DC_ENOENT, DC_EDEVICE, DC_ESTATE, DC_ETOOBIG = 0, -1, -2, -3, -4, -5, -6, -7
+DC_STATIC_SCRATCH_BYTES = 4 << 20
 DC_TOPSIS, DC_AHP = 0, 1
 DC_AHP_SAATY9, DC_AHP_RATIO, DC_AHP_DIFF = 0, 1, 2
 DC_MODE_PLAIN, DC_MODE_BATCHED, DC_MODE_SERVING = 0, 1, 2
@@ -100,6 +101,7 @@ def lib():
         L.dc_last_timing.argtypes = [P, C.POINTER(C.c_float), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.dc_pending.argtypes = [P, C.POINTER(C.c_int64)]
         L.dc_topsis_tiles.argtypes = [C.c_int64, C.c_int32, C.c_int32, P, P, i32p, C.POINTER(C.c_float), P, P, P, P]
+        L.dc_topsis_tiles_noalloc.argtypes = L.dc_topsis_tiles.argtypes
         L.dc_destroy.argtypes = [P]
         L.dc_destroy.restype = None
         L.dc_strerror.argtypes = [C.c_int]
@@ -397,3 +399,36 @@ def topsis_tiles(x, weight, cost=None, feasible=None, scores: bool = False, stre
                                  best.data_ptr(), bscore.data_ptr(), _stream_handle(stream)),
            "dc_topsis_tiles")
     return best, bscore, sc
+
+
+def topsis_tiles_noalloc(x, weight, best, best_score=None, cost=None, feasible=None, scores=None, stream=None):
+    """dc_topsis_tiles_noalloc on caller-owned device tensors: x int32
+    [T][C][N], feasible uint8 [T][N] or None, outputs best int32 [T],
+    best_score float32 [T] or None, scores float32 [T][N] or None, all
+    contiguous on one device.  Allocates nothing on the device; launched on
+    `stream` (default: torch's current stream of x's device)."""
+    import torch
+    if x.dtype != torch.int32 or x.dim() != 3 or not x.is_cuda or not x.is_contiguous():
+        raise ValueError("x must be a contiguous int32 [T][C][N] device tensor")
+    T, Cn, N = x.shape
+    dev = x.device
+
+    def out(t, dtype, shape, name):
+        if t is None:
+            return None
+        if t.dtype != dtype or tuple(t.shape) != shape or t.device != dev or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {dtype} {list(shape)} tensor on x's device")
+        return t.data_ptr()
+
+    bp = out(best, torch.int32, (T,), "best")
+    if bp is None:
+        raise ValueError("best is required")
+    sp = out(best_score, torch.float32, (T,), "best_score")
+    scp = out(scores, torch.float32, (T, N), "scores")
+    fp = out(feasible, torch.uint8, (T, N), "feasible")
+    w = (C.c_float * Cn)(*[float(v) for v in weight])
+    cv = (C.c_int32 * Cn)(*[int(v) for v in (cost if cost is not None else [0] * Cn)])
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    _check(lib().dc_topsis_tiles_noalloc(T, Cn, N, x.data_ptr(), fp, cv, w, scp, bp, sp, _stream_handle(stream)),
+           "dc_topsis_tiles_noalloc")

@@ -15,6 +15,7 @@
 #include <fstream>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <thread>
@@ -1096,9 +1097,9 @@ int tiles_prepare(int64_t T, int32_t C, int32_t N, const int32_t *x, const uint8
     return DC_OK;
 }
 
-// scratch: split_scratch_bytes(T, N, C) device bytes for the split path
+// work: split_scratch_bytes(T, N, C) device bytes for the split path
 // (unused otherwise).
-int tiles_launch(const TileArgs &a, int64_t T, const TilePath &path, void *scratch, hipStream_t st) {
+int tiles_launch(const TileArgs &a, int64_t T, const TilePath &path, void *work, hipStream_t st) {
     if (path.kind == TILE_WAVE) {
         // persistent grid: as many workgroups as fit on the device at once,
         // never more than needed for one wavefront per tile
@@ -1143,7 +1144,7 @@ int tiles_launch(const TileArgs &a, int64_t T, const TilePath &path, void *scrat
         }
 #undef DCS_TILES_LAUNCH
     } else if (path.kind == TILE_SPLIT) {
-        const TileSplit sp = split_carve(scratch, T, a.N, a.C);
+        const TileSplit sp = split_carve(work, T, a.N, a.C);
         const dim3 grid(static_cast<unsigned>(sp.S), static_cast<unsigned>(T));
         hipLaunchKernelGGL(k_tiles_split_stats, grid, dim3(kTileBlock), 0, st, a, sp);
         hipLaunchKernelGGL(k_tiles_split_score, grid, dim3(kTileBlock), 0, st, a, sp);
@@ -1152,6 +1153,36 @@ int tiles_launch(const TileArgs &a, int64_t T, const TilePath &path, void *scrat
         hipLaunchKernelGGL(k_topsis_tiles_gen, dim3(static_cast<unsigned>(T)), dim3(kTileBlock), 0, st, a);
     }
     if (hipGetLastError() != hipSuccess) return DC_EDEVICE;
+    return DC_OK;
+}
+
+// Scratch of dc_topsis_tiles_noalloc: the split path's partials in a
+// static device array, one copy per device, held until the process ends.
+// Host code never passes the array's name to a kernel (on the host it is a
+// stand-in, not a device address): the address comes from
+// hipGetSymbolAddress, resolved once per device with that device current.
+constexpr size_t kStaticScratchBytes = DC_STATIC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+// Device address of the current device's copy of `scratch`.
+int static_scratch(void **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return DC_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return DC_EDEVICE;
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
     return DC_OK;
 }
 
@@ -1168,6 +1199,7 @@ const char *dc_strerror(int code) {
     case DC_ENOENT: return "unknown or not accepted request";
     case DC_EDEVICE: return "device error (context poisoned)";
     case DC_ESTATE: return "call not valid in this mode or state";
+    case DC_ETOOBIG: return "needs more scratch than the static buffer holds";
     default: return "unknown error";
     }
 }
@@ -1751,6 +1783,20 @@ int dc_topsis_tiles(int64_t T, int32_t C, int32_t N, const int32_t *x, const uin
     const bool done = hipStreamSynchronize(st) == hipSuccess;
     if (done) (void)hipFree(scr);      // left allocated if the device did not finish
     return done ? rc : DC_EDEVICE;
+}
+
+int dc_topsis_tiles_noalloc(int64_t T, int32_t C, int32_t N, const int32_t *x, const uint8_t *feasible,
+                            const int32_t *cost, const float *weight, float *scores, int32_t *best,
+                            float *best_score, void *stream) {
+    TileArgs a{};
+    TilePath path{};
+    int rc = tiles_prepare(T, C, N, x, feasible, cost, weight, scores, best, best_score, &a, &path);
+    if (rc) return rc;
+    void *work = nullptr;
+    if ((rc = static_scratch(&work))) return rc;     // the first call on a device resolves the address
+    if (T == 0) return DC_OK;
+    if (path.kind == TILE_SPLIT && split_scratch_bytes(T, N, C) > kStaticScratchBytes) return DC_ETOOBIG;
+    return tiles_launch(a, T, path, work, static_cast<hipStream_t>(stream));
 }
 
 int dc_last_timing(dc_ctx *ctx, float *ms, int64_t *launches, int64_t *steps) {
