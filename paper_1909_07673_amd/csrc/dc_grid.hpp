@@ -138,7 +138,7 @@ __device__ bool grid_topsis_step(const Topo &t, const State &st, const Method &m
     // ---- A: peers, own capacities
     for (int p = threadIdx.x; p < P; p += BS) {
         const int v = rv.hosts[rv.pj[p]];
-        sm.pk[p] = make_int4(v, fdiv(v, t.rh) | (fdiv(v, t.rhh) << 16), rv.pbw[p], st.up[v]);
+        sm.pk[p] = make_int4(v, edge_of(t, v) | (pod_of(t, v) << 16), rv.pbw[p], st.up[v]);
     }
     for (int e = threadIdx.x; e < h; e += BS) {
         int se = 0;
@@ -179,7 +179,7 @@ __device__ bool grid_topsis_step(const Topo &t, const State &st, const Method &m
     for (int c = 0; c < kMaxCrit; ++c) { s2[c] = 0; mx[c] = -kBig - 1; mn[c] = kBig; }
     for (int x = threadIdx.x; x < hh; x += BS) {
         const int u = ubase + x;
-        const int up_u = st.up[u], el = fdiv(x, t.rh), eu = w * h + el;
+        const int up_u = st.up[u], el = edge_of(t, x), eu = w * h + el;
         int pbw_acc = up_u, up_acc = 0, hop_acc = 0, oute = 0, outp = 0;
         int feas = (st.cpu[u] >= s.cpu) & (st.ram[u] >= s.ram);
         for (int pc = 0; pc < P; ++pc) {
@@ -299,7 +299,7 @@ __device__ bool grid_topsis_step(const Topo &t, const State &st, const Method &m
         int f = xs[nc * hh + x];
         if (!m.route_end) {
             f &= (dh1 < 0) | ((dh0 == dh1) & (u == dh0));
-            f &= (de1 < 0) | ((de0 == de1) & (w * h + fdiv(x, t.rh) == de0));
+            f &= (de1 < 0) | ((de0 == de1) & (w * h + edge_of(t, x) == de0));
             f &= (dp1 < 0) | ((dp0 == dp1) & (w == dp0));
         }
         if (!f) return 0ull;

@@ -619,14 +619,41 @@ __host__ __device__ inline size_t req_lds_ints() { return 6 * (size_t)kMaxN + 4 
 // the whole launch; the workgroup walks its requests in FCFS order and
 // their containers in index order.  Each thread scores G servers together
 // (the autotuner picks BS and G, and the peer chunk p.pc_cap).
-template <int BS, int G>
+// K > 0: the data centers are k = K fat-trees scored on the four default
+// criteria (CPU, RAM, active, path bandwidth; all benefits), so the
+// topology and the criterion list are compile-time constants: index
+// arithmetic becomes shifts and the per-criterion selection folds away.
+// Same arithmetic as K = 0 (any k and criteria), bit-identical results.
+template <int K>
+__device__ __forceinline__ Topo topo_of(const Topo &t) {
+    if (K == 0) return t;
+    constexpr int h = K / 2, hh = h * h;
+    return Topo{K, h, hh, K * hh, K * h, 1.0f / h, 1.0f / hh, 1.0f / (K * h)};
+}
+
+template <int K>
+__device__ __forceinline__ Method method_of(const Method &m) {
+    if (K == 0) return m;
+    Method d = m;
+    d.method = 0;
+    d.nc = 4;
+    for (int c = 0; c < kMaxCrit; ++c) {
+        d.crit[c] = c < 4 ? c : 0;
+        d.cost[c] = 0;
+    }
+    return d;
+}
+
+template <int BS, int G, int K>
 __global__ __launch_bounds__(BS) void k_topsis_batched(Params p) {
     extern __shared__ __align__(16) char dsm[];
     const int inst = blockIdx.x;
-    const int N = p.t.N;
-    Smem sm = carve(dsm, p.pc_cap, p.t.nsw);
-    int *xs = lds_after_tables(dsm, p.pc_cap, p.t.nsw);
-    int *ls = xs + (size_t)xs_rows(p.m.nc) * N;
+    const Topo t = topo_of<K>(p.t);
+    const Method m = method_of<K>(p.m);
+    const int N = t.N;
+    Smem sm = carve(dsm, p.pc_cap, t.nsw);
+    int *xs = lds_after_tables(dsm, p.pc_cap, t.nsw);
+    int *ls = xs + (size_t)xs_rows(m.nc) * N;
     int *rq_host = ls + 6 * (size_t)N;
     int *rq_cpu = rq_host + kMaxN, *rq_ram = rq_cpu + kMaxN, *rq_poff = rq_ram + kMaxN;
     int *rq_pj = rq_poff + kMaxN + 4, *rq_pbw = rq_pj + kMaxPairs, *rq_pbmax = rq_pbw + kMaxPairs;
@@ -662,7 +689,7 @@ __global__ __launch_bounds__(BS) void k_topsis_batched(Params p) {
             const StepIn s{r, i, n, g0, g0 + i, pb + q0, rq_poff[i + 1] - q0, rq_cpu[i], rq_ram[i],
                            rq_cmax[i], rq_rmax[i]};
             const ReqView rv{rq_pj + q0, rq_pbw + q0, rq_host, rq_host, rq_pbmax + q0};
-            if (!topsis_step<BS, G, true>(p.t, st, p.m, lb, sm, xs, p.pc_cap, p.tr, inst, s, rv)) break;
+            if (!topsis_step<BS, G, true>(t, st, m, lb, sm, xs, p.pc_cap, p.tr, inst, s, rv)) break;
         }
         __syncthreads();
     }

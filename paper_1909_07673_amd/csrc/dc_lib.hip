@@ -619,9 +619,28 @@ size_t batched_lds(const dc_ctx *ctx, int pc) {
     return step_lds_bytes(pc, ctx->t.nsw, (size_t)xs_rows(ctx->m.nc) * ctx->N, 6 * (size_t)ctx->N + req_lds_ints());
 }
 
+// The batched kernel compiled for k = 16 fat-trees scored on the four
+// default criteria (the constants fold into the kernel), or for any case.
+constexpr int kBatchedK = 16;
+bool batched_specialised(const dc_ctx *ctx) {
+    if (ctx->t.k != kBatchedK || ctx->m.nc != 4) return false;
+    for (int c = 0; c < 4; ++c)
+        if (ctx->m.crit[c] != c || ctx->m.cost[c] != 0) return false;
+    return true;
+}
+
 template <int BS, int G>
 void launch_batched_k(dc_ctx *ctx, const Params &p, size_t lds, hipStream_t stream) {
-    hipLaunchKernelGGL((k_topsis_batched<BS, G>), dim3(ctx->I), dim3(BS), lds, stream, p);
+    if (batched_specialised(ctx))
+        hipLaunchKernelGGL((k_topsis_batched<BS, G, kBatchedK>), dim3(ctx->I), dim3(BS), lds, stream, p);
+    else
+        hipLaunchKernelGGL((k_topsis_batched<BS, G, 0>), dim3(ctx->I), dim3(BS), lds, stream, p);
+}
+
+template <int BS, int G>
+int set_lds_batched(dc_ctx *ctx, size_t lds) {
+    return batched_specialised(ctx) ? set_lds(ctx, k_topsis_batched<BS, G, kBatchedK>, lds)
+                                    : set_lds(ctx, k_topsis_batched<BS, G, 0>, lds);
 }
 
 // sh must be a built shape with 1 <= sh.pc <= ctx->pc_batched (callers check)
@@ -698,7 +717,7 @@ int collect(dc_ctx *ctx, DevBatch &b) {
     std::memcpy(b.score.data(), t0 + 2 * b.R, sizeof(float) * b.Ct);
     b.tsb.resize(b.R);
     b.tse.resize(b.R);
-    const long long *ts = reinterpret_cast<const long long *>(b.view.tsb);
+    const long long *ts = b.view.tsb;
     const size_t o_ts = (size_t)(reinterpret_cast<const int *>(ts) - dout) - tail0;
     std::memcpy(b.tsb.data(), t0 + o_ts, sizeof(long long) * b.R);
     std::memcpy(b.tse.data(), t0 + o_ts + 2 * (size_t)b.R, sizeof(long long) * b.R);
@@ -1299,10 +1318,9 @@ int dc_create(const dc_config *cfg, dc_ctx **out) {
         c->pc_batched = (int)std::min<size_t>(kMaxN, (lds_max - fixed) / (8 * (size_t)c->t.nsw));
         c->bshape.pc = c->pc_batched;
         const size_t lb = batched_lds(c, c->pc_batched);
-        if (set_lds(c, k_topsis_batched<256, 1>, lb) || set_lds(c, k_topsis_batched<256, 2>, lb) ||
-            set_lds(c, k_topsis_batched<256, 4>, lb) || set_lds(c, k_topsis_batched<512, 1>, lb) ||
-            set_lds(c, k_topsis_batched<512, 2>, lb) || set_lds(c, k_topsis_batched<512, 4>, lb) ||
-            set_lds(c, k_topsis_batched<1024, 1>, lb) || set_lds(c, k_topsis_batched<1024, 2>, lb)) {
+        if (set_lds_batched<256, 1>(c, lb) || set_lds_batched<256, 2>(c, lb) || set_lds_batched<256, 4>(c, lb) ||
+            set_lds_batched<512, 1>(c, lb) || set_lds_batched<512, 2>(c, lb) || set_lds_batched<512, 4>(c, lb) ||
+            set_lds_batched<1024, 1>(c, lb) || set_lds_batched<1024, 2>(c, lb)) {
             dc_destroy(ctx.release());
             return DC_EDEVICE;
         }

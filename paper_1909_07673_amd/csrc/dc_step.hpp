@@ -41,6 +41,17 @@ struct Topo {
 // integer, far more than the two roundings can move it.
 __device__ __forceinline__ int fdiv(int x, float r) { return static_cast<int>((static_cast<float>(x) + 0.5f) * r); }
 
+// floor(x / d) for 0 <= x < 2^18: an integer division where d is known at
+// compile time (a shift for a power of two), the reciprocal form otherwise.
+__device__ __forceinline__ int div_floor(int x, int d, float r) {
+    if (__builtin_constant_p(d)) return static_cast<int>(static_cast<unsigned>(x) / static_cast<unsigned>(d));
+    return fdiv(x, r);
+}
+
+// Edge switch and pod of server u; aggregation index of candidate c.
+__device__ __forceinline__ int edge_of(const Topo &t, int u) { return div_floor(u, t.h, t.rh); }
+__device__ __forceinline__ int pod_of(const Topo &t, int u) { return div_floor(u, t.hh, t.rhh); }
+
 // Residual state of one data center, structure-of-arrays, N entries each.
 struct State {
     int *cpu, *ram, *npl, *up, *ea, *ac;
@@ -54,6 +65,20 @@ struct Method {
     float w[kMaxCrit];
 };
 
+// A pointer to an array in global memory.  Indexing goes through an
+// address-space-1 pointer, so the access stays a global load or store even
+// where the pointer itself was read back from LDS (a plain pointer would
+// become a flat access there, and every later wait for an LDS result would
+// also wait for the flat access's round trip to memory).
+#define DCS_GLOBAL __attribute__((address_space(1)))
+template <class T>
+struct GPtr {
+    T *p;
+    __host__ __device__ GPtr &operator=(T *q) { p = q; return *this; }
+    __host__ __device__ __forceinline__ operator T *() const { return p; }
+    __device__ __forceinline__ DCS_GLOBAL T &operator[](long long i) const { return ((DCS_GLOBAL T *)p)[i]; }
+};
+
 // Requests of one schedule call, CSR layout.  Container g of request r is
 // coff[r] + i; its placed peers are pj[poff[g]..poff[g+1]) (container index
 // within the request, ascending) with demands pbw[].  Demands are intervals
@@ -61,18 +86,18 @@ struct Method {
 // maxima (equal for fixed demands); cpua, rama, pbwa receive what each
 // container and pair was given, which is what a release gives back.
 struct Batch {
-    const int *coff, *cpu, *ram, *poff, *pj, *pbw;
-    const int *cmax, *rmax, *pbmax;
-    int *cpua, *rama;  // [Ct] allocated CPU and RAM
-    int *pbwa;         // [Pt] allocated bandwidth
-    int *host;      // [Ct] chosen server, -1 until placed
-    float *score;   // [Ct] score of the chosen server
-    int *code;      // [Pt] path choice per peer pair, -1 when co-located
-    int *status;    // [R]  1 accepted (optimistic), 0 rejected
-    int *failat;    // [R]  container without a server, -1
-    const int *iroff;  // [I+1] first request of each instance (batched form)
-    const int *rid;    // [R]  request id (low 31 bits), for trace records
-    long long *tsb, *tse;  // [R] device clock (100 MHz) at the first step's start / the decision
+    GPtr<const int> coff, cpu, ram, poff, pj, pbw;
+    GPtr<const int> cmax, rmax, pbmax;
+    GPtr<int> cpua, rama;  // [Ct] allocated CPU and RAM
+    GPtr<int> pbwa;        // [Pt] allocated bandwidth
+    GPtr<int> host;        // [Ct] chosen server, -1 until placed
+    GPtr<float> score;     // [Ct] score of the chosen server
+    GPtr<int> code;        // [Pt] path choice per peer pair, -1 when co-located
+    GPtr<int> status;      // [R]  1 accepted (optimistic), 0 rejected
+    GPtr<int> failat;      // [R]  container without a server, -1
+    GPtr<const int> iroff; // [I+1] first request of each instance (batched form)
+    GPtr<const int> rid;   // [R]  request id (low 31 bits), for trace records
+    GPtr<long long> tsb, tse;  // [R] device clock (100 MHz) at the first step's start / the decision
 };
 
 // One container step: where it sits in the batch, and its demand.
@@ -208,9 +233,9 @@ __device__ __forceinline__ unsigned wave_umax(unsigned v) {
 // a*h + j (different pods).
 // Link x (0..5) of that path, or nullptr when the path is shorter.
 __device__ __forceinline__ int *path_link(const Topo &t, const State &st, int u, int v, int c, int x) {
-    const int eu = fdiv(u, t.rh), ev = fdiv(v, t.rh), pu = fdiv(u, t.rhh), pv = fdiv(v, t.rhh);
+    const int eu = edge_of(t, u), ev = edge_of(t, v), pu = pod_of(t, u), pv = pod_of(t, v);
     int a = 0, j = 0;
-    if (pu == pv) a = c; else { a = fdiv(c, t.rh); j = c - a * t.h; }
+    if (pu == pv) a = c; else { a = div_floor(c, t.h, t.rh); j = c - a * t.h; }
     switch (x) {
     case 0: return st.up + u;
     case 1: return st.up + v;
@@ -244,7 +269,7 @@ __device__ __forceinline__ unsigned widest_wave(const Topo &t, const State &st, 
     for (int c = lane; c < ncand; c += kWave) {
         int b = base;
         if (eu != ev) {
-            const int a = (pu == pv) ? c : fdiv(c, t.rh);
+            const int a = (pu == pv) ? c : div_floor(c, t.h, t.rh);
             b = min(b, min(st.ea[eu * t.h + a], st.ea[ev * t.h + a]));
             if (pu != pv) {
                 const int j = c - a * t.h;
@@ -286,7 +311,7 @@ __device__ __forceinline__ bool commit_wave(const Topo &t, const State &st, cons
                                             int P, const Smem &sm, const int *pbmax, int lane) {
     const int pmax = lane < P ? pbmax[lane] : 0;
     if (st.cpu[u] < s.cpu || st.ram[u] < s.ram) return false;
-    const int eu = fdiv(u, t.rh), pu = fdiv(u, t.rhh);
+    const int eu = edge_of(t, u), pu = pod_of(t, u);
     int routed = 0, mycode = -1, mine = pmax;   // lane p keeps peer p's path choice and allocation
     bool ok = true;
     for (int p = 0; p < P; ++p) {
@@ -400,8 +425,8 @@ template <int BS>
 __device__ __forceinline__ void table_T(const Topo &t, const State &st, const Smem &sm, int pbeg, int pn) {
     const int tot = pn * t.nsw;
     for (int it = threadIdx.x; it < tot; it += BS) {
-        const int pc = fdiv(it, t.rnsw), ag = it - pc * t.nsw;
-        const int pv = sm.pk[pbeg + pc].y >> 16, pa = fdiv(ag, t.rh);
+        const int pc = div_floor(it, t.nsw, t.rnsw), ag = it - pc * t.nsw;
+        const int pv = sm.pk[pbeg + pc].y >> 16, pa = edge_of(t, ag);
         int val = 0;
         if (pa != pv) {
             const int a = ag - pa * t.h;
@@ -425,9 +450,9 @@ template <int BS>
 __device__ __forceinline__ void table_E(const Topo &t, const State &st, const Smem &sm, int pbeg, int pn) {
     const int tot = pn * t.nsw;
     for (int it = threadIdx.x; it < tot; it += BS) {
-        const int pc = fdiv(it, t.rnsw), eg = it - pc * t.nsw;
+        const int pc = div_floor(it, t.nsw, t.rnsw), eg = it - pc * t.nsw;
         const int ed = sm.pk[pbeg + pc].y;
-        const int ev = ed & 0xffff, pv = ed >> 16, pe = fdiv(eg, t.rh);
+        const int ev = ed & 0xffff, pv = ed >> 16, pe = edge_of(t, eg);
         int val = 0;
         if (eg != ev) {
             const int *x = st.ea + eg * t.h;
@@ -462,7 +487,7 @@ __device__ __forceinline__ void load_peers(const Topo &t, const State &st, const
         const int bw = rv.pbw[p];
         sm.ph[p] = v;
         sm.pbw[p] = rv.pbmax[p];
-        sm.pk[p] = make_int4(v, fdiv(v, t.rh) | (fdiv(v, t.rhh) << 16), bw, st.up[v]);
+        sm.pk[p] = make_int4(v, edge_of(t, v) | (pod_of(t, v) << 16), bw, st.up[v]);
     }
     if (threadIdx.x < 6) sm.misc[M_DH0 + threadIdx.x] = (threadIdx.x & 1) ? -1 : kBig;
     if (LIMITS && P > 0) {
@@ -559,8 +584,8 @@ __device__ void criteria_stage(const Topo &t, const State &st, const Method &m, 
                 const int us = valid[g] ? u : 0;
                 uu[g] = u;
                 up_u[g] = st.up[us];
-                eu[g] = fdiv(us, t.rh);
-                pu[g] = fdiv(us, t.rhh);
+                eu[g] = edge_of(t, us);
+                pu[g] = pod_of(t, us);
                 if (ch == 0) {
                     pbw_acc[g] = up_u[g]; up_acc[g] = 0; hop_acc[g] = 0; oute[g] = 0; outp[g] = 0;
                     int f = (st.cpu[us] >= cpu_i) & (st.ram[us] >= ram_i);
@@ -805,12 +830,12 @@ __device__ bool route_request_end(const Topo &t, const State &st, const Batch &b
     if (threadIdx.x == 0) *lds_ok = 1;
     __syncthreads();
     for (int g = wid; g < s.n; g += NW) {
-        const int u = host(g), eu = fdiv(u, t.rh), pu = fdiv(u, t.rhh);
+        const int u = host(g), eu = edge_of(t, u), pu = pod_of(t, u);
         for (int x = b.poff[s.g0 + g]; x < b.poff[s.g0 + g + 1]; ++x) {
             const int v = host(b.pj[x]);
             int c = -1;
             if (v != u) {
-                const unsigned best = widest_wave(t, st, u, v, eu, pu, fdiv(v, t.rh), fdiv(v, t.rhh), lane);
+                const unsigned best = widest_wave(t, st, u, v, eu, pu, edge_of(t, v), pod_of(t, v), lane);
                 c = 1023 - static_cast<int>(best & 1023u);
             }
             if (lane == 0) {
