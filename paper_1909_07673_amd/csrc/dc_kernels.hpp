@@ -631,29 +631,17 @@ __device__ __forceinline__ Topo topo_of(const Topo &t) {
     return Topo{K, h, hh, K * hh, K * h, 1.0f / h, 1.0f / hh, 1.0f / (K * h)};
 }
 
-template <int K>
-__device__ __forceinline__ Method method_of(const Method &m) {
-    if (K == 0) return m;
-    Method d = m;
-    d.method = 0;
-    d.nc = 4;
-    for (int c = 0; c < kMaxCrit; ++c) {
-        d.crit[c] = c < 4 ? c : 0;
-        d.cost[c] = 0;
-    }
-    return d;
-}
-
 template <int BS, int G, int K>
 __global__ __launch_bounds__(BS) void k_topsis_batched(Params p) {
     extern __shared__ __align__(16) char dsm[];
     const int inst = blockIdx.x;
     const Topo t = topo_of<K>(p.t);
-    const Method m = method_of<K>(p.m);
+    const Method &m = p.m;
+    constexpr int CS = K ? 4 : 0;
     const int N = t.N;
     Smem sm = carve(dsm, p.pc_cap, t.nsw);
     int *xs = lds_after_tables(dsm, p.pc_cap, t.nsw);
-    int *ls = xs + (size_t)xs_rows(m.nc) * N;
+    int *ls = xs + (size_t)xs_rows(crit_count<CS>(m)) * N;
     int *rq_host = ls + 6 * (size_t)N;
     int *rq_cpu = rq_host + kMaxN, *rq_ram = rq_cpu + kMaxN, *rq_poff = rq_ram + kMaxN;
     int *rq_pj = rq_poff + kMaxN + 4, *rq_pbw = rq_pj + kMaxPairs, *rq_pbmax = rq_pbw + kMaxPairs;
@@ -689,7 +677,7 @@ __global__ __launch_bounds__(BS) void k_topsis_batched(Params p) {
             const StepIn s{r, i, n, g0, g0 + i, pb + q0, rq_poff[i + 1] - q0, rq_cpu[i], rq_ram[i],
                            rq_cmax[i], rq_rmax[i]};
             const ReqView rv{rq_pj + q0, rq_pbw + q0, rq_host, rq_host, rq_pbmax + q0};
-            if (!topsis_step<BS, G, true>(t, st, m, lb, sm, xs, p.pc_cap, p.tr, inst, s, rv)) break;
+            if (!topsis_step<BS, G, true, CS>(t, st, m, lb, sm, xs, p.pc_cap, p.tr, inst, s, rv)) break;
         }
         __syncthreads();
     }

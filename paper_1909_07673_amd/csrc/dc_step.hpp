@@ -48,7 +48,7 @@ __device__ __forceinline__ int div_floor(int x, int d, float r) {
     return fdiv(x, r);
 }
 
-// Edge switch and pod of server u; aggregation index of candidate c.
+// Edge switch and pod of server u.
 __device__ __forceinline__ int edge_of(const Topo &t, int u) { return div_floor(u, t.h, t.rh); }
 __device__ __forceinline__ int pod_of(const Topo &t, int u) { return div_floor(u, t.hh, t.rhh); }
 
@@ -64,6 +64,13 @@ struct Method {
     int cost[kMaxCrit];
     float w[kMaxCrit];
 };
+
+// Criteria of a step: CS = 0 takes them from the method; CS = 4 is the
+// default list (CPU, RAM, active, path bandwidth; all benefits), fixed at
+// compile time.
+template <int CS> __device__ __forceinline__ int crit_count(const Method &m) { return CS ? CS : m.nc; }
+template <int CS> __device__ __forceinline__ int crit_at(const Method &m, int c) { return CS ? c : m.crit[c]; }
+template <int CS> __device__ __forceinline__ int crit_cost(const Method &m, int c) { return CS ? 0 : m.cost[c]; }
 
 // A pointer to an array in global memory.  Indexing goes through an
 // address-space-1 pointer, so the access stays a global load or store even
@@ -375,7 +382,7 @@ __device__ __forceinline__ bool commit_wave(const Topo &t, const State &st, cons
 // given, the placed count and the allocation of every routed peer pair.
 // Block-wide, with atomics.
 template <int BS>
-__device__ void give_back(const Topo &t, const State &st, const Batch &b, int r, int upto) {
+__device__ __forceinline__ void give_back(const Topo &t, const State &st, const Batch &b, int r, int upto) {
     const int g0 = b.coff[r];
     const int p_beg = b.poff[g0], p_end = b.poff[g0 + upto];
     for (int q = p_beg + threadIdx.x; q < p_end; q += BS) {
@@ -402,7 +409,7 @@ __device__ void give_back(const Topo &t, const State &st, const Batch &b, int r,
 // [0, upto) (all or nothing) and mark the request rejected.  host[] keeps
 // the servers the undone containers had been given (attempt record).
 template <int BS>
-__device__ void rollback_request(const Topo &t, const State &st, const Batch &b, int r, int upto) {
+__device__ __forceinline__ void rollback_request(const Topo &t, const State &st, const Batch &b, int r, int upto) {
     give_back<BS>(t, st, b, r, upto);
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -546,10 +553,10 @@ __device__ __forceinline__ void peer_deficits(const Smem &sm, int P) {
 // the demand of the peers outside them, and the peer-side deficits.
 // With nwg > 1, workgroup wg of nwg takes every nwg-th group of G * BS
 // servers (the other workgroups build the same peer tables for theirs).
-template <int BS, bool STATS, int G = host_group(BS)>
-__device__ void criteria_stage(const Topo &t, const State &st, const Method &m, const Smem &sm, int *xs,
+template <int BS, bool STATS, int G = host_group(BS), int CS = 0>
+__device__ __forceinline__ void criteria_stage(const Topo &t, const State &st, const Method &m, const Smem &sm, int *xs,
                                int cpu_i, int ram_i, int P, int pc_cap, int wg = 0, int nwg = 1) {
-    const int N = t.N, nc = m.nc;
+    const int N = t.N, nc = crit_count<CS>(m);
     const int nch = P == 0 ? 1 : (P + pc_cap - 1) / pc_cap;
     unsigned long long s2[kMaxCrit];
     int mx[kMaxCrit], mn[kMaxCrit];
@@ -644,7 +651,7 @@ __device__ void criteria_stage(const Topo &t, const State &st, const Method &m, 
                 for (int c = 0; c < kMaxCrit; ++c) {
                     if (c >= nc) break;
                     int x;
-                    switch (m.crit[c]) {
+                    switch (crit_at<CS>(m, c)) {
                     case CRIT_CPU: x = st.cpu[u]; break;
                     case CRIT_RAM: x = st.ram[u]; break;
                     case CRIT_ACTIVE: x = st.npl[u] > 0 ? 1 : 0; break;
@@ -745,13 +752,13 @@ __device__ __forceinline__ float topsis_close(int nc, Get get, const float *q, c
 // slots; every thread reads them after the barrier.  Same values as the
 // per-wave path of criteria_stage + finish_stats, with 5 wave reductions per
 // criterion instead of 5 per criterion in every wave.
-template <int BS>
+template <int BS, int CS = 0>
 __device__ __forceinline__ void column_factors_lds(const Smem &sm, const Method &m, const int *xs, int N, float *q,
                                                    float *ap, float *am) {
     constexpr int NW = BS / kWave;
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     float *f = reinterpret_cast<float *>(sm.wst);
-    for (int c = wid; c < m.nc; c += NW) {
+    for (int c = wid; c < crit_count<CS>(m); c += NW) {
         const int *col = xs + static_cast<size_t>(c) * N;
         unsigned long long s2 = 0;
         int hi = -kBig - 1, lo = kBig;
@@ -772,15 +779,15 @@ __device__ __forceinline__ void column_factors_lds(const Smem &sm, const Method 
                                          (static_cast<unsigned long long>(c1) << 17) +
                                          (static_cast<unsigned long long>(c2) << 34);
             f[c] = a ? (m.w[c] * m.w[c]) / static_cast<float>(a) : 0.0f;
-            f[kMaxCrit + c] = static_cast<float>(m.cost[c] ? lo : hi);
-            f[2 * kMaxCrit + c] = static_cast<float>(m.cost[c] ? hi : lo);
+            f[kMaxCrit + c] = static_cast<float>(crit_cost<CS>(m, c) ? lo : hi);
+            f[2 * kMaxCrit + c] = static_cast<float>(crit_cost<CS>(m, c) ? hi : lo);
         }
     }
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < kMaxCrit; ++c) {
         q[c] = ap[c] = am[c] = 0.f;
-        if (c >= m.nc) continue;
+        if (c >= crit_count<CS>(m)) continue;
         q[c] = f[c];
         ap[c] = f[kMaxCrit + c];
         am[c] = f[2 * kMaxCrit + c];
@@ -818,7 +825,7 @@ __device__ __forceinline__ int trace_slot(const Trace &tr, int inst, int rid, in
 // g (u for the unit just placed).  Returns true when the request was
 // accepted.
 template <int BS, class HostFn>
-__device__ bool route_request_end(const Topo &t, const State &st, const Batch &b, int *lds_ok, const StepIn &s,
+__device__ __forceinline__ bool route_request_end(const Topo &t, const State &st, const Batch &b, int *lds_ok, const StepIn &s,
                                   HostFn host) {
     constexpr int NW = BS / kWave;
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -907,7 +914,7 @@ __device__ bool route_request_end(const Topo &t, const State &st, const Batch &b
 // thread rescans its servers, and the argmax repeats.  Rolls the request
 // back when no server is left.  Returns true when the container was placed.
 template <int BS, int G, class KeyFn>
-__device__ bool select_commit(const Topo &t, const State &st, const Batch &b, const Smem &sm, int *feas_row,
+__device__ __forceinline__ bool select_commit(const Topo &t, const State &st, const Batch &b, const Smem &sm, int *feas_row,
                               const StepIn &s, const ReqView &rv, int m_route_end, KeyFn key_of) {
     const int lane = threadIdx.x & (kWave - 1);
     auto scan = [&]() {
@@ -978,19 +985,19 @@ __device__ bool select_commit(const Topo &t, const State &st, const Batch &b, co
 // false when the request was rejected at this container.
 // XS_LDS: the criteria rows xs are in LDS, so the column statistics are
 // taken from them afterwards by one wave per criterion.
-template <int BS, int G = host_group(BS), bool XS_LDS = false>
-__device__ bool topsis_step(const Topo &t, const State &st, const Method &m, const Batch &b, const Smem &sm,
+template <int BS, int G = host_group(BS), bool XS_LDS = false, int CS = 0>
+__device__ __forceinline__ bool topsis_step(const Topo &t, const State &st, const Method &m, const Batch &b, const Smem &sm,
                             int *xs, int pc_cap, const Trace &tr, int inst, const StepIn &s, const ReqView &rv) {
     if (s.i == 0 && threadIdx.x == 0) b.tsb[s.r] = dev_clock();
     if (threadIdx.x == 0) sm.misc[M_TRACE] = tr.stride > 0 ? trace_slot(tr, inst, b.rid[s.r], s.i) : -1;
     load_peers<BS, true>(t, st, rv, sm, s.P);
-    const int nc = m.nc, N = t.N;
-    criteria_stage<BS, !XS_LDS, G>(t, st, m, sm, xs, s.cpu, s.ram, s.P, pc_cap);
+    const int nc = crit_count<CS>(m), N = t.N;
+    criteria_stage<BS, !XS_LDS, G, CS>(t, st, m, sm, xs, s.cpu, s.ram, s.P, pc_cap);
     __syncthreads();
 
     float q[kMaxCrit], ap[kMaxCrit], am[kMaxCrit];
     if (XS_LDS) {
-        column_factors_lds<BS>(sm, m, xs, N, q, ap, am);
+        column_factors_lds<BS, CS>(sm, m, xs, N, q, ap, am);
     } else {
         unsigned long long s2[kMaxCrit];
         int mx[kMaxCrit], mn[kMaxCrit];
@@ -1001,8 +1008,8 @@ __device__ bool topsis_step(const Topo &t, const State &st, const Method &m, con
             if (c >= nc) continue;
             const unsigned long long a = s2[c];
             q[c] = a ? (m.w[c] * m.w[c]) / static_cast<float>(a) : 0.0f;
-            ap[c] = static_cast<float>(m.cost[c] ? mn[c] : mx[c]);
-            am[c] = static_cast<float>(m.cost[c] ? mx[c] : mn[c]);
+            ap[c] = static_cast<float>(crit_cost<CS>(m, c) ? mn[c] : mx[c]);
+            am[c] = static_cast<float>(crit_cost<CS>(m, c) ? mx[c] : mn[c]);
         }
     }
     auto closeness = [&](int u) -> float {
