@@ -123,11 +123,11 @@ __device__ __forceinline__ int block_sum(int v, int *slot) {
 // One container step on the pod of this workgroup (w = blockIdx.x).
 // rv.hosts_out, when given, is this workgroup's LDS copy of the request's
 // servers.  Returns false when the request was rejected at this container.
-template <int BS>
-__device__ bool grid_topsis_step(const Topo &t, const State &st, const Method &m, const Batch &b, const GSmem &sm,
+template <int BS, int CS = 0>
+__device__ __forceinline__ bool grid_topsis_step(const Topo &t, const State &st, const Method &m, const Batch &b, const GSmem &sm,
                                  const GridCtl &g, long long timeout, const StepIn &s, const ReqView &rv,
                                  const Trace &tr) {
-    const int w = blockIdx.x, G = gridDim.x, h = t.h, hh = t.hh, nc = m.nc;
+    const int w = blockIdx.x, G = gridDim.x, h = t.h, hh = t.hh, nc = crit_count<CS>(m);
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     const int P = s.P, ubase = w * hh;
     int *xs = sm.xs;
@@ -202,7 +202,7 @@ __device__ bool grid_topsis_step(const Topo &t, const State &st, const Method &m
         for (int c = 0; c < kMaxCrit; ++c) {
             if (c >= nc) break;
             int v;
-            switch (m.crit[c]) {
+            switch (crit_at<CS>(m, c)) {
             case CRIT_CPU: v = st.cpu[u]; break;
             case CRIT_RAM: v = st.ram[u]; break;
             case CRIT_ACTIVE: v = st.npl[u] > 0 ? 1 : 0; break;
@@ -291,8 +291,8 @@ __device__ bool grid_topsis_step(const Topo &t, const State &st, const Method &m
         q[c] = ap[c] = am[c] = 0.f;
         if (c >= nc) continue;
         q[c] = S2[c] ? (m.w[c] * m.w[c]) / static_cast<float>(S2[c]) : 0.0f;
-        ap[c] = static_cast<float>(m.cost[c] ? MN[c] : MX[c]);
-        am[c] = static_cast<float>(m.cost[c] ? MX[c] : MN[c]);
+        ap[c] = static_cast<float>(crit_cost<CS>(m, c) ? MN[c] : MX[c]);
+        am[c] = static_cast<float>(crit_cost<CS>(m, c) ? MX[c] : MN[c]);
     }
     auto key_of = [&](int x) -> unsigned long long {
         const int u = ubase + x;
@@ -404,23 +404,29 @@ __device__ __forceinline__ int *grid_req_lds(char *dsm, int h, int hh, int nc) {
 }
 
 // Plain form, large data centers: one cooperative launch per container step.
-template <int BS>
+// K > 0: k = K fat-trees on the four default criteria, as compile-time
+// constants (as in the batched kernel); K = 0: any.
+template <int BS, int K>
 __global__ __launch_bounds__(BS) void k_topsis_grid(Params p, GridCtl g, long long timeout) {
     extern __shared__ __align__(16) char dsm[];
     if (p.b.status[p.s.r] == 0) return;        // every workgroup leaves: no barrier is reached
-    const GSmem sm = gcarve(dsm, p.t.h, p.t.hh, p.m.nc);
-    grid_topsis_step<BS>(p.t, p.st, p.m, p.b, sm, g, timeout, p.s, plain_view(p), p.tr);
+    constexpr int CS = K ? 4 : 0;
+    const Topo t = topo_of<K>(p.t);
+    const GSmem sm = gcarve(dsm, t.h, t.hh, crit_count<CS>(p.m));
+    grid_topsis_step<BS, CS>(t, p.st, p.m, p.b, sm, g, timeout, p.s, plain_view(p), p.tr);
 }
 
 // Serving form, large data centers: the persistent loop of k_serve run by
 // one cooperative workgroup per pod.  Workgroup 0 polls the command ring
 // and publishes each command to the others through a grid barrier; every
 // workgroup keeps its own LDS copy of the request.
-template <int BS>
+template <int BS, int K>
 __global__ __launch_bounds__(BS) void k_serve_grid(Params p, ServeArgs a, GridCtl g, long long timeout) {
     extern __shared__ __align__(16) char dsm[];
-    const GSmem sm = gcarve(dsm, p.t.h, p.t.hh, p.m.nc);
-    int *rq_host = grid_req_lds(dsm, p.t.h, p.t.hh, p.m.nc);
+    constexpr int CS = K ? 4 : 0;
+    const Topo t = topo_of<K>(p.t);
+    const GSmem sm = gcarve(dsm, t.h, t.hh, crit_count<CS>(p.m));
+    int *rq_host = grid_req_lds(dsm, t.h, t.hh, crit_count<CS>(p.m));
     int *rq_cpu = rq_host + kMaxN, *rq_ram = rq_cpu + kMaxN, *rq_poff = rq_ram + kMaxN;
     int *rq_pj = rq_poff + kMaxN + 4, *rq_pbw = rq_pj + kMaxPairs, *rq_pbmax = rq_pbw + kMaxPairs;
     int *rq_cmax = rq_pbmax + kMaxPairs, *rq_rmax = rq_cmax + kMaxN;
@@ -496,13 +502,13 @@ __global__ __launch_bounds__(BS) void k_serve_grid(Params p, ServeArgs a, GridCt
                 const int q0 = rq_poff[i];
                 const StepIn s{0, i, n, 0, i, q0, rq_poff[i + 1] - q0, rq_cpu[i], rq_ram[i], rq_cmax[i], rq_rmax[i]};
                 const ReqView rv{rq_pj + q0, rq_pbw + q0, rq_host, rq_host, rq_pbmax + q0};
-                if (!grid_topsis_step<BS>(p.t, p.st, p.m, b, sm, g, timeout, s, rv, p.tr)) {
+                if (!grid_topsis_step<BS, CS>(t, p.st, p.m, b, sm, g, timeout, s, rv, p.tr)) {
                     fault = __hip_atomic_load(g.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
                     break;
                 }
             }
         } else if (lead) {
-            give_back<BS>(p.t, p.st, b, 0, n);       // departure of an accepted request
+            give_back<BS>(t, p.st, b, 0, n);         // departure of an accepted request
         }
         if (fault) break;
         if (lead) {

@@ -624,13 +624,6 @@ __host__ __device__ inline size_t req_lds_ints() { return 6 * (size_t)kMaxN + 4 
 // topology and the criterion list are compile-time constants: index
 // arithmetic becomes shifts and the per-criterion selection folds away.
 // Same arithmetic as K = 0 (any k and criteria), bit-identical results.
-template <int K>
-__device__ __forceinline__ Topo topo_of(const Topo &t) {
-    if (K == 0) return t;
-    constexpr int h = K / 2, hh = h * h;
-    return Topo{K, h, hh, K * hh, K * h, 1.0f / h, 1.0f / hh, 1.0f / (K * h)};
-}
-
 template <int BS, int G, int K>
 __global__ __launch_bounds__(BS) void k_topsis_batched(Params p) {
     extern __shared__ __align__(16) char dsm[];

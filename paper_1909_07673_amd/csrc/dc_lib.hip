@@ -542,6 +542,28 @@ int upload_pending(dc_ctx *ctx) {
     return DC_OK;
 }
 
+// Whether the context runs k = K fat-trees on the four default criteria
+// (CPU, RAM, active, path bandwidth; all benefits, TOPSIS), for which
+// kernels are also compiled with these as compile-time constants.
+bool specialised(const dc_ctx *ctx, int K) {
+    if (ctx->t.k != K || ctx->m.method != DC_TOPSIS || ctx->m.nc != 4) return false;
+    for (int c = 0; c < 4; ++c)
+        if (ctx->m.crit[c] != c || ctx->m.cost[c] != 0) return false;
+    return true;
+}
+
+// The cooperative kernels compiled for k = 48 (the large data center of the
+// serving form) on the default criteria, or for any case.
+constexpr int kGridK = 48;
+const void *grid_step_kernel(const dc_ctx *ctx) {
+    return specialised(ctx, kGridK) ? reinterpret_cast<const void *>(k_topsis_grid<kGridBlock, kGridK>)
+                                    : reinterpret_cast<const void *>(k_topsis_grid<kGridBlock, 0>);
+}
+const void *grid_serve_kernel(const dc_ctx *ctx) {
+    return specialised(ctx, kGridK) ? reinterpret_cast<const void *>(k_serve_grid<kGridBlock, kGridK>)
+                                    : reinterpret_cast<const void *>(k_serve_grid<kGridBlock, 0>);
+}
+
 template <int BS>
 void launch_plain_step(dc_ctx *ctx, const Params &p) {
     if (ctx->use_grid) {
@@ -549,8 +571,8 @@ void launch_plain_step(dc_ctx *ctx, const Params &p) {
         GridCtl g = ctx->grid;
         long long timeout = ctx->grid_timeout;
         void *args[] = {&pp, &g, &timeout};
-        const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_topsis_grid<kGridBlock>),
-                                                        dim3(ctx->t.k), dim3(kGridBlock), args, ctx->lds_grid, ctx->stream);
+        const hipError_t e = hipLaunchCooperativeKernel(grid_step_kernel(ctx), dim3(ctx->t.k), dim3(kGridBlock), args,
+                                                        ctx->lds_grid, ctx->stream);
         if (e != hipSuccess && ctx->launch_err == hipSuccess) ctx->launch_err = e;
         ctx->last_launches += 1;
         return;
@@ -622,12 +644,7 @@ size_t batched_lds(const dc_ctx *ctx, int pc) {
 // The batched kernel compiled for k = 16 fat-trees scored on the four
 // default criteria (the constants fold into the kernel), or for any case.
 constexpr int kBatchedK = 16;
-bool batched_specialised(const dc_ctx *ctx) {
-    if (ctx->t.k != kBatchedK || ctx->m.nc != 4) return false;
-    for (int c = 0; c < 4; ++c)
-        if (ctx->m.crit[c] != c || ctx->m.cost[c] != 0) return false;
-    return true;
-}
+bool batched_specialised(const dc_ctx *ctx) { return specialised(ctx, kBatchedK); }
 
 template <int BS, int G>
 void launch_batched_k(dc_ctx *ctx, const Params &p, size_t lds, hipStream_t stream) {
@@ -772,7 +789,10 @@ int grid_init(dc_ctx *ctx) {
     ctx->lds_grid = gsmem_bytes(h, ctx->t.hh, ctx->m.nc);
     const size_t serve_lds = align4(ctx->lds_grid / sizeof(int)) * sizeof(int) + req_lds_ints() * sizeof(int);
     if (serve_lds > 159 * 1024) return DC_EINVAL;
-    if (set_lds(ctx, k_topsis_grid<kGridBlock>, ctx->lds_grid) || set_lds(ctx, k_serve_grid<kGridBlock>, serve_lds))
+    if (hipFuncSetAttribute(grid_step_kernel(ctx), hipFuncAttributeMaxDynamicSharedMemorySize, (int)ctx->lds_grid) !=
+            hipSuccess ||
+        hipFuncSetAttribute(grid_serve_kernel(ctx), hipFuncAttributeMaxDynamicSharedMemorySize, (int)serve_lds) !=
+            hipSuccess)
         return DC_EDEVICE;
     ctx->use_grid = true;
     return DC_OK;
@@ -843,8 +863,8 @@ int serve_ensure_running(dc_ctx *ctx) {
         long long timeout = ctx->grid_timeout;
         void *args[] = {&p, &a, &g, &timeout};
         const size_t lds = align4(ctx->lds_grid / sizeof(int)) * sizeof(int) + req_lds_ints() * sizeof(int);
-        HIPCHK(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_serve_grid<kGridBlock>), dim3(ctx->t.k),
-                                          dim3(kGridBlock), args, lds, ctx->stream));
+        HIPCHK(hipLaunchCooperativeKernel(grid_serve_kernel(ctx), dim3(ctx->t.k), dim3(kGridBlock), args, lds,
+                                          ctx->stream));
     } else if (sv.bs == 256) {
         hipLaunchKernelGGL((k_serve<256>), dim3(1), dim3(256), sv.lds, ctx->stream, p, a);
     } else {

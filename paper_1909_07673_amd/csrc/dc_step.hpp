@@ -48,6 +48,15 @@ __device__ __forceinline__ int div_floor(int x, int d, float r) {
     return fdiv(x, r);
 }
 
+// The topology of a k = K fat-tree as compile-time constants (K = 0: the
+// run-time values in t).
+template <int K>
+__device__ __forceinline__ Topo topo_of(const Topo &t) {
+    if (K == 0) return t;
+    constexpr int h = K / 2, hh = h * h;
+    return Topo{K, h, hh, K * hh, K * h, 1.0f / h, 1.0f / hh, 1.0f / (K * h)};
+}
+
 // Edge switch and pod of server u.
 __device__ __forceinline__ int edge_of(const Topo &t, int u) { return div_floor(u, t.h, t.rh); }
 __device__ __forceinline__ int pod_of(const Topo &t, int u) { return div_floor(u, t.hh, t.rhh); }
