@@ -22,11 +22,84 @@ struct GridCtl {
     int *err;                     // set when a barrier wait timed out
     int *part;                    // [kStatFields][G] per-workgroup column statistics
     int *cap;                     // [2][G*h]: summed residuals per edge switch, then [G] per pod
-    unsigned long long *keys;     // [G] per-workgroup best key
-    int *flag;                    // [kGridFlags]: commit result, trace slot, command buffers
+    unsigned long long *kslot;    // [2][G] per-workgroup best key of a selection round, tagged
+    unsigned long long *rflag;    // outcome of a selection round's commit, tagged
+    unsigned *round;              // selection rounds so far (kept across launches)
+    int *flag;                    // [kGridFlags]: trace slot, command buffers
 };
 
-// flag[0]: commit result of the current attempt; flag[7]: trace slot of the
+// Selection rounds.  Round r of the argmax and commit needs no grid barrier:
+// each workgroup publishes its best key in its own slot of set r & 1 as one
+// 64-bit word, tagged with r, which a wave of every workgroup polls until all
+// slots carry r (the payload is the word itself, so no fence is needed);
+// workgroup 0 then commits and publishes the outcome tagged with r (release),
+// which the others poll for (acquire).  A workgroup publishes round r + 2 in
+// the same slot only after the outcome of round r + 1, which workgroup 0
+// gives only after reading every slot of round r + 1, so nothing is
+// overwritten before every workgroup has read it.  Keys are packed as
+// (score bits + 1) << 17 | (2^17 - 1 - server) (servers below 2^17), the tag
+// in bits 47..63; tags never are 0, which the slots hold initially.
+constexpr int kRoundTagShift = 47;
+constexpr unsigned long long kRoundPayload = (1ull << kRoundTagShift) - 1;
+__device__ __forceinline__ unsigned long long round_tag(unsigned r) {
+    return static_cast<unsigned long long>((r & 0xffffu) | 0x10000u) << kRoundTagShift;
+}
+__device__ __forceinline__ unsigned long long round_key(unsigned long long kb) {
+    if (!kb) return 0ull;
+    const unsigned u = ~static_cast<unsigned>(kb);
+    return ((kb >> 32) << 17) | (0x1ffffu - u);
+}
+
+// Wave: waits until the G slots of round r all carry its tag and returns the
+// largest payload, or sets bad when the wait timed out or a workgroup
+// reported an error.
+__device__ __forceinline__ unsigned long long round_max(const GridCtl &g, unsigned r, long long timeout,
+                                                        bool &bad) {
+    const int lane = threadIdx.x & (kWave - 1), G = gridDim.x;
+    const unsigned long long *sl = g.kslot + (r & 1) * G, tag = round_tag(r);
+    const long long t0 = dev_clock();
+    for (;;) {
+        bool ok = true;
+        unsigned long long m = 0;
+        for (int x = lane; x < G; x += kWave) {
+            const unsigned long long v = __hip_atomic_load(sl + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok &= (v & ~kRoundPayload) == tag;
+            const unsigned long long pv = v & kRoundPayload;
+            m = pv > m ? pv : m;
+        }
+        if (__all(ok)) {
+            const unsigned hiw = wave_umax(static_cast<unsigned>(m >> 32));
+            const unsigned low = wave_umax(static_cast<unsigned>(m >> 32) == hiw ? static_cast<unsigned>(m) : 0u);
+            return (static_cast<unsigned long long>(hiw) << 32) | low;
+        }
+        if (__hip_atomic_load(g.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || dev_clock() - t0 > timeout) {
+            if (lane == 0) __hip_atomic_store(g.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            bad = true;
+            return 0ull;
+        }
+    }
+}
+
+// Thread: waits for workgroup 0's outcome of round r; -1 when the wait
+// timed out or a workgroup reported an error.
+__device__ __forceinline__ int round_outcome(const GridCtl &g, unsigned r, long long timeout) {
+    const unsigned long long tag = round_tag(r);
+    const long long t0 = dev_clock();
+    for (;;) {
+        const unsigned long long v = __hip_atomic_load(g.rflag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((v & ~kRoundPayload) == tag) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            return static_cast<int>(v & 3u);
+        }
+        if (__hip_atomic_load(g.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || dev_clock() - t0 > timeout) {
+            __hip_atomic_store(g.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return -1;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// flag[7]: trace slot of the
 // step; flag[8 + 8 * (pos & 1) ...]: the command at ring position pos,
 // double-buffered so that the leader can publish command pos + 1 while a
 // slower workgroup still reads command pos.
@@ -124,9 +197,9 @@ __device__ __forceinline__ int block_sum(int v, int *slot) {
 // rv.hosts_out, when given, is this workgroup's LDS copy of the request's
 // servers.  Returns false when the request was rejected at this container.
 template <int BS, int CS = 0>
-__device__ __forceinline__ bool grid_topsis_step(const Topo &t, const State &st, const Method &m, const Batch &b, const GSmem &sm,
-                                 const GridCtl &g, long long timeout, const StepIn &s, const ReqView &rv,
-                                 const Trace &tr) {
+__device__ __forceinline__ bool grid_topsis_step(const Topo &t, const State &st, const Method &m, const Batch &b,
+                                                 const GSmem &sm, const GridCtl &g, long long timeout, const StepIn &s,
+                                                 const ReqView &rv, const Trace &tr, unsigned &rnd) {
     const int w = blockIdx.x, G = gridDim.x, h = t.h, hh = t.hh, nc = crit_count<CS>(m);
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     const int P = s.P, ubase = w * hh;
@@ -305,6 +378,7 @@ __device__ __forceinline__ bool grid_topsis_step(const Topo &t, const State &st,
         if (!f) return 0ull;
         return score_key(topsis_close(nc, [&](int c) { return xs[c * hh + x]; }, q, ap, am), u);
     };
+    // the workgroup's best key (largest packed key) into LDS slot 0..1
     auto wg_best = [&]() {
         unsigned long long kb = 0;
         for (int x = threadIdx.x; x < hh; x += BS) {
@@ -325,7 +399,7 @@ __device__ __forceinline__ bool grid_topsis_step(const Topo &t, const State &st,
                                              static_cast<unsigned>(sm.wst[kMaxWaves + x]);
                 best = k > best ? k : best;
             }
-            g.keys[w] = best;
+            *reinterpret_cast<unsigned long long *>(sm.misc + M_KEY) = round_key(best);
         }
     };
     const int slot = g.flag[7];
@@ -334,25 +408,30 @@ __device__ __forceinline__ bool grid_topsis_step(const Topo &t, const State &st,
             tr.scores[static_cast<size_t>(slot) * t.N + ubase + x] =
                 topsis_close(nc, [&](int c) { return xs[c * hh + x]; }, q, ap, am);
     wg_best();
-    // ---- E: global argmax, commit by workgroup 0, retries
+    // ---- E: selection rounds (global argmax, commit by workgroup 0, retries)
     for (;;) {
-        if (!grid_sync(g, sm.misc + M_OK, timeout)) return false;             // barrier 2
-        unsigned long long kb = 0;
-        for (int x = lane; x < G; x += kWave) {
-            const unsigned long long k = g.keys[x];
-            kb = k > kb ? k : kb;
+        const unsigned r = rnd++;
+        if (threadIdx.x == 0)
+            __hip_atomic_store(g.kslot + (r & 1) * G + w,
+                               round_tag(r) | *reinterpret_cast<const unsigned long long *>(sm.misc + M_KEY),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x < kWave) {
+            bool bad = false;
+            const unsigned long long kb = round_max(g, r, timeout, bad);
+            if (lane == 0) {
+                *reinterpret_cast<unsigned long long *>(sm.wst + 2 * kMaxWaves) = kb;
+                sm.misc[M_OK] = bad;
+            }
         }
-        {
-            const unsigned hiw = wave_umax(static_cast<unsigned>(kb >> 32));
-            const unsigned low = wave_umax(static_cast<unsigned>(kb >> 32) == hiw ? static_cast<unsigned>(kb) : 0u);
-            kb = (static_cast<unsigned long long>(hiw) << 32) | low;
-        }
+        __syncthreads();
+        if (sm.misc[M_OK]) return false;
+        const unsigned long long kb = *reinterpret_cast<const unsigned long long *>(sm.wst + 2 * kMaxWaves);
         if (kb == 0) {                                                        // no server left
             if (w == 0) rollback_request<BS>(t, st, b, s.r, s.i);
             grid_sync(g, sm.misc + M_OK, timeout);
             return false;
         }
-        const int u = static_cast<int>(~static_cast<unsigned>(kb & 0xffffffffu));
+        const int u = static_cast<int>(0x1ffffu - static_cast<unsigned>(kb & 0x1ffffu));
         if (w == 0) {
             // workgroup 0 commits: 1 placed, 0 retry with the next server,
             // 2 request rejected when its links were routed at its end
@@ -366,7 +445,7 @@ __device__ __forceinline__ bool grid_topsis_step(const Topo &t, const State &st,
                     sm.misc[M_ROUTE + 1] = ok;
                     if (ok) {
                         b.host[s.g] = u;
-                        b.score[s.g] = __uint_as_float(static_cast<unsigned>(kb >> 32) - 1u);
+                        b.score[s.g] = __uint_as_float(static_cast<unsigned>(kb >> 17) - 1u);
                         if (s.i == s.n - 1) b.tse[s.r] = dev_clock();
                     }
                 }
@@ -376,11 +455,18 @@ __device__ __forceinline__ bool grid_topsis_step(const Topo &t, const State &st,
             if (res && m.route_end && s.i == s.n - 1)
                 res = route_request_end<BS>(t, st, b, sm.misc + M_ROUTE, s,
                                             [&](int q) { return q == s.i ? u : rv.hosts[q]; }) ? 1 : 2;
-            if (threadIdx.x == 0) __hip_atomic_store(g.flag, res, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                __hip_atomic_store(g.rflag, round_tag(r) | static_cast<unsigned>(res), __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                sm.misc[M_RES] = res;
+            }
+        } else if (threadIdx.x == 0) {
+            sm.misc[M_RES] = round_outcome(g, r, timeout);
         }
-        if (!grid_sync(g, sm.misc + M_OK, timeout)) return false;             // barrier 3
-        const int ok = __hip_atomic_load(g.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (ok == 2) return false;
+        __syncthreads();
+        const int ok = sm.misc[M_RES];
+        if (ok < 0 || ok == 2) return false;
         if (ok) {
             if (rv.hosts_out && threadIdx.x == 0) rv.hosts_out[s.i] = u;
             __syncthreads();
@@ -391,6 +477,7 @@ __device__ __forceinline__ bool grid_topsis_step(const Topo &t, const State &st,
             __syncthreads();
             wg_best();
         }
+        __syncthreads();
     }
 }
 
@@ -413,7 +500,9 @@ __global__ __launch_bounds__(BS) void k_topsis_grid(Params p, GridCtl g, long lo
     constexpr int CS = K ? 4 : 0;
     const Topo t = topo_of<K>(p.t);
     const GSmem sm = gcarve(dsm, t.h, t.hh, crit_count<CS>(p.m));
-    grid_topsis_step<BS, CS>(t, p.st, p.m, p.b, sm, g, timeout, p.s, plain_view(p), p.tr);
+    unsigned rnd = __hip_atomic_load(g.round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    grid_topsis_step<BS, CS>(t, p.st, p.m, p.b, sm, g, timeout, p.s, plain_view(p), p.tr, rnd);
+    if (blockIdx.x == 0 && threadIdx.x == 0) __hip_atomic_store(g.round, rnd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Serving form, large data centers: the persistent loop of k_serve run by
@@ -432,6 +521,7 @@ __global__ __launch_bounds__(BS) void k_serve_grid(Params p, ServeArgs a, GridCt
     int *rq_cmax = rq_pbmax + kMaxPairs, *rq_rmax = rq_cmax + kMaxN;
     const bool lead = blockIdx.x == 0;
     int pos = a.start;
+    unsigned rnd = __hip_atomic_load(g.round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);   // selection rounds
     long long idle0 = dev_clock();
     for (;;) {
         if (lead && threadIdx.x == 0) {
@@ -502,7 +592,7 @@ __global__ __launch_bounds__(BS) void k_serve_grid(Params p, ServeArgs a, GridCt
                 const int q0 = rq_poff[i];
                 const StepIn s{0, i, n, 0, i, q0, rq_poff[i + 1] - q0, rq_cpu[i], rq_ram[i], rq_cmax[i], rq_rmax[i]};
                 const ReqView rv{rq_pj + q0, rq_pbw + q0, rq_host, rq_host, rq_pbmax + q0};
-                if (!grid_topsis_step<BS, CS>(t, p.st, p.m, b, sm, g, timeout, s, rv, p.tr)) {
+                if (!grid_topsis_step<BS, CS>(t, p.st, p.m, b, sm, g, timeout, s, rv, p.tr, rnd)) {
                     fault = __hip_atomic_load(g.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
                     break;
                 }
@@ -539,6 +629,7 @@ __global__ __launch_bounds__(BS) void k_serve_grid(Params p, ServeArgs a, GridCt
         idle0 = dev_clock();
     }
     if (lead && threadIdx.x == 0) {
+        __hip_atomic_store(g.round, rnd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(a.ctrl, pos, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
         __hip_atomic_store(a.ctrl + 1, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }

@@ -148,7 +148,10 @@ struct Trace {
 enum {
     M_OK = 0, M_TRACE = 1,
     M_DH0 = 2, M_DH1 = 3, M_DE0 = 4, M_DE1 = 5, M_DP0 = 6, M_DP1 = 7,   // deficits (min, max id)
-    M_ALIVE = 8, M_ROUTE = 9, M_MISC = 16
+    M_ALIVE = 8, M_ROUTE = 9,
+    M_KEY = 12,                  // cooperative step: the workgroup's packed best key (two slots, 8-byte aligned)
+    M_RES = 14,                  // cooperative step: outcome of the selection round
+    M_MISC = 16
 };
 
 constexpr int kMaxWaves = 16;          // 1024-thread workgroups
