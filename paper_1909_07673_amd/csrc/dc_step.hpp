@@ -282,21 +282,29 @@ __device__ __forceinline__ void path_apply(const Topo &t, const State &st, int u
 // there are at most 1024 candidates.
 __device__ __forceinline__ unsigned widest_wave(const Topo &t, const State &st, int u, int v, int eu, int pu,
                                                 int ev, int pv, int lane) {
-    const int ncand = (eu == ev) ? 1 : (pu == pv ? t.h : t.hh);
+    // every load of a candidate is made before any is used, so a peer costs
+    // one round of memory latency (the loop trips are compile-time constants
+    // where the topology is)
     const int base = min(st.up[u], st.up[v]);
     unsigned best = 0;
-    for (int c = lane; c < ncand; c += kWave) {
-        int b = base;
-        if (eu != ev) {
-            const int a = (pu == pv) ? c : div_floor(c, t.h, t.rh);
-            b = min(b, min(st.ea[eu * t.h + a], st.ea[ev * t.h + a]));
-            if (pu != pv) {
-                const int j = c - a * t.h;
-                b = min(b, min(st.ac[(pu * t.h + a) * t.h + j], st.ac[(pv * t.h + a) * t.h + j]));
-            }
+    if (eu == ev) {                                   // same edge switch: the two uplinks
+        best = lane == 0 ? (static_cast<unsigned>(base) << 10) | 1023u : 0u;
+    } else if (pu == pv) {                            // same pod: candidates are aggregation switches
+#pragma unroll
+        for (int c = lane; c < t.h; c += kWave) {
+            const int b = min(base, min(st.ea[eu * t.h + c], st.ea[ev * t.h + c]));
+            const unsigned key = (static_cast<unsigned>(b) << 10) | static_cast<unsigned>(1023 - c);
+            best = key > best ? key : best;
         }
-        const unsigned key = (static_cast<unsigned>(b) << 10) | static_cast<unsigned>(1023 - c);
-        best = key > best ? key : best;
+    } else {                                          // candidates c = a * h + j: aggregation a, core (a, j)
+#pragma unroll
+        for (int c = lane; c < t.hh; c += kWave) {
+            const int a = div_floor(c, t.h, t.rh);
+            const int b = min(min(base, min(st.ea[eu * t.h + a], st.ea[ev * t.h + a])),
+                              min(st.ac[pu * t.hh + c], st.ac[pv * t.hh + c]));
+            const unsigned key = (static_cast<unsigned>(b) << 10) | static_cast<unsigned>(1023 - c);
+            best = key > best ? key : best;
+        }
     }
     return wave_umax(best);
 }
