@@ -280,33 +280,61 @@ __device__ __forceinline__ void path_apply(const Topo &t, const State &st, int u
 // one wave, candidates spread over lanes.  Returns the 32-bit key
 // bottleneck << 10 | (1023 - candidate): residuals stay below 2^22 and
 // there are at most 1024 candidates.
-__device__ __forceinline__ unsigned widest_wave(const Topo &t, const State &st, int u, int v, int eu, int pu,
-                                                int ev, int pv, int lane) {
+// The widest path's key and the residuals of its links (in the roles of
+// path_link: uplinks of u and v, edge-aggregation links on u's and v's side,
+// aggregation-core links on u's and v's side; 0 where the path has none).
+struct Widest {
+    unsigned key;
+    int link[6];
+};
+
+__device__ __forceinline__ Widest widest_wave_links(const Topo &t, const State &st, int u, int v, int eu, int pu,
+                                                    int ev, int pv, int lane) {
     // every load of a candidate is made before any is used, so a peer costs
     // one round of memory latency (the loop trips are compile-time constants
-    // where the topology is)
-    const int base = min(st.up[u], st.up[v]);
+    // where the topology is); each lane keeps the residuals of its best
+    // candidate, and the lane holding the overall best hands them out
+    const int upu = st.up[u], upv = st.up[v];
+    const int base = min(upu, upv);
     unsigned best = 0;
+    int b2 = 0, b3 = 0, b4 = 0, b5 = 0;
     if (eu == ev) {                                   // same edge switch: the two uplinks
         best = lane == 0 ? (static_cast<unsigned>(base) << 10) | 1023u : 0u;
     } else if (pu == pv) {                            // same pod: candidates are aggregation switches
 #pragma unroll
         for (int c = lane; c < t.h; c += kWave) {
-            const int b = min(base, min(st.ea[eu * t.h + c], st.ea[ev * t.h + c]));
+            const int x2 = st.ea[eu * t.h + c], x3 = st.ea[ev * t.h + c];
+            const int b = min(base, min(x2, x3));
             const unsigned key = (static_cast<unsigned>(b) << 10) | static_cast<unsigned>(1023 - c);
-            best = key > best ? key : best;
+            if (key > best) { best = key; b2 = x2; b3 = x3; }
         }
     } else {                                          // candidates c = a * h + j: aggregation a, core (a, j)
 #pragma unroll
         for (int c = lane; c < t.hh; c += kWave) {
             const int a = div_floor(c, t.h, t.rh);
-            const int b = min(min(base, min(st.ea[eu * t.h + a], st.ea[ev * t.h + a])),
-                              min(st.ac[pu * t.hh + c], st.ac[pv * t.hh + c]));
+            const int x2 = st.ea[eu * t.h + a], x3 = st.ea[ev * t.h + a];
+            const int x4 = st.ac[pu * t.hh + c], x5 = st.ac[pv * t.hh + c];
+            const int b = min(min(base, min(x2, x3)), min(x4, x5));
             const unsigned key = (static_cast<unsigned>(b) << 10) | static_cast<unsigned>(1023 - c);
-            best = key > best ? key : best;
+            if (key > best) { best = key; b2 = x2; b3 = x3; b4 = x4; b5 = x5; }
         }
     }
-    return wave_umax(best);
+    Widest w;
+    w.key = wave_umax(best);
+    const unsigned long long mask = __ballot(best == w.key);
+    const int src = mask ? __builtin_ctzll(mask) : 0;
+    w.link[0] = upu;
+    w.link[1] = upv;
+    w.link[2] = __builtin_amdgcn_readlane(b2, src);
+    w.link[3] = __builtin_amdgcn_readlane(b3, src);
+    w.link[4] = __builtin_amdgcn_readlane(b4, src);
+    w.link[5] = __builtin_amdgcn_readlane(b5, src);
+    return w;
+}
+
+__device__ __forceinline__ unsigned widest_wave(const Topo &t, const State &st, int u, int v, int eu, int pu,
+                                                int ev, int pv, int lane) {
+    return widest_wave_links(t, st, u, v, eu, pu, ev, pv, lane).key;
 }
 
 // Lanes 0..5 each update one link of the path (its links are distinct).
@@ -337,7 +365,10 @@ __device__ __forceinline__ void path_apply_lanes(const Topo &t, const State &st,
 __device__ __forceinline__ bool commit_wave(const Topo &t, const State &st, const Batch &b, int u, const StepIn &s,
                                             int P, const Smem &sm, const int *pbmax, int lane) {
     const int pmax = lane < P ? pbmax[lane] : 0;
-    if (st.cpu[u] < s.cpu || st.ram[u] < s.ram) return false;
+    // the server's resources, read once: only this wave writes them until
+    // the commit ends
+    const int cpu_u = st.cpu[u], ram_u = st.ram[u], npl_u = st.npl[u];
+    if (cpu_u < s.cpu || ram_u < s.ram) return false;
     const int eu = edge_of(t, u), pu = pod_of(t, u);
     int routed = 0, mycode = -1, mine = pmax;   // lane p keeps peer p's path choice and allocation
     bool ok = true;
@@ -348,11 +379,19 @@ __device__ __forceinline__ bool commit_wave(const Topo &t, const State &st, cons
             routed = p + 1;
             continue;
         }
-        const unsigned best = widest_wave(t, st, u, v, eu, pu, pk.y & 0xffff, pk.y >> 16, lane);
-        const int bn = static_cast<int>(best >> 10);
-        const int c = 1023 - static_cast<int>(best & 1023u);
+        const Widest wd = widest_wave_links(t, st, u, v, eu, pu, pk.y & 0xffff, pk.y >> 16, lane);
+        const int bn = static_cast<int>(wd.key >> 10);
+        const int c = 1023 - static_cast<int>(wd.key & 1023u);
         if (bn < pk.z) { ok = false; break; }
-        path_apply_lanes<false>(t, st, u, v, c, -pk.z, lane);
+        // lane x writes link x of the path with its residual less the demand
+        // (the residuals were just read; no other wave writes them meanwhile)
+        if (lane < 6) {
+            int *l = path_link(t, st, u, v, c, lane);
+            int cur = wd.link[0];
+#pragma unroll
+            for (int x = 1; x < 6; ++x) cur = lane == x ? wd.link[x] : cur;
+            if (l) *l = cur - pk.z;
+        }
         mycode = lane == p ? c : mycode;
         mine = lane == p ? pk.z : mine;
         __threadfence_block();
@@ -387,10 +426,10 @@ __device__ __forceinline__ bool commit_wave(const Topo &t, const State &st, cons
         b.pbwa[s.p0 + lane] = mine;
     }
     if (lane == 0) {
-        const int ca = max(s.cpu, min(s.cmax, st.cpu[u])), ra = max(s.ram, min(s.rmax, st.ram[u]));
-        st.cpu[u] -= ca;
-        st.ram[u] -= ra;
-        st.npl[u] += 1;
+        const int ca = max(s.cpu, min(s.cmax, cpu_u)), ra = max(s.ram, min(s.rmax, ram_u));
+        st.cpu[u] = cpu_u - ca;
+        st.ram[u] = ram_u - ra;
+        st.npl[u] = npl_u + 1;
         b.cpua[s.g] = ca;
         b.rama[s.g] = ra;
     }
