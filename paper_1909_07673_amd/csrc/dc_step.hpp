@@ -280,6 +280,10 @@ __device__ __forceinline__ void path_apply(const Topo &t, const State &st, int u
 // one wave, candidates spread over lanes.  Returns the 32-bit key
 // bottleneck << 10 | (1023 - candidate): residuals stay below 2^22 and
 // there are at most 1024 candidates.
+// Candidate paths a lane takes between two pods: hh / 64 rounded up, at
+// most 1024 / 64 (k <= 64).
+constexpr int kMaxCandIters = 16;
+
 // The widest path's key and the residuals of its links (in the roles of
 // path_link: uplinks of u and v, edge-aggregation links on u's and v's side,
 // aggregation-core links on u's and v's side; 0 where the path has none).
@@ -295,28 +299,55 @@ __device__ __forceinline__ Widest widest_wave_links(const Topo &t, const State &
     // where the topology is); each lane keeps the residuals of its best
     // candidate, and the lane holding the overall best hands them out
     const int upu = st.up[u], upv = st.up[v];
-    const int base = min(upu, upv);
     unsigned best = 0;
     int b2 = 0, b3 = 0, b4 = 0, b5 = 0;
     if (eu == ev) {                                   // same edge switch: the two uplinks
-        best = lane == 0 ? (static_cast<unsigned>(base) << 10) | 1023u : 0u;
+        best = lane == 0 ? (static_cast<unsigned>(min(upu, upv)) << 10) | 1023u : 0u;
     } else if (pu == pv) {                            // same pod: candidates are aggregation switches
+        const int iters = (t.h + kWave - 1) / kWave;
 #pragma unroll
-        for (int c = lane; c < t.h; c += kWave) {
+        for (int i = 0; i < iters; ++i) {
+            const int c = lane + i * kWave;
+            if (c >= t.h) break;
             const int x2 = st.ea[eu * t.h + c], x3 = st.ea[ev * t.h + c];
-            const int b = min(base, min(x2, x3));
+            const int b = min(min(upu, upv), min(x2, x3));
             const unsigned key = (static_cast<unsigned>(b) << 10) | static_cast<unsigned>(1023 - c);
             if (key > best) { best = key; b2 = x2; b3 = x3; }
         }
-    } else {                                          // candidates c = a * h + j: aggregation a, core (a, j)
-#pragma unroll
+    } else if (!__builtin_constant_p(t.hh)) {         // candidates c = a * h + j: aggregation a, core (a, j)
         for (int c = lane; c < t.hh; c += kWave) {
             const int a = div_floor(c, t.h, t.rh);
             const int x2 = st.ea[eu * t.h + a], x3 = st.ea[ev * t.h + a];
             const int x4 = st.ac[pu * t.hh + c], x5 = st.ac[pv * t.hh + c];
-            const int b = min(min(base, min(x2, x3)), min(x4, x5));
+            const int b = min(min(min(upu, upv), min(x2, x3)), min(x4, x5));
             const unsigned key = (static_cast<unsigned>(b) << 10) | static_cast<unsigned>(1023 - c);
             if (key > best) { best = key; b2 = x2; b3 = x3; b4 = x4; b5 = x5; }
+        }
+    } else {
+        // the same where hh is a compile-time constant: a trip count the
+        // compiler sees, so the loads of all of a lane's candidates are made
+        // up front, in registers
+        const int iters = (t.hh + kWave - 1) / kWave;
+        int x2[kMaxCandIters], x3[kMaxCandIters], x4[kMaxCandIters], x5[kMaxCandIters];
+#pragma unroll
+        for (int i = 0; i < kMaxCandIters; ++i) {
+            if (i >= iters) break;
+            const int c = min(lane + i * kWave, t.hh - 1);
+            const int a = div_floor(c, t.h, t.rh);
+            x2[i] = st.ea[eu * t.h + a];
+            x3[i] = st.ea[ev * t.h + a];
+            x4[i] = st.ac[pu * t.hh + c];
+            x5[i] = st.ac[pv * t.hh + c];
+        }
+        const int base = min(upu, upv);
+#pragma unroll
+        for (int i = 0; i < kMaxCandIters; ++i) {
+            if (i >= iters) break;
+            const int c = lane + i * kWave;
+            if (c >= t.hh) break;
+            const int b = min(min(base, min(x2[i], x3[i])), min(x4[i], x5[i]));
+            const unsigned key = (static_cast<unsigned>(b) << 10) | static_cast<unsigned>(1023 - c);
+            if (key > best) { best = key; b2 = x2[i]; b3 = x3[i]; b4 = x4[i]; b5 = x5[i]; }
         }
     }
     Widest w;
