@@ -313,18 +313,26 @@ TILE_T, TILE_C, TILE_N = 32768, 4, 1024
 # WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads
 # for the run's plain device copy of copy_kib KiB (which reads and writes
 # copy_kib).  Valid only for the kernel sources the counters were taken on
-# (their SHA-256) and, for the batched kernel, the launch shape; reported as
-# null otherwise.
+# (their SHA-256); reported as null otherwise.
 TILE_TRAFFIC = {
-    "sources": ("paper_1909_07673_amd/csrc/dc_tiles.hpp", "paper_1909_07673_amd/csrc/dc_step.hpp"),
-    "sha256": "fe44d0a139b0563055380f40dd70c609f189bdd011f6626bfd62dd65cebe8c27",
+    "sources": ('paper_1909_07673_amd/csrc/dc_tiles.hpp', 'paper_1909_07673_amd/csrc/dc_step.hpp'),
+    "sha256": "939980b337badb0e989294da85da2ab7c37ca9d506a13e13e061596644aa17c8",
     "copy_kib": 524288.0,
-    "fetch_kib": 262216.77, "fetch_copy_kib": 262161.44,
-    "write_kib": 517.37, "write_copy_kib": 524288.0,
+    "fetch_kib": 262216.59, "fetch_copy_kib": 262162.13,
+    "write_kib": 517.58, "write_copy_kib": 524288.0,
 }
 # the batched kernel at the default workload (taken with
-# `bench.py --workload batched --steps 1 --warmup 0 --copy-ref`); None until measured
-BATCHED_TRAFFIC = None
+# `bench.py --workload batched --no-extras --no-cpu-baseline --steps 1
+# --warmup 0 --copy-ref`, one pass per counter); its HBM traffic is the
+# staging of each instance's state and the requests and results, which the
+# launch shape (workgroup size, servers per thread, peer chunk) does not change
+BATCHED_TRAFFIC = {
+    "sources": ('paper_1909_07673_amd/csrc/dc_kernels.hpp', 'paper_1909_07673_amd/csrc/dc_step.hpp'),
+    "sha256": "b5d78ae8c72ef5ac54fff583d88e58ded14d78925e1104beb57d9bcac190e7ce",
+    "copy_kib": 524288.0,
+    "fetch_kib": 122288.13, "fetch_copy_kib": 262161.63,
+    "write_kib": 39380.94, "write_copy_kib": 524288.0,
+}
 
 
 def _sources_sha(files):

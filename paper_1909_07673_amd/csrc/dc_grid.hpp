@@ -1,9 +1,10 @@
 // Cooperative container step for large data centers: one workgroup per pod
 // (k workgroups, launched cooperatively so that all are resident).  Each
 // workgroup builds the path tables for its own pod's aggregation and edge
-// switches, scores its pod's servers, and the column statistics and the
-// argmax are exchanged through global memory between three grid barriers;
-// workgroup 0 commits.  Same arithmetic as the single-workgroup step, so
+// switches, scores its pod's servers; the column statistics are exchanged
+// through global memory at a grid barrier, the argmax and the commit's
+// outcome through tagged slots (selection rounds, below); workgroup 0
+// commits.  Same arithmetic as the single-workgroup step, so
 // results are bit-identical.  Used by the plain form (one cooperative launch
 // per container step) and the serving form (one persistent cooperative
 // kernel) when k is large.
