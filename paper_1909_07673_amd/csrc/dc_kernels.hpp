@@ -91,23 +91,27 @@ __device__ __forceinline__ ReqView plain_view(const Params &p) {
 // One launch per container step, one workgroup.  With RES the instance's
 // state (6N int32) is staged into LDS for the step and written back, and
 // the criteria scratch lives in LDS too; otherwise both stay in HBM/L2.
-template <int BS, bool RES>
+// K > 0: compiled for k = K fat-trees on the four default criteria (as the
+// batched kernel); K = 0: any.
+template <int BS, bool RES, int K = 0>
 __global__ __launch_bounds__(BS) void k_topsis_plain(Params p) {
     extern __shared__ __align__(16) char dsm[];
     if (p.b.status[p.s.r] == 0) return;        // request already rejected
-    Smem sm = carve(dsm, p.pc_cap, p.t.nsw);
+    constexpr int CS = K ? 4 : 0;
+    const Topo t = topo_of<K>(p.t);
+    Smem sm = carve(dsm, p.pc_cap, t.nsw);
     const ReqView rv = plain_view(p);
     if (!RES) {
-        topsis_step<BS>(p.t, p.st, p.m, p.b, sm, p.xs, p.pc_cap, p.tr, p.inst, p.s, rv);
+        topsis_step<BS, host_group(BS), false, CS>(t, p.st, p.m, p.b, sm, p.xs, p.pc_cap, p.tr, p.inst, p.s, rv);
         return;
     }
-    const int N = p.t.N;
-    int *xs = lds_after_tables(dsm, p.pc_cap, p.t.nsw);
-    int *ls = xs + (size_t)xs_rows(p.m.nc) * N;
+    const int N = t.N;
+    int *xs = lds_after_tables(dsm, p.pc_cap, t.nsw);
+    int *ls = xs + (size_t)xs_rows(crit_count<CS>(p.m)) * N;
     stage_in<BS>(ls, p.st.cpu, 6 * N);        // the six arrays are contiguous
     // (the barrier at the end of load_peers orders these writes before any read)
     const State st{ls, ls + N, ls + 2 * N, ls + 3 * N, ls + 4 * N, ls + 5 * N};
-    topsis_step<BS, host_group(BS), true>(p.t, st, p.m, p.b, sm, xs, p.pc_cap, p.tr, p.inst, p.s, rv);
+    topsis_step<BS, host_group(BS), true, CS>(t, st, p.m, p.b, sm, xs, p.pc_cap, p.tr, p.inst, p.s, rv);
     __syncthreads();
     stage_out<BS>(p.st.cpu, ls, 6 * N);
 }

@@ -564,6 +564,10 @@ const void *grid_serve_kernel(const dc_ctx *ctx) {
                                     : reinterpret_cast<const void *>(k_serve_grid<kGridBlock, 0>);
 }
 
+// The plain kernel (state staged in LDS, 1,024 threads) compiled for k = 16
+// on the default criteria.
+constexpr int kPlainK = 16;
+
 template <int BS>
 void launch_plain_step(dc_ctx *ctx, const Params &p) {
     if (ctx->use_grid) {
@@ -579,7 +583,11 @@ void launch_plain_step(dc_ctx *ctx, const Params &p) {
     }
     if (ctx->m.method == DC_TOPSIS) {
         if (ctx->plain_res)
-            hipLaunchKernelGGL((k_topsis_plain<BS, true>), dim3(1), dim3(BS), ctx->lds_plain, ctx->stream, p);
+            if (BS == 1024 && specialised(ctx, kPlainK))
+                hipLaunchKernelGGL((k_topsis_plain<1024, true, kPlainK>), dim3(1), dim3(1024), ctx->lds_plain,
+                                   ctx->stream, p);
+            else
+                hipLaunchKernelGGL((k_topsis_plain<BS, true>), dim3(1), dim3(BS), ctx->lds_plain, ctx->stream, p);
         else
             hipLaunchKernelGGL((k_topsis_plain<BS, false>), dim3(1), dim3(BS), ctx->lds_plain, ctx->stream, p);
         ctx->last_launches += 1;
@@ -1351,7 +1359,8 @@ int dc_create(const dc_config *cfg, dc_ctx **out) {
     if (set_lds(c, k_topsis_plain<64, true>, c->lds_plain) || set_lds(c, k_topsis_plain<64, false>, c->lds_plain) ||
         set_lds(c, k_topsis_plain<256, true>, c->lds_plain) || set_lds(c, k_topsis_plain<256, false>, c->lds_plain) ||
         set_lds(c, k_topsis_plain<512, true>, c->lds_plain) || set_lds(c, k_topsis_plain<512, false>, c->lds_plain) ||
-        set_lds(c, k_topsis_plain<1024, true>, c->lds_plain) || set_lds(c, k_topsis_plain<1024, false>, c->lds_plain)) {
+        set_lds(c, k_topsis_plain<1024, true>, c->lds_plain) || set_lds(c, k_topsis_plain<1024, false>, c->lds_plain) ||
+        set_lds(c, k_topsis_plain<1024, true, kPlainK>, c->lds_plain)) {
         dc_destroy(ctx.release());
         return DC_EDEVICE;
     }
