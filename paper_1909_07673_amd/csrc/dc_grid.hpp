@@ -21,10 +21,9 @@ constexpr int kGridBlock = 256;
 struct GridCtl {
     unsigned *count, *gen;        // grid barrier: arrivals, generation
     int *err;                     // set when a barrier wait timed out
-    int *part;                    // [kStatFields][G] per-workgroup column statistics
-    int *cap;                     // [2][G*h]: summed residuals per edge switch, then [G] per pod
     unsigned long long *kslot;    // [2][G] per-workgroup best key of a selection round, tagged
     unsigned long long *rflag;    // outcome of a selection round's commit, tagged
+    unsigned long long *rec;      // [G][kRecWords] per-workgroup records of a step, tagged (below)
     unsigned *round;              // selection rounds so far (kept across launches)
     int *flag;                    // [kGridFlags]: trace slot, command buffers
 };
@@ -100,8 +99,7 @@ __device__ __forceinline__ int round_outcome(const GridCtl &g, unsigned r, long 
     }
 }
 
-// flag[7]: trace slot of the
-// step; flag[8 + 8 * (pos & 1) ...]: the command at ring position pos,
+// flag[8 + 8 * (pos & 1) ...]: the command at ring position pos,
 // double-buffered so that the leader can publish command pos + 1 while a
 // slower workgroup still reads command pos.
 constexpr int kGridFlags = 24;
@@ -146,6 +144,62 @@ __device__ __forceinline__ bool grid_sync(const GridCtl &g, int *lds_flag, long 
     }
     __syncthreads();
     return !*lds_flag;
+}
+
+// Records of a step: instead of a grid barrier, each workgroup publishes
+// its column-statistics partials, its edge switches' and its pod's summed
+// residuals (and workgroup 0 the trace slot) as 64-bit words, the value in
+// the low half and in the high half a tag made of the number of the step's
+// first selection round with the top bit set (never 0, which the words hold
+// initially); a reader polls a word until it carries that tag, so no fence
+// is needed.  Every word is written at every step, a step has fewer than
+// 2^31 rounds, so a word read with the current tag was written in this step.
+// A workgroup writes the next step's record only after this step's last
+// selection round, whose outcome needs every workgroup's key, which each
+// publishes after it has read the records.
+__device__ __forceinline__ unsigned long long rec_tag(unsigned r) {
+    return static_cast<unsigned long long>(r | 0x80000000u) << 32;
+}
+constexpr int kRecWords = 80;
+constexpr int kRecCapE = 5 * kMaxCrit;            // then h edge switches (h <= 32)
+constexpr int kRecCapP = kRecCapE + 32;
+constexpr int kRecTrace = kRecCapP + 1;
+static_assert(kRecTrace < kRecWords, "record layout");
+
+__device__ __forceinline__ void rec_put(const GridCtl &g, int w, int x, unsigned long long tag, int v) {
+    __hip_atomic_store(g.rec + static_cast<size_t>(w) * kRecWords + x, tag | static_cast<unsigned>(v),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ unsigned long long rec_load(const GridCtl &g, int w, int x) {
+    return __hip_atomic_load(g.rec + static_cast<size_t>(w) * kRecWords + x, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool rec_has(unsigned long long v, unsigned long long tag) { return (v >> 32) == (tag >> 32); }
+
+// Thread: n words of the records (workgroup ws[j], word xs[j]) once all
+// carry tag, every poll with all its loads in flight together; false when
+// the wait timed out or a workgroup reported an error.
+template <int NW>
+__device__ __forceinline__ bool rec_get(const GridCtl &g, int n, const int (&ws)[NW], const int (&xs)[NW],
+                                        unsigned long long tag, long long timeout, int (&v)[NW]) {
+    const long long t0 = dev_clock();
+    for (;;) {
+        bool ok = true;
+#pragma unroll
+        for (int j = 0; j < NW; ++j)
+            if (j < n) {
+                const unsigned long long r = rec_load(g, ws[j], xs[j]);
+                ok &= rec_has(r, tag);
+                v[j] = static_cast<int>(static_cast<unsigned>(r));
+            }
+        if (ok) return true;
+        if (__hip_atomic_load(g.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || dev_clock() - t0 > timeout) {
+            __hip_atomic_store(g.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
 }
 
 // LDS of the cooperative step (per workgroup): peers, own-pod tables and
@@ -205,9 +259,11 @@ __device__ __forceinline__ bool grid_topsis_step(const Topo &t, const State &st,
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     const int P = s.P, ubase = w * hh;
     int *xs = sm.xs;
+    const unsigned long long stag = rec_tag(rnd);     // this step's records
+    int my_slot = -1;                                   // trace slot (workgroup 0, thread 0)
     if (w == 0 && threadIdx.x == 0) {
         if (s.i == 0) b.tsb[s.r] = dev_clock();
-        g.flag[7] = tr.stride > 0 ? trace_slot(tr, 0, b.rid[s.r], s.i) : -1;
+        if (tr.stride > 0) my_slot = trace_slot(tr, 0, b.rid[s.r], s.i);
     }
     // ---- A: peers, own capacities
     for (int p = threadIdx.x; p < P; p += BS) {
@@ -301,34 +357,45 @@ __device__ __forceinline__ bool grid_topsis_step(const Topo &t, const State &st,
             lane == 0 ? c0 : lane == 1 ? c1 : lane == 2 ? c2 : lane == 3 ? hi : -lo;
     }
     __syncthreads();
-    // workgroup partials to global; own capacities for the other pods' checks
+    // this workgroup's record: statistics partials, own capacities for the
+    // other pods' checks, and (workgroup 0) the trace slot
     for (int f = threadIdx.x; f < 5 * nc; f += BS) {
         int v = (f % 5) < 3 ? 0 : -kBig - 1;
         for (int x = 0; x < BS / kWave; ++x) {
             const int pv = sm.wst[f * kMaxWaves + x];
             v = (f % 5) < 3 ? v + pv : max(v, pv);
         }
-        g.part[f * G + w] = v;
+        rec_put(g, w, f, stag, v);
     }
-    for (int e = threadIdx.x; e < h; e += BS) g.cap[w * h + e] = sm.capE[e];
-    if (threadIdx.x == 0) g.cap[G * h + w] = capP_own;
-    if (!grid_sync(g, sm.misc + M_OK, timeout)) return false;                  // barrier 1
+    for (int e = threadIdx.x; e < h; e += BS) rec_put(g, w, kRecCapE + e, stag, sm.capE[e]);
+    if (threadIdx.x == 0) {
+        rec_put(g, w, kRecCapP, stag, capP_own);
+        if (w == 0) rec_put(g, 0, kRecTrace, stag, my_slot);
+    }
     // ---- D: block totals, peer-side deficits, scores, workgroup best
+    // every wave reads the statistics words of all workgroups (lane x:
+    // workgroup x, G <= 64), waiting until all carry this step's tag
+    constexpr int NF = 5 * (CS ? CS : kMaxCrit);
+    bool bad = false;
+    int fv[NF];
+    {
+        int fw[NF], fx[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            fw[f] = lane;
+            fx[f] = f;
+            fv[f] = (f % 5) < 3 ? 0 : -kBig - 1;
+        }
+        if (lane < G) bad = !rec_get(g, 5 * nc, fw, fx, stag, timeout, fv);
+    }
     unsigned long long S2[kMaxCrit];
     int MX[kMaxCrit], MN[kMaxCrit];
 #pragma unroll
     for (int c = 0; c < kMaxCrit; ++c) {
         S2[c] = 0;
         MX[c] = MN[c] = 0;
-        if (c >= nc) continue;
-        int a0 = 0, a1 = 0, a2 = 0, hi = -kBig - 1, nlo = -kBig - 1;
-        for (int x = lane; x < G; x += kWave) {
-            a0 += g.part[(5 * c) * G + x];
-            a1 += g.part[(5 * c + 1) * G + x];
-            a2 += g.part[(5 * c + 2) * G + x];
-            hi = max(hi, g.part[(5 * c + 3) * G + x]);
-            nlo = max(nlo, g.part[(5 * c + 4) * G + x]);
-        }
+        if (c >= nc || 5 * c >= NF) continue;
+        int a0 = fv[5 * c], a1 = fv[5 * c + 1], a2 = fv[5 * c + 2], hi = fv[5 * c + 3], nlo = fv[5 * c + 4];
         a0 = wave_sum(a0);
         a1 = wave_sum(a1);
         a2 = wave_sum(a2);
@@ -341,6 +408,7 @@ __device__ __forceinline__ bool grid_topsis_step(const Topo &t, const State &st,
     // peer-side deficits (server uplink, edge switch, pod) as in the
     // single-workgroup step; they only narrow the candidates
     if (threadIdx.x < 6) sm.misc[M_DH0 + threadIdx.x] = (threadIdx.x & 1) ? -1 : kBig;
+    if (threadIdx.x == 6) sm.misc[M_OK] = 0;
     __syncthreads();
     for (int p = threadIdx.x; p < P; p += BS) {
         const int4 me = sm.pk[p];
@@ -353,10 +421,29 @@ __device__ __forceinline__ bool grid_topsis_step(const Topo &t, const State &st,
             sp += (o.y >> 16) == d ? o.z : 0;
         }
         if (me.w < sh) { atomicMin(sm.misc + M_DH0, v); atomicMax(sm.misc + M_DH1, v); }
-        if (g.cap[e] < se) { atomicMin(sm.misc + M_DE0, e); atomicMax(sm.misc + M_DE1, e); }
-        if (g.cap[G * h + d] < sp) { atomicMin(sm.misc + M_DP0, d); atomicMax(sm.misc + M_DP1, d); }
+        // the peer's edge switch and pod capacities, from their owners' records
+        const int cw[2] = {e / h, d}, cx[2] = {kRecCapE + e % h, kRecCapP};
+        int cv[2];
+        bad |= !rec_get(g, 2, cw, cx, stag, timeout, cv);
+        if (cv[0] < se) {
+            atomicMin(sm.misc + M_DE0, e);
+            atomicMax(sm.misc + M_DE1, e);
+        }
+        if (cv[1] < sp) {
+            atomicMin(sm.misc + M_DP0, d);
+            atomicMax(sm.misc + M_DP1, d);
+        }
     }
+    int slot = -1;
+    if (tr.stride > 0) {
+        const int zw[1] = {0}, zx[1] = {kRecTrace};
+        int zv[1];
+        bad |= !rec_get(g, 1, zw, zx, stag, timeout, zv);
+        slot = zv[0];
+    }
+    if (bad) sm.misc[M_OK] = 1;
     __syncthreads();
+    if (sm.misc[M_OK]) return false;
     const int dh0 = sm.misc[M_DH0], dh1 = sm.misc[M_DH1], de0 = sm.misc[M_DE0], de1 = sm.misc[M_DE1];
     const int dp0 = sm.misc[M_DP0], dp1 = sm.misc[M_DP1];
     float q[kMaxCrit], ap[kMaxCrit], am[kMaxCrit];
@@ -403,7 +490,6 @@ __device__ __forceinline__ bool grid_topsis_step(const Topo &t, const State &st,
             *reinterpret_cast<unsigned long long *>(sm.misc + M_KEY) = round_key(best);
         }
     };
-    const int slot = g.flag[7];
     if (slot >= 0)
         for (int x = threadIdx.x; x < hh; x += BS)
             tr.scores[static_cast<size_t>(slot) * t.N + ubase + x] =
@@ -497,7 +583,11 @@ __device__ __forceinline__ int *grid_req_lds(char *dsm, int h, int hh, int nc) {
 template <int BS, int K>
 __global__ __launch_bounds__(BS) void k_topsis_grid(Params p, GridCtl g, long long timeout) {
     extern __shared__ __align__(16) char dsm[];
-    if (p.b.status[p.s.r] == 0) return;        // every workgroup leaves: no barrier is reached
+    // every workgroup leaves before any wait: the request was rejected at an
+    // earlier step, or a wait of an earlier launch timed out (the launches of
+    // a batch's steps are queued together, and a step after a failed one
+    // would read the missing peer's server as -1)
+    if (p.b.status[p.s.r] == 0 || __hip_atomic_load(g.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     constexpr int CS = K ? 4 : 0;
     const Topo t = topo_of<K>(p.t);
     const GSmem sm = gcarve(dsm, t.h, t.hh, crit_count<CS>(p.m));

@@ -778,9 +778,9 @@ int collect(dc_ctx *ctx, DevBatch &b) {
 // ---------------------------------------------------------------- cooperative step
 int grid_init(dc_ctx *ctx) {
     const int G = ctx->t.k, h = ctx->t.h;
-    // count, gen, err, round, flag[kGridFlags], part[kStatFields][G], cap[G*h + G], then 8-byte aligned:
-    // kslot[2][G], rflag
-    const size_t ints = 4 + kGridFlags + (size_t)kStatFields * G + (size_t)G * h + G + 2 + 4 * (size_t)G + 2;
+    if (h > kRecCapP - kRecCapE || G > kWave) return DC_EINVAL;
+    // count, gen, err, round, flag[kGridFlags], then 8-byte aligned: kslot[2][G], rflag, rec[G][kRecWords]
+    const size_t ints = 4 + kGridFlags + 2 + 2 * (2 * (size_t)G + 1 + (size_t)G * kRecWords);
     HIPCHK(hipMalloc(&ctx->d_grid, ints * sizeof(int)));
     hipLaunchKernelGGL(k_fill_i32, dim3(16), dim3(256), 0, ctx->stream, ctx->d_grid, 0, (long long)ints);
     HIPCHK(hipGetLastError());
@@ -791,12 +791,11 @@ int grid_init(dc_ctx *ctx) {
     g.err = p + 2;
     g.round = reinterpret_cast<unsigned *>(p + 3);
     g.flag = p + 4;
-    g.part = g.flag + kGridFlags;
-    g.cap = g.part + (size_t)kStatFields * G;
-    int *k = g.cap + (size_t)G * h + G;
+    int *k = g.flag + kGridFlags;
     k += (reinterpret_cast<uintptr_t>(k) & 7) ? 1 : 0;
     g.kslot = reinterpret_cast<unsigned long long *>(k);
     g.rflag = g.kslot + 2 * G;
+    g.rec = g.rflag + 1;
     ctx->lds_grid = gsmem_bytes(h, ctx->t.hh, ctx->m.nc);
     const size_t serve_lds = align4(ctx->lds_grid / sizeof(int)) * sizeof(int) + req_lds_ints() * sizeof(int);
     if (serve_lds > 159 * 1024) return DC_EINVAL;
