@@ -265,6 +265,23 @@ __device__ __forceinline__ int *path_link(const Topo &t, const State &st, int u,
     }
 }
 
+// The same for a lane-dependent x (u, v and c the same on every lane): the
+// link is chosen by selects rather than branches, so a wave whose lanes
+// take different links runs no divergent code.
+__device__ __forceinline__ int *path_link_lane(const Topo &t, const State &st, int u, int v, int c, int x) {
+    const int eu = edge_of(t, u), ev = edge_of(t, v), pu = pod_of(t, u), pv = pod_of(t, v);
+    const int a = pu == pv ? c : div_floor(c, t.h, t.rh);
+    const int j = c - a * t.h;
+    const bool vs = x & 1;
+    const int kind = x >> 1;
+    int *l0 = st.up + (vs ? v : u);
+    int *l1 = st.ea + (vs ? ev : eu) * t.h + a;
+    int *l2 = st.ac + ((vs ? pv : pu) * t.h + a) * t.h + j;
+    int *l = kind == 0 ? l0 : (kind == 1 ? l1 : l2);
+    const bool has = x < 6 && (kind == 0 || (kind == 1 ? eu != ev : pu != pv));
+    return has ? l : nullptr;
+}
+
 template <bool ATOMIC>
 __device__ __forceinline__ void path_apply(const Topo &t, const State &st, int u, int v, int c, int delta) {
     for (int x = 0; x < 6; ++x) {
@@ -372,12 +389,10 @@ __device__ __forceinline__ unsigned widest_wave(const Topo &t, const State &st, 
 template <bool ATOMIC>
 __device__ __forceinline__ void path_apply_lanes(const Topo &t, const State &st, int u, int v, int c, int delta,
                                                  int lane) {
-    if (lane < 6) {
-        int *l = path_link(t, st, u, v, c, lane);
-        if (l) {
-            if (ATOMIC) atomicAdd(l, delta);
-            else *l += delta;
-        }
+    int *l = path_link_lane(t, st, u, v, c, lane);
+    if (l) {
+        if (ATOMIC) atomicAdd(l, delta);
+        else *l += delta;
     }
 }
 
@@ -416,8 +431,8 @@ __device__ __forceinline__ bool commit_wave(const Topo &t, const State &st, cons
         if (bn < pk.z) { ok = false; break; }
         // lane x writes link x of the path with its residual less the demand
         // (the residuals were just read; no other wave writes them meanwhile)
-        if (lane < 6) {
-            int *l = path_link(t, st, u, v, c, lane);
+        {
+            int *l = path_link_lane(t, st, u, v, c, lane);
             int cur = wd.link[0];
 #pragma unroll
             for (int x = 1; x < 6; ++x) cur = lane == x ? wd.link[x] : cur;
@@ -445,7 +460,7 @@ __device__ __forceinline__ bool commit_wave(const Topo &t, const State &st, cons
         const int v = __builtin_amdgcn_readlane(mypk.x, p);
         const int room = __builtin_amdgcn_readlane(pmax, p) - __builtin_amdgcn_readlane(mypk.z, p);
         const int c = __builtin_amdgcn_readlane(mycode, p);
-        const int *l = lane < 6 ? path_link(t, st, u, v, c, lane) : nullptr;
+        const int *l = path_link_lane(t, st, u, v, c, lane);
         const int add = min(room, wave_min(l ? *l : kBig));
         if (add <= 0) continue;
         path_apply_lanes<false>(t, st, u, v, c, -add, lane);
@@ -956,8 +971,8 @@ __device__ __forceinline__ bool route_request_end(const Topo &t, const State &st
         const int u = host(g);
         for (int x = b.poff[s.g0 + g]; x < b.poff[s.g0 + g + 1]; ++x) {
             const int c = b.code[x];
-            if (c >= 0 && lane < 6) {
-                const int *l = path_link(t, st, u, host(b.pj[x]), c, lane);
+            if (c >= 0) {
+                const int *l = path_link_lane(t, st, u, host(b.pj[x]), c, lane);
                 if (l && __hip_atomic_load(l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < 0) *lds_ok = 0;
             }
         }
@@ -971,7 +986,7 @@ __device__ __forceinline__ bool route_request_end(const Topo &t, const State &st
                     const int c = b.code[x], room = b.pbmax[x] - b.pbw[x];
                     if (c < 0 || room <= 0) continue;
                     const int v = host(b.pj[x]);
-                    const int *l = lane < 6 ? path_link(t, st, u, v, c, lane) : nullptr;
+                    const int *l = path_link_lane(t, st, u, v, c, lane);
                     const int left = l ? __hip_atomic_load(l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kBig;
                     const int add = min(room, wave_min(left));
                     if (add <= 0) continue;
