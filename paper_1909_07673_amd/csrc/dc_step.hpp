@@ -417,9 +417,12 @@ __device__ __forceinline__ bool commit_wave(const Topo &t, const State &st, cons
     if (cpu_u < s.cpu || ram_u < s.ram) return false;
     const int eu = edge_of(t, u), pu = pod_of(t, u);
     int routed = 0, mycode = -1, mine = pmax;   // lane p keeps peer p's path choice and allocation
+    // lane p holds peer p's record (P <= 64), handed out per peer below
+    const int4 mypk = lane < P ? sm.pk[lane] : make_int4(u, 0, 0, 0);
     bool ok = true;
     for (int p = 0; p < P; ++p) {
-        const int4 pk = sm.pk[p];
+        const int4 pk = make_int4(__builtin_amdgcn_readlane(mypk.x, p), __builtin_amdgcn_readlane(mypk.y, p),
+                                  __builtin_amdgcn_readlane(mypk.z, p), 0);
         const int v = pk.x;
         if (v == u) {
             routed = p + 1;
@@ -445,8 +448,10 @@ __device__ __forceinline__ bool commit_wave(const Topo &t, const State &st, cons
     }
     if (!ok) {
         for (int p = routed - 1; p >= 0; --p) {
-            const int4 pk = sm.pk[p];
-            if (pk.x != u) path_apply_lanes<false>(t, st, u, pk.x, __builtin_amdgcn_readlane(mycode, p), pk.z, lane);
+            const int v = __builtin_amdgcn_readlane(mypk.x, p);
+            if (v != u)
+                path_apply_lanes<false>(t, st, u, v, __builtin_amdgcn_readlane(mycode, p),
+                                        __builtin_amdgcn_readlane(mypk.z, p), lane);
             __threadfence_block();
         }
         return false;
@@ -454,7 +459,6 @@ __device__ __forceinline__ bool commit_wave(const Topo &t, const State &st, cons
     // top-ups, only over the routed peers with room (none for fixed
     // demands); a lane always reads the links it alone writes (slot x of
     // every path from u is a link in the same role)
-    const int4 mypk = lane < P ? sm.pk[lane] : make_int4(u, 0, 0, 0);
     for (unsigned long long todo = __ballot(mypk.x != u && pmax > mypk.z); todo; todo &= todo - 1) {
         const int p = __builtin_ctzll(todo);
         const int v = __builtin_amdgcn_readlane(mypk.x, p);
@@ -533,12 +537,14 @@ __device__ __forceinline__ void rollback_request(const Topo &t, const State &st,
 //   E[eg] = max_a min(ea(eg, a), ea(ev, a), T[(p, a)] or +inf in pod pv)   eg != ev
 // so that the widest shortest path from u to v has bottleneck
 // min(up[u], up[v], E[edge(u)]) (or min(up[u], up[v]) on the same edge).
-template <int BS>
-__device__ __forceinline__ void table_T(const Topo &t, const State &st, const Smem &sm, int pbeg, int pn) {
+// peer_pod(pc): the pod of peer pbeg + pc.
+template <int BS, class PeerPod>
+__device__ __forceinline__ void table_T(const Topo &t, const State &st, const Smem &sm, int pbeg, int pn,
+                                        PeerPod peer_pod) {
     const int tot = pn * t.nsw;
     for (int it = threadIdx.x; it < tot; it += BS) {
         const int pc = div_floor(it, t.nsw, t.rnsw), ag = it - pc * t.nsw;
-        const int pv = sm.pk[pbeg + pc].y >> 16, pa = edge_of(t, ag);
+        const int pv = peer_pod(pc), pa = edge_of(t, ag);
         int val = 0;
         if (pa != pv) {
             const int a = ag - pa * t.h;
@@ -590,10 +596,12 @@ __device__ __forceinline__ void table_E(const Topo &t, const State &st, const Sm
 // Phase A of a step (no barrier needed before it): the peer list of the
 // container into LDS (server, demand, uplink residual, edge switch, pod),
 // the summed residuals per edge switch and per pod when LIMITS, and the
-// reset of the reduction slots.  Ends with a barrier.
-template <int BS, bool LIMITS>
+// reset of the reduction slots.  With T0, also the aggregation table T of
+// the first pc_cap peers, each peer's pod taken from the request itself,
+// so that T needs no barrier of its own.  Ends with a barrier.
+template <int BS, bool LIMITS, bool T0 = false>
 __device__ __forceinline__ void load_peers(const Topo &t, const State &st, const ReqView &rv, const Smem &sm,
-                                           int P) {
+                                           int P, int pc_cap = 0) {
     for (int p = threadIdx.x; p < P; p += BS) {
         const int v = rv.hosts[rv.pj[p]];
         const int bw = rv.pbw[p];
@@ -617,6 +625,8 @@ __device__ __forceinline__ void load_peers(const Topo &t, const State &st, const
             if (lane == 0) sm.capP[pod] = s;
         }
     }
+    if (T0 && P > 0)
+        table_T<BS>(t, st, sm, 0, min(P, pc_cap), [&](int pc) { return pod_of(t, rv.hosts[rv.pj[pc]]); });
     __syncthreads();
 }
 
@@ -625,13 +635,15 @@ __device__ __forceinline__ void load_peers(const Topo &t, const State &st, const
 // be reached by a server inside it, so at most one such server (switch,
 // pod) leaves any server feasible.  misc[M_DH0..M_DP1] = (min, max) id of
 // the deficient servers, edge switches, pods; (kBig, -1) when none.  No
-// barrier: the results are read after the next one.
+// barrier: the results are read after the next one.  Run by the last
+// threads of the block, which the path tables that follow leave idle.
 template <int BS>
 __device__ __forceinline__ void peer_deficits(const Smem &sm, int P) {
-    for (int p = threadIdx.x; p < P; p += BS) {
+    for (int p = BS - 1 - static_cast<int>(threadIdx.x); p < P; p += BS) {
         const int4 me = sm.pk[p];
         const int v = me.x, e = me.y & 0xffff, d = me.y >> 16;
         int sh = 0, se = 0, sp = 0;
+#pragma unroll 4
         for (int q = 0; q < P; ++q) {
             const int4 o = sm.pk[q];
             sh += o.x == v ? o.z : 0;
@@ -658,7 +670,8 @@ __device__ __forceinline__ void peer_deficits(const Smem &sm, int P) {
 // the demand of the peers outside them, and the peer-side deficits.
 // With nwg > 1, workgroup wg of nwg takes every nwg-th group of G * BS
 // servers (the other workgroups build the same peer tables for theirs).
-template <int BS, bool STATS, int G = host_group(BS), int CS = 0>
+// T0: the first chunk's table T was built by load_peers<.., true>.
+template <int BS, bool STATS, int G = host_group(BS), int CS = 0, bool T0 = false>
 __device__ __forceinline__ void criteria_stage(const Topo &t, const State &st, const Method &m, const Smem &sm, int *xs,
                                int cpu_i, int ram_i, int P, int pc_cap, int wg = 0, int nwg = 1) {
     const int N = t.N, nc = crit_count<CS>(m);
@@ -672,9 +685,11 @@ __device__ __forceinline__ void criteria_stage(const Topo &t, const State &st, c
         const int pn = min(P, pbeg + pc_cap) - pbeg;
         if (pn > 0) {
             if (ch == 0) peer_deficits<BS>(sm, P);
-            else __syncthreads();                       // previous chunk done with the tables
-            table_T<BS>(t, st, sm, pbeg, pn);
-            __syncthreads();
+            if (!(T0 && ch == 0)) {
+                if (ch > 0) __syncthreads();            // previous chunk done with the tables
+                table_T<BS>(t, st, sm, pbeg, pn, [&](int pc) { return sm.pk[pbeg + pc].y >> 16; });
+                __syncthreads();
+            }
             table_E<BS>(t, st, sm, pbeg, pn);
             __syncthreads();
         }
@@ -1037,18 +1052,29 @@ __device__ __forceinline__ bool select_commit(const Topo &t, const State &st, co
     };
     constexpr int NW = BS / kWave;
     const int wid = threadIdx.x / kWave;
+    // at most one server per thread, thread u holding server u (N <= BS, a
+    // compile-time fact): lanes and waves are in server order, so among
+    // equal high words the first lane (wave) holds the lowest server, the
+    // largest low word, and a ballot replaces the second reduction
+    auto low_of = [&](unsigned hi, unsigned hiw, unsigned lo) -> unsigned {
+        if (__builtin_constant_p(t.N) && t.N <= BS) {
+            const unsigned long long m = __ballot(hi == hiw);
+            return __builtin_amdgcn_readlane(lo, m ? __builtin_ctzll(m) : 0);
+        }
+        return wave_umax(hi == hiw ? lo : 0u);
+    };
     unsigned long long mine = scan();
     for (int it = 0;; ++it) {
         unsigned *shi = sm.ahi + (it & 1) * kMaxWaves, *slo = sm.alo + (it & 1) * kMaxWaves;
         // wave argmax: largest high word, then among those the largest low
         // word; one slot per wave, then every wave reduces the slots
         unsigned hiw = wave_umax(static_cast<unsigned>(mine >> 32));
-        unsigned low = wave_umax(static_cast<unsigned>(mine >> 32) == hiw ? static_cast<unsigned>(mine) : 0u);
+        unsigned low = low_of(static_cast<unsigned>(mine >> 32), hiw, static_cast<unsigned>(mine));
         if (lane == 0) { shi[wid] = hiw; slo[wid] = low; }
         __syncthreads();
         const unsigned wh = lane < NW ? shi[lane] : 0u, wl = lane < NW ? slo[lane] : 0u;
         hiw = wave_umax(wh);
-        low = wave_umax(wh == hiw ? wl : 0u);
+        low = low_of(wh, hiw, wl);
         const unsigned long long kb = (static_cast<unsigned long long>(hiw) << 32) | low;
         if (hiw == 0) {
             rollback_request<BS>(t, st, b, s.r, s.i);
@@ -1095,9 +1121,9 @@ __device__ __forceinline__ bool topsis_step(const Topo &t, const State &st, cons
                             int *xs, int pc_cap, const Trace &tr, int inst, const StepIn &s, const ReqView &rv) {
     if (s.i == 0 && threadIdx.x == 0) b.tsb[s.r] = dev_clock();
     if (threadIdx.x == 0) sm.misc[M_TRACE] = tr.stride > 0 ? trace_slot(tr, inst, b.rid[s.r], s.i) : -1;
-    load_peers<BS, true>(t, st, rv, sm, s.P);
+    load_peers<BS, true, true>(t, st, rv, sm, s.P, pc_cap);
     const int nc = crit_count<CS>(m), N = t.N;
-    criteria_stage<BS, !XS_LDS, G, CS>(t, st, m, sm, xs, s.cpu, s.ram, s.P, pc_cap);
+    criteria_stage<BS, !XS_LDS, G, CS, true>(t, st, m, sm, xs, s.cpu, s.ram, s.P, pc_cap);
     __syncthreads();
 
     float q[kMaxCrit], ap[kMaxCrit], am[kMaxCrit];
