@@ -649,10 +649,13 @@ __global__ __launch_bounds__(BS) void k_topsis_batched(Params p) {
     __shared__ Batch lb;
     if (threadIdx.x == 0) lb = p.b;
     __syncthreads();
-    const int r0 = p.b.iroff[inst], r1 = p.b.iroff[inst + 1];
+    // per-request values are the same on every lane: moved to scalar
+    // registers once loaded, so that no later wait for memory (which also
+    // waits for the step's outstanding stores) is placed for them
+    const int r0 = uniform(p.b.iroff[inst]), r1 = uniform(p.b.iroff[inst + 1]);
     for (int r = r0; r < r1; ++r) {
-        const int g0 = p.b.coff[r], n = p.b.coff[r + 1] - g0;
-        const int pb = p.b.poff[g0], npair = p.b.poff[g0 + n] - pb;
+        const int g0 = uniform(p.b.coff[r]), n = uniform(p.b.coff[r + 1]) - g0;
+        const int pb = uniform(p.b.poff[g0]), npair = uniform(p.b.poff[g0 + n]) - pb;
         for (int x = threadIdx.x; x <= n; x += BS) {
             rq_poff[x] = p.b.poff[g0 + x] - pb;
             if (x < n) {

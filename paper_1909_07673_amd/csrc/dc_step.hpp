@@ -134,6 +134,17 @@ struct ReqView {
     const int *pbmax;  // the peers' maximum demands
 };
 
+// Waits for this wave's outstanding global loads and stores (s_waitcnt
+// vmcnt(0) on gfx9).  Placed at the end of rarely taken paths that load from
+// global memory, so that where they join the common path the compiler's
+// per-register wait analysis finds no load outstanding; otherwise it
+// places waits there, which on this architecture also wait for every
+// store issued since (the results a step writes).
+__device__ __forceinline__ void vm_drain() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// A value that is the same on every lane, as a scalar.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // Constant-rate device clock (100 MHz), read without a memory access.
 __device__ __forceinline__ long long dev_clock() { return static_cast<long long>(wall_clock64()); }
 
@@ -411,6 +422,10 @@ __device__ __forceinline__ void path_apply_lanes(const Topo &t, const State &st,
 __device__ __forceinline__ bool commit_wave(const Topo &t, const State &st, const Batch &b, int u, const StepIn &s,
                                             int P, const Smem &sm, const int *pbmax, int lane) {
     const int pmax = lane < P ? pbmax[lane] : 0;
+    // the result arrays' addresses, read now: the Batch may sit in LDS, and
+    // read after the fences below they would add an LDS round trip to the
+    // end of the chain
+    const GPtr<int> o_code = b.code, o_pbwa = b.pbwa, o_cpua = b.cpua, o_rama = b.rama;
     // the server's resources, read once: only this wave writes them until
     // the commit ends
     const int cpu_u = st.cpu[u], ram_u = st.ram[u], npl_u = st.npl[u];
@@ -472,16 +487,16 @@ __device__ __forceinline__ bool commit_wave(const Topo &t, const State &st, cons
         __threadfence_block();
     }
     if (lane < P) {
-        b.code[s.p0 + lane] = mycode;
-        b.pbwa[s.p0 + lane] = mine;
+        o_code[s.p0 + lane] = mycode;
+        o_pbwa[s.p0 + lane] = mine;
     }
     if (lane == 0) {
         const int ca = max(s.cpu, min(s.cmax, cpu_u)), ra = max(s.ram, min(s.rmax, ram_u));
         st.cpu[u] = cpu_u - ca;
         st.ram[u] = ram_u - ra;
         st.npl[u] = npl_u + 1;
-        b.cpua[s.g] = ca;
-        b.rama[s.g] = ra;
+        o_cpua[s.g] = ca;
+        o_rama[s.g] = ra;
     }
     __threadfence_block();
     return true;
@@ -527,6 +542,7 @@ __device__ __forceinline__ void rollback_request(const Topo &t, const State &st,
         b.tse[r] = dev_clock();
     }
     __threadfence_block();
+    vm_drain();
     __syncthreads();
 }
 
@@ -898,7 +914,12 @@ __device__ __forceinline__ void column_factors_lds(const Smem &sm, const Method 
             const unsigned long long a = static_cast<unsigned long long>(c0) +
                                          (static_cast<unsigned long long>(c1) << 17) +
                                          (static_cast<unsigned long long>(c2) << 34);
-            f[c] = a ? (m.w[c] * m.w[c]) / static_cast<float>(a) : 0.0f;
+            // the weight by constant indices (scalar loads the compiler
+            // hoists), not by the wave's index (a vector load per step)
+            float wc = 0.f;
+#pragma unroll
+            for (int x = 0; x < kMaxCrit; ++x) wc = x == c ? m.w[x] : wc;
+            f[c] = a ? (wc * wc) / static_cast<float>(a) : 0.0f;
             f[kMaxCrit + c] = static_cast<float>(crit_cost<CS>(m, c) ? lo : hi);
             f[2 * kMaxCrit + c] = static_cast<float>(crit_cost<CS>(m, c) ? hi : lo);
         }
@@ -1011,6 +1032,7 @@ __device__ __forceinline__ bool route_request_end(const Topo &t, const State &st
                 }
             }
         __threadfence();
+        vm_drain();
         __syncthreads();
         return true;
     }
@@ -1022,6 +1044,7 @@ __device__ __forceinline__ bool route_request_end(const Topo &t, const State &st
         b.tse[s.r] = dev_clock();
     }
     __threadfence_block();
+    vm_drain();
     __syncthreads();
     return false;
 }
@@ -1082,14 +1105,17 @@ __device__ __forceinline__ bool select_commit(const Topo &t, const State &st, co
         }
         const int u = static_cast<int>(~static_cast<unsigned>(kb & 0xffffffffu));
         if (threadIdx.x < kWave) {
+            const GPtr<int> o_host = b.host;              // read before the commit's fences
+            const GPtr<float> o_score = b.score;
+            const GPtr<long long> o_tse = b.tse;
             const bool ok = commit_wave(t, st, b, u, s, m_route_end ? 0 : s.P, sm, sm.pbw, lane);
             if (lane == 0) {
                 sm.misc[M_OK] = ok;
                 if (ok) {
-                    b.host[s.g] = u;
+                    o_host[s.g] = u;
                     if (rv.hosts_out) rv.hosts_out[s.i] = u;
-                    b.score[s.g] = __uint_as_float(static_cast<unsigned>(kb >> 32) - 1u);
-                    if (s.i == s.n - 1) b.tse[s.r] = dev_clock();
+                    o_score[s.g] = __uint_as_float(static_cast<unsigned>(kb >> 32) - 1u);
+                    if (s.i == s.n - 1) o_tse[s.r] = dev_clock();
                 } else {
                     feas_row[u] = 0;
                 }
@@ -1120,7 +1146,14 @@ template <int BS, int G = host_group(BS), bool XS_LDS = false, int CS = 0>
 __device__ __forceinline__ bool topsis_step(const Topo &t, const State &st, const Method &m, const Batch &b, const Smem &sm,
                             int *xs, int pc_cap, const Trace &tr, int inst, const StepIn &s, const ReqView &rv) {
     if (s.i == 0 && threadIdx.x == 0) b.tsb[s.r] = dev_clock();
-    if (threadIdx.x == 0) sm.misc[M_TRACE] = tr.stride > 0 ? trace_slot(tr, inst, b.rid[s.r], s.i) : -1;
+    if (threadIdx.x == 0) {
+        int slot = -1;
+        if (tr.stride > 0) {
+            slot = trace_slot(tr, inst, b.rid[s.r], s.i);
+            vm_drain();
+        }
+        sm.misc[M_TRACE] = slot;
+    }
     load_peers<BS, true, true>(t, st, rv, sm, s.P, pc_cap);
     const int nc = crit_count<CS>(m), N = t.N;
     criteria_stage<BS, !XS_LDS, G, CS, true>(t, st, m, sm, xs, s.cpu, s.ram, s.P, pc_cap);
