@@ -24,6 +24,7 @@ struct Params {
     int ti, tj, nI, nJ;
     int *ysort;      // AHP on the 1-9 scale: [nc][N] criterion values in ascending order
     double *wsort;   // and 1 / column sum at each sorted position
+    double p1[kMaxCrit];  // criteria-level priorities P1 (ahp_p1), computed once per context
     StepIn s;        // the container step of a plain launch
     int pj[kMaxN], pbw[kMaxN];   // its placed peers (container index, minimum demand)
     int pbmax[kMaxN];            // and their maximum demands
@@ -391,81 +392,95 @@ __device__ __forceinline__ void lds_load_i32(int *lds, const int *g, int n) {
     }
 }
 
-// Pass R: rank of every value, lt[j] = #{i : x_i < x_j}, as partial counts
-// over nI chunks of i.  Grid (ceil(N/256), nI, nc).
-__global__ __launch_bounds__(kAhpBlock) void k_ahp_rank(Params p) {
-    if (p.b.status[p.s.r] == 0) return;
-    __shared__ __align__(16) int sx[kAhpTile];
-    const int N = p.t.N, c = blockIdx.z, ib = blockIdx.y;
-    const int j = blockIdx.x * kAhpBlock + threadIdx.x;
-    const int *x = p.xs + (size_t)c * N;
-    const int q = j < N ? x[j] : 0;
-    int acc = 0;
-    const int i0 = ib * p.ti, i1 = min(N, i0 + p.ti);
-    for (int base = i0; base < i1; base += kAhpTile) {
-        const int cnt = min(kAhpTile, i1 - base);
-        __syncthreads();
-        for (int t = threadIdx.x; t < cnt; t += kAhpBlock) sx[t] = x[base + t];
-        __syncthreads();
-        // sixteen values per round, four 16-byte LDS reads in flight
-        int t = 0;
-        for (; t + 16 <= cnt; t += 16) {
-            const int4 a = *reinterpret_cast<const int4 *>(sx + t), b = *reinterpret_cast<const int4 *>(sx + t + 4);
-            const int4 e = *reinterpret_cast<const int4 *>(sx + t + 8), f = *reinterpret_cast<const int4 *>(sx + t + 12);
-            acc += (a.x < q) + (a.y < q) + (a.z < q) + (a.w < q) + (b.x < q) + (b.y < q) + (b.z < q) + (b.w < q);
-            acc += (e.x < q) + (e.y < q) + (e.z < q) + (e.w < q) + (f.x < q) + (f.y < q) + (f.z < q) + (f.w < q);
-        }
-        for (; t < cnt; ++t) acc += sx[t] < q;
-    }
-    if (j < N) p.colpart[((size_t)c * p.nI + ib) * N + j] = acc;
-}
-
-// Pass S: the sorted values of criterion c.  Each value goes to its rank
-// (equal values to the same slot), then a running maximum fills the rest of
-// each run of equal values.  Grid (1, 1, nc).
+// Pass S: the values of criterion c in ascending order, duplicates kept
+// (what the column and row sums search), in two launches spread over
+// R = ceil(N / 1024) workgroups per criterion.
+//
+// S1 sorts each run of 1,024 values (the last padded with INT_MAX, which
+// sorts last) by a bitonic network, one value per thread: compare-exchanges
+// at distances below 64 go between the lanes of a wave (lane xor j), longer
+// ones through LDS, one barrier each; every trip count is a compile-time
+// constant, so the network unrolls.  With one run its output is the sorted
+// array itself, and S2 is not launched.  Grid (R, 1, nc).
 constexpr int kAhpSortBlock = 1024;
 
-__global__ __launch_bounds__(kAhpSortBlock) void k_ahp_sort_build(Params p) {
+__global__ __launch_bounds__(kAhpSortBlock) void k_ahp_sort_runs(Params p, int *runs) {
     if (p.b.status[p.s.r] == 0) return;
-    __shared__ int y[kAhpSortMax];
-    __shared__ int sh[kAhpSortBlock];
-    const int N = p.t.N, c = blockIdx.z, tid = threadIdx.x;
-    const int *x = p.xs + (size_t)c * N;
-    const int *lt = p.colpart + (size_t)c * p.nI * N;
-    // each thread's values and their ranks, with all loads of one chunk of
-    // partial counts in flight together
-    constexpr int PER = kAhpSortMax / kAhpSortBlock;
-    int xv[PER], rk[PER];
+    constexpr int L = kAhpSortBlock;
+    __shared__ int y[L];
+    const int N = p.t.N, c = blockIdx.z, tid = threadIdx.x, i = tid;
+    const int g = blockIdx.x * L + i;
+    int v = g < N ? p.xs[(size_t)c * N + g] : INT_MAX;
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-        const int j = tid + u * kAhpSortBlock;
-        xv[u] = j < N ? x[j] : 0;
-        rk[u] = 0;
-    }
-    for (int ib = 0; ib < p.nI; ++ib) {
-        const int *l = lt + (size_t)ib * N;
+    for (int k = 2; k <= L; k <<= 1) {
+        const bool desc_k = (i & k) != 0;                  // ascending where bit k of the slot is clear
+        if ((k >> 1) >= kWave) {
+            y[i] = v;
+            __syncthreads();
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int j = tid + u * kAhpSortBlock;
-            rk[u] += j < N ? l[j] : 0;
+            for (int j = k >> 1; j >= kWave; j >>= 1) {
+                if (tid < L / 2) {
+                    const int a = 2 * tid - (tid & (j - 1));   // pair (a, a + j)
+                    const int x0 = y[a], x1 = y[a + j];
+                    const bool asc = (a & k) == 0;
+                    y[a] = asc ? min(x0, x1) : max(x0, x1);
+                    y[a + j] = asc ? max(x0, x1) : min(x0, x1);
+                }
+                __syncthreads();
+            }
+            v = y[i];
+            __syncthreads();                                   // y is written again at the next k
+        }
+#pragma unroll
+        for (int j = min(k >> 1, kWave / 2); j >= 1; j >>= 1) {
+            const int o = __shfl_xor(v, j);
+            v = desc_k == ((i & j) != 0) ? min(v, o) : max(v, o);
         }
     }
-    for (int m = tid; m < N; m += kAhpSortBlock) y[m] = -1;
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < PER; ++u)
-        if (tid + u * kAhpSortBlock < N) y[rk[u]] = xv[u];
-    __syncthreads();
-    const int E = (N + kAhpSortBlock - 1) / kAhpSortBlock, m0 = min(N, tid * E), m1 = min(N, m0 + E);
-    int run = -1;
-    for (int m = m0; m < m1; ++m) run = max(run, y[m]);
-    run = block_excl_scan<kAhpSortBlock>(run, -1, sh, op_max);
-    for (int m = m0; m < m1; ++m) {
-        run = max(run, y[m]);
-        y[m] = run;
+    const int R = gridDim.x;
+    if (R == 1) {
+        if (g < N) p.ysort[(size_t)c * N + g] = v;
+    } else {
+        runs[((size_t)c * R + blockIdx.x) * L + i] = v;
     }
+}
+
+// S2 merges the R sorted runs: the value at index a of run r goes to
+// a + (values below it in every other run), counting a run's equal values
+// when the run comes first, so that the positions are distinct.  Each
+// workgroup takes one run's values against all runs staged in LDS, the
+// binary searches into the other runs advanced together.  Grid (R, 1, nc).
+__global__ __launch_bounds__(kAhpSortBlock) void k_ahp_merge_runs(Params p, const int *runs) {
+    if (p.b.status[p.s.r] == 0) return;
+    constexpr int L = kAhpSortBlock, RMAX = kAhpSortMax / L;
+    __shared__ __align__(16) int y[kAhpSortMax];
+    const int N = p.t.N, c = blockIdx.z, R = gridDim.x, r = blockIdx.x, a = threadIdx.x;
+    lds_load_i32<kAhpSortBlock>(y, runs + (size_t)c * R * L, R * L);
     __syncthreads();
-    for (int m = tid; m < N; m += kAhpSortBlock) p.ysort[(size_t)c * N + m] = y[m];
+    const int x = y[r * L + a];
+    if (x == INT_MAX) return;                                  // padding of the last run
+    // per other run q: the first index whose value is >= x (q after r) or
+    // > x (q before r), by halving a window of L + 1 positions
+    int lo[RMAX];
+#pragma unroll
+    for (int q = 0; q < RMAX; ++q) lo[q] = 0;
+#pragma unroll
+    for (int w = L; w >= 1; w >>= 1) {
+#pragma unroll
+        for (int q = 0; q < RMAX; ++q) {
+            if (q >= R || q == r) continue;
+            const int m = lo[q] + w - 1;                       // probe: is y_q[m] "before" x?
+            if (m < L) {
+                const int yv = y[q * L + m];
+                if (q < r ? yv <= x : yv < x) lo[q] = m + 1;
+            }
+        }
+    }
+    int pos = a;
+#pragma unroll
+    for (int q = 0; q < RMAX; ++q)
+        if (q < R && q != r) pos += lo[q];
+    p.ysort[(size_t)c * N + pos] = x;
 }
 
 // Pass C: exact column sums at every sorted position, stored as 1 / sum
@@ -550,7 +565,10 @@ __global__ __launch_bounds__(kAhpBlock) void k_ahp_sort_row(Params p) {
 // Local rank of the criteria-level ratio matrix W[a] / W[b] (column sums,
 // then row means of the normalised matrix); equal to W when the weights sum
 // to 1.  Kept as FP32 values, widened to FP64 for the sums that use them.
-__device__ __forceinline__ void ahp_p1(const Method &m, double *p1) {
+// Depends on the weights only: computed on the host once per context and
+// passed in the launch parameters (the same FP64 operations in the same
+// order, each rounded as IEEE specifies on both sides).
+__host__ __device__ inline void ahp_p1(const Method &m, double *p1) {
     const int nc = m.nc;
     double colsum[kMaxCrit];
     for (int b = 0; b < kMaxCrit; ++b) {
@@ -577,14 +595,12 @@ __global__ __launch_bounds__(kAhpBlock) void k_ahp_pg(Params p) {
     const int N = p.t.N, nc = p.m.nc;
     const int u = blockIdx.x * kAhpBlock + threadIdx.x;
     if (u >= N) return;
-    double p1[kMaxCrit];
-    ahp_p1(p.m, p1);
     const double invN = 1.0 / N;
     double s = 0.0;
     for (int c = 0; c < nc; ++c) {
         double l = 0.0;
         for (int jb = 0; jb < p.nJ; ++jb) l += p.rowpart[((size_t)c * p.nJ + jb) * N + u];
-        s += p1[c] * (l * invN);
+        s += p.p1[c] * (l * invN);
     }
     const float v = static_cast<float>(s);
     reinterpret_cast<float *>(p.xs + (size_t)(nc + 1) * N)[u] = v;

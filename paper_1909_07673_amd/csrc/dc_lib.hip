@@ -296,8 +296,9 @@ struct dc_ctx {
     int ti = 0, tj = 0, nI = 0, nJ = 0;
     bool ahp_sorted = false;       // AHP on the 1-9 scale through the sorted passes
     int *d_ysort = nullptr;        // [nc][N]
+    int *d_runs = nullptr;         // [nc][sort_runs][1024] sorted runs before their merge
     double *d_wsort = nullptr;     // [nc][N]
-    int ti_rank = 0, nI_rank = 0;  // row chunks of the rank pass
+    int sort_runs = 1;             // sorted passes: runs of 1,024 values sorted apart, then merged
     int *d_tmeta = nullptr, *d_tcount = nullptr;
     float *d_tscore = nullptr;
     int plain_bs = 1024;
@@ -406,6 +407,7 @@ Params base_params(dc_ctx *ctx, const DevBatch &b, int inst) {
     p.t = ctx->t;
     p.st = state_of(ctx, inst);
     p.m = ctx->m;
+    ahp_p1(ctx->m, p.p1);
     p.b = b.view;
     p.tr = Trace{ctx->d_tmeta, ctx->d_tscore, ctx->d_tcount, ctx->cfg.trace_stride, ctx->cfg.trace_cap};
     p.xs = ctx->d_xs + (size_t)inst * xs_rows(ctx->m.nc) * ctx->N;
@@ -598,16 +600,18 @@ void launch_plain_step(dc_ctx *ctx, const Params &p) {
         hipLaunchKernelGGL((k_criteria_plain<BS>), dim3(ncw), dim3(BS), ctx->lds_plain, ctx->stream, p);
         if (ctx->ahp_sorted) {
             Params q = p;
-            q.ti = ctx->ti_rank;
-            q.nI = ctx->nI_rank;
             q.nJ = 1;
-            hipLaunchKernelGGL(k_ahp_rank, dim3(bx, q.nI, ctx->m.nc), dim3(kAhpBlock), 0, ctx->stream, q);
-            hipLaunchKernelGGL(k_ahp_sort_build, dim3(1, 1, ctx->m.nc), dim3(kAhpSortBlock), 0, ctx->stream, q);
+            const dim3 gs(ctx->sort_runs, 1, ctx->m.nc), bs(kAhpSortBlock);
+            hipLaunchKernelGGL(k_ahp_sort_runs, gs, bs, 0, ctx->stream, q, ctx->d_runs);
+            if (ctx->sort_runs > 1) {
+                hipLaunchKernelGGL(k_ahp_merge_runs, gs, bs, 0, ctx->stream, q, ctx->d_runs);
+                ctx->last_launches += 1;
+            }
             hipLaunchKernelGGL(k_ahp_sort_col, dim3(bx, 1, ctx->m.nc), dim3(kAhpBlock), 0, ctx->stream, q);
             hipLaunchKernelGGL(k_ahp_sort_row, dim3(bx, 1, ctx->m.nc), dim3(kAhpBlock), 0, ctx->stream, q);
             hipLaunchKernelGGL(k_ahp_pg, dim3(bx), dim3(kAhpBlock), 0, ctx->stream, q);
             hipLaunchKernelGGL((k_ahp_select<BS>), dim3(1), dim3(BS), ctx->lds_select, ctx->stream, q);
-            ctx->last_launches += 7;
+            ctx->last_launches += 6;
         } else {
             hipLaunchKernelGGL(k_ahp_colsum, dim3(bx, ctx->nI, ctx->m.nc), dim3(kAhpBlock), 0, ctx->stream, p);
             hipLaunchKernelGGL(k_ahp_rowsum, dim3(bx, ctx->nJ, ctx->m.nc), dim3(kAhpBlock), 0, ctx->stream, p);
@@ -1373,14 +1377,15 @@ int dc_create(const dc_config *cfg, dc_ctx **out) {
         // the 1-9 scale takes the sorted passes while a criterion's sorted
         // values and their prefix sums fit one workgroup's LDS
         c->ahp_sorted = cfg->ahp_scale == DC_AHP_SAATY9 && N <= kAhpSortMax;
-        c->nI_rank = std::max(1, std::min(8, (512 + bx * nc - 1) / (bx * nc)));
-        c->ti_rank = (N + c->nI_rank - 1) / c->nI_rank;
-        c->nI_rank = (N + c->ti_rank - 1) / c->ti_rank;
-        const size_t colpart = std::max((size_t)c->nI * sizeof(long long), (size_t)c->nI_rank * sizeof(int));
+        c->sort_runs = (N + kAhpSortBlock - 1) / kAhpSortBlock;
+        const size_t colpart = (size_t)c->nI * sizeof(long long);
         if (hipMalloc(&c->d_colpart, (size_t)nc * N * colpart) != hipSuccess ||
             hipMalloc(&c->d_rowpart, (size_t)nc * c->nJ * N * sizeof(float)) != hipSuccess ||
             (c->ahp_sorted && (hipMalloc(&c->d_ysort, (size_t)nc * N * sizeof(int)) != hipSuccess ||
-                               hipMalloc(&c->d_wsort, (size_t)nc * N * sizeof(double)) != hipSuccess))) {
+                               hipMalloc(&c->d_wsort, (size_t)nc * N * sizeof(double)) != hipSuccess ||
+                               (c->sort_runs > 1 &&
+                                hipMalloc(&c->d_runs, (size_t)nc * c->sort_runs * kAhpSortBlock * sizeof(int)) !=
+                                    hipSuccess)))) {
             dc_destroy(ctx.release());
             return DC_ENOMEM;
         }
@@ -1879,7 +1884,7 @@ void dc_destroy(dc_ctx *ctx) {
         for (auto &b : ctx->batches)
             if (b->dmem) (void)hipFree(b->dmem);
         int *ptrs[] = {ctx->d_state, ctx->d_init, ctx->d_xs, ctx->d_colpart, ctx->d_tmeta, ctx->d_tcount, ctx->d_grid,
-                       ctx->d_ysort};
+                       ctx->d_ysort, ctx->d_runs};
         for (int *p : ptrs)
             if (p) (void)hipFree(p);
         if (ctx->d_rowpart) (void)hipFree(ctx->d_rowpart);

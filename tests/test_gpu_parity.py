@@ -127,16 +127,17 @@ def test_ahp_k32_full_requests_every_step():
     s.close()
 
 
-@pytest.mark.parametrize("k", [20, 34])
+@pytest.mark.parametrize("k", [20, 24, 34])
 def test_ahp_saaty_sorted_and_pairwise_sizes(k):
     """The 1-9 scale through both forms of the column and row sums: k=20
-    (2,000 hosts, not a multiple of the 256-thread block) takes the sorted
-    passes; k=34 (9,826 hosts) is beyond their LDS limit of 8,192 hosts and
-    takes the pairwise passes.  One request of three containers (two at
-    k=34, where the oracle takes about 5 s per step), every step and score
-    vector against the oracle."""
+    (2,000 hosts, not a multiple of the 256-thread block) and k=24 (3,456
+    hosts) take the sorted passes, whose sorting network then holds 2 and 4
+    slots per thread (k=16 and below: 1, k=32: 8); k=34 (9,826 hosts) is
+    beyond their LDS limit of 8,192 hosts and takes the pairwise passes.
+    One request of three containers (two at k=34, where the oracle takes
+    about 5 s per step), every step and score vector against the oracle."""
     insts, reqs = make_config("ahp", seed=3, n_req=1, k=k)
-    req, n = reqs[0][0], 3 if k == 20 else 2
+    req, n = reqs[0][0], 2 if k == 34 else 3
     req = Request(req.cpu[:n].copy(), req.ram[:n].copy(),
                   np.array([e for e in req.edges if e[0] < n and e[1] < n], np.int32).reshape(-1, 3))
     s, ids, res = _run(insts, [[req]], method=dc.DC_AHP, crit=C5, cost=C5_COST, trace_stride=1, trace_cap=8)
