@@ -682,7 +682,7 @@ __global__ __launch_bounds__(BS) void k_serve_grid(Params p, ServeArgs a, GridCt
             for (int i = 0; i < n; ++i) {
                 const int q0 = rq_poff[i];
                 const StepIn s{0, i, n, 0, i, q0, rq_poff[i + 1] - q0, rq_cpu[i], rq_ram[i], rq_cmax[i], rq_rmax[i]};
-                const ReqView rv{rq_pj + q0, rq_pbw + q0, rq_host, rq_host, rq_pbmax + q0};
+                const ReqView rv{rq_pj + q0, rq_pbw + q0, rq_host, rq_host, rq_pbmax + q0, rq_poff, rq_pj};
                 if (!grid_topsis_step<BS, CS>(t, p.st, p.m, b, sm, g, timeout, s, rv, p.tr, rnd)) {
                     fault = __hip_atomic_load(g.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
                     break;

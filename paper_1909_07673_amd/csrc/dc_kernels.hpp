@@ -692,7 +692,7 @@ __global__ __launch_bounds__(BS) void k_topsis_batched(Params p) {
             const int q0 = rq_poff[i];
             const StepIn s{r, i, n, g0, g0 + i, pb + q0, rq_poff[i + 1] - q0, rq_cpu[i], rq_ram[i],
                            rq_cmax[i], rq_rmax[i]};
-            const ReqView rv{rq_pj + q0, rq_pbw + q0, rq_host, rq_host, rq_pbmax + q0};
+            const ReqView rv{rq_pj + q0, rq_pbw + q0, rq_host, rq_host, rq_pbmax + q0, rq_poff, rq_pj};
             if (!topsis_step<BS, G, true, CS>(t, st, m, lb, sm, xs, p.pc_cap, p.tr, inst, s, rv)) break;
         }
         __syncthreads();

@@ -170,7 +170,7 @@ __global__ __launch_bounds__(BS) void k_serve(Params p, ServeArgs a) {
             for (int i = 0; i < n; ++i) {
                 const int q0 = rq_poff[i];
                 const StepIn s{0, i, n, 0, i, q0, rq_poff[i + 1] - q0, rq_cpu[i], rq_ram[i], rq_cmax[i], rq_rmax[i]};
-                const ReqView rv{rq_pj + q0, rq_pbw + q0, rq_host, rq_host, rq_pbmax + q0};
+                const ReqView rv{rq_pj + q0, rq_pbw + q0, rq_host, rq_host, rq_pbmax + q0, rq_poff, rq_pj};
                 if (!topsis_step<BS, BS >= 1024 ? 1 : host_group(BS)>(p.t, p.st, p.m, lb, sm, p.xs, p.pc_cap, p.tr, 0,
                                                                       s, rv))
                     break;

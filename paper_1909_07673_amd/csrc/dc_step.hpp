@@ -132,6 +132,10 @@ struct ReqView {
     const int *pj, *pbw, *hosts;
     int *hosts_out;    // LDS copy of hosts to update (batched form), or nullptr
     const int *pbmax;  // the peers' maximum demands
+    // the whole request in LDS (forms that stage it there), else nullptr:
+    // rpoff[x] the first pair of container x relative to the request's
+    // first pair (x <= n), rpj the pairs' peer containers
+    const int *rpoff = nullptr, *rpj = nullptr;
 };
 
 // Waits for this wave's outstanding global loads and stores (s_waitcnt
@@ -532,9 +536,38 @@ __device__ __forceinline__ void give_back(const Topo &t, const State &st, const 
 // Request r found no server for container `upto`: undo containers
 // [0, upto) (all or nothing) and mark the request rejected.  host[] keeps
 // the servers the undone containers had been given (attempt record).
+// The same from the LDS copy of the request (ReqView::rpoff, rpj, hosts):
+// the pair owners are found in LDS, not by a search through global memory.
+// g0 and pb: the request's first container and first pair in the batch.
 template <int BS>
-__device__ __forceinline__ void rollback_request(const Topo &t, const State &st, const Batch &b, int r, int upto) {
-    give_back<BS>(t, st, b, r, upto);
+__device__ __forceinline__ void give_back_lds(const Topo &t, const State &st, const Batch &b, int g0, int pb,
+                                              int upto, const ReqView &rv) {
+    const int q_end = rv.rpoff[upto];
+    for (int q = threadIdx.x; q < q_end; q += BS) {
+        int lo = 0, hi = upto - 1;                       // container owning pair q
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (rv.rpoff[mid] <= q) lo = mid; else hi = mid - 1;
+        }
+        const int u = rv.hosts[lo], v = rv.hosts[rv.rpj[q]];
+        const int c = b.code[pb + q];
+        if (u != v && c >= 0) path_apply<true>(t, st, u, v, c, b.pbwa[pb + q]);
+    }
+    for (int i = threadIdx.x; i < upto; i += BS) {
+        const int u = rv.hosts[i];
+        atomicAdd(st.cpu + u, b.cpua[g0 + i]);
+        atomicAdd(st.ram + u, b.rama[g0 + i]);
+        atomicSub(st.npl + u, 1);
+    }
+}
+
+template <int BS>
+__device__ __forceinline__ void rollback_request(const Topo &t, const State &st, const Batch &b, int r, int upto,
+                                                 const ReqView *rv = nullptr, const StepIn *s = nullptr) {
+    if (rv && rv->rpoff)
+        give_back_lds<BS>(t, st, b, s->g0, s->p0 - rv->rpoff[s->i], upto, *rv);
+    else
+        give_back<BS>(t, st, b, r, upto);
     __syncthreads();
     if (threadIdx.x == 0) {
         b.status[r] = 0;
@@ -1100,7 +1133,7 @@ __device__ __forceinline__ bool select_commit(const Topo &t, const State &st, co
         low = low_of(wh, hiw, wl);
         const unsigned long long kb = (static_cast<unsigned long long>(hiw) << 32) | low;
         if (hiw == 0) {
-            rollback_request<BS>(t, st, b, s.r, s.i);
+            rollback_request<BS>(t, st, b, s.r, s.i, &rv, &s);
             return false;
         }
         const int u = static_cast<int>(~static_cast<unsigned>(kb & 0xffffffffu));
