@@ -459,27 +459,29 @@ __global__ __launch_bounds__(kAhpSortBlock) void k_ahp_merge_runs(Params p, cons
     __syncthreads();
     const int x = y[r * L + a];
     if (x == INT_MAX) return;                                  // padding of the last run
-    // per other run q: the first index whose value is >= x (q after r) or
-    // > x (q before r), by halving a window of L + 1 positions
-    int lo[RMAX];
+    // per other run q: how many of its values come before x (< x for q
+    // after r, <= x for q before r), by a branch-free search that halves a
+    // window of the run, so that each halving issues its loads for all runs
+    // together (runs past R and run r itself are searched too, and not
+    // counted)
+    // (x < INT_MAX here, so y <= x is y < x + 1)
+    int base[RMAX], xq[RMAX];
 #pragma unroll
-    for (int q = 0; q < RMAX; ++q) lo[q] = 0;
+    for (int q = 0; q < RMAX; ++q) {
+        base[q] = min(q, R - 1) * L;
+        xq[q] = q < r ? x + 1 : x;
+    }
+    auto before = [&](int q, int yv) { return yv < xq[q]; };
 #pragma unroll
-    for (int w = L; w >= 1; w >>= 1) {
+    for (int len = L; len > 1; len -= len >> 1) {
+        const int half = len >> 1;
 #pragma unroll
-        for (int q = 0; q < RMAX; ++q) {
-            if (q >= R || q == r) continue;
-            const int m = lo[q] + w - 1;                       // probe: is y_q[m] "before" x?
-            if (m < L) {
-                const int yv = y[q * L + m];
-                if (q < r ? yv <= x : yv < x) lo[q] = m + 1;
-            }
-        }
+        for (int q = 0; q < RMAX; ++q) base[q] = before(q, y[base[q] + half]) ? base[q] + half : base[q];
     }
     int pos = a;
 #pragma unroll
     for (int q = 0; q < RMAX; ++q)
-        if (q < R && q != r) pos += lo[q];
+        if (q < R && q != r) pos += base[q] - q * L + (before(q, y[base[q]]) ? 1 : 0);
     p.ysort[(size_t)c * N + pos] = x;
 }
 
