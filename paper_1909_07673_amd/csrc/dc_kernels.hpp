@@ -118,15 +118,19 @@ __global__ __launch_bounds__(BS) void k_topsis_plain(Params p) {
 }
 
 // AHP step, stage 1: criteria of every server into the global xs rows,
-// spread over ceil(N / (G * BS)) workgroups.
-template <int BS>
+// spread over ceil(N / (G * BS)) workgroups.  K > 0: compiled for k = K
+// fat-trees and the criteria list CS (as the TOPSIS kernels are); K = 0:
+// any.
+template <int BS, int K = 0, int CS = 0>
 __global__ __launch_bounds__(BS) void k_criteria_plain(Params p) {
     extern __shared__ __align__(16) char dsm[];
     if (p.b.status[p.s.r] == 0) return;
     if (p.s.i == 0 && blockIdx.x == 0 && threadIdx.x == 0) p.b.tsb[p.s.r] = dev_clock();
-    Smem sm = carve(dsm, p.pc_cap, p.t.nsw);
-    load_peers<BS, true>(p.t, p.st, plain_view(p), sm, p.s.P);
-    criteria_stage<BS, false>(p.t, p.st, p.m, sm, p.xs, p.s.cpu, p.s.ram, p.s.P, p.pc_cap, blockIdx.x, gridDim.x);
+    const Topo t = topo_of<K>(p.t);
+    Smem sm = carve(dsm, p.pc_cap, t.nsw);
+    load_peers<BS, true>(t, p.st, plain_view(p), sm, p.s.P);
+    criteria_stage<BS, false, host_group(BS), CS>(t, p.st, p.m, sm, p.xs, p.s.cpu, p.s.ram, p.s.P, p.pc_cap,
+                                                  blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------- AHP (section V-B)

@@ -547,6 +547,16 @@ int upload_pending(dc_ctx *ctx) {
 // Whether the context runs k = K fat-trees on the four default criteria
 // (CPU, RAM, active, path bandwidth; all benefits, TOPSIS), for which
 // kernels are also compiled with these as compile-time constants.
+// The large AHP case: k = K with CPU, RAM, uplink, path bandwidth and hops
+// (a cost), the list the CS = 5 kernels are compiled for.
+bool specialised_ahp5(const dc_ctx *ctx, int K) {
+    static const int crit[5] = {DC_CRIT_CPU, DC_CRIT_RAM, DC_CRIT_UPLINK, DC_CRIT_PATHBW, DC_CRIT_HOPS};
+    if (ctx->t.k != K || ctx->m.method != DC_AHP || ctx->m.nc != 5) return false;
+    for (int c = 0; c < 5; ++c)
+        if (ctx->m.crit[c] != crit[c] || ctx->m.cost[c] != (c == 4)) return false;
+    return true;
+}
+
 bool specialised(const dc_ctx *ctx, int K) {
     if (ctx->t.k != K || ctx->m.method != DC_TOPSIS || ctx->m.nc != 4) return false;
     for (int c = 0; c < 4; ++c)
@@ -569,6 +579,8 @@ const void *grid_serve_kernel(const dc_ctx *ctx) {
 // The plain kernel (state staged in LDS, 1,024 threads) compiled for k = 16
 // on the default criteria.
 constexpr int kPlainK = 16;
+// The AHP criteria kernel compiled for k = 32 (8,192 servers) on five criteria.
+constexpr int kAhpK = 32;
 
 template <int BS>
 void launch_plain_step(dc_ctx *ctx, const Params &p) {
@@ -597,7 +609,11 @@ void launch_plain_step(dc_ctx *ctx, const Params &p) {
         const int bx = (ctx->N + kAhpBlock - 1) / kAhpBlock;
         // criteria over several workgroups, each with G * BS servers at a time
         const int ncw = (ctx->N + host_group(BS) * BS - 1) / (host_group(BS) * BS);
-        hipLaunchKernelGGL((k_criteria_plain<BS>), dim3(ncw), dim3(BS), ctx->lds_plain, ctx->stream, p);
+        if (BS == 1024 && specialised_ahp5(ctx, kAhpK))
+            hipLaunchKernelGGL((k_criteria_plain<1024, kAhpK, 5>), dim3(ncw), dim3(BS), ctx->lds_plain, ctx->stream,
+                               p);
+        else
+            hipLaunchKernelGGL((k_criteria_plain<BS>), dim3(ncw), dim3(BS), ctx->lds_plain, ctx->stream, p);
         if (ctx->ahp_sorted) {
             Params q = p;
             q.nJ = 1;

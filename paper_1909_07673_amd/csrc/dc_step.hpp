@@ -75,11 +75,20 @@ struct Method {
 };
 
 // Criteria of a step: CS = 0 takes them from the method; CS = 4 is the
-// default list (CPU, RAM, active, path bandwidth; all benefits), fixed at
-// compile time.
+// default list (CPU, RAM, active, path bandwidth; all benefits) and CS = 5
+// the five of the large AHP case (CPU, RAM, uplink, path bandwidth and hops,
+// the last a cost), fixed at compile time.
 template <int CS> __device__ __forceinline__ int crit_count(const Method &m) { return CS ? CS : m.nc; }
-template <int CS> __device__ __forceinline__ int crit_at(const Method &m, int c) { return CS ? c : m.crit[c]; }
-template <int CS> __device__ __forceinline__ int crit_cost(const Method &m, int c) { return CS ? 0 : m.cost[c]; }
+template <int CS> __device__ __forceinline__ int crit_at(const Method &m, int c) {
+    if (CS == 4) return c;
+    if (CS == 5) return c < 2 ? c : c == 2 ? CRIT_UPLINK : c == 3 ? CRIT_PATHBW : CRIT_HOPS;
+    return m.crit[c];
+}
+template <int CS> __device__ __forceinline__ int crit_cost(const Method &m, int c) {
+    if (CS == 4) return 0;
+    if (CS == 5) return c == 4;
+    return m.cost[c];
+}
 
 // A pointer to an array in global memory.  Indexing goes through an
 // address-space-1 pointer, so the access stays a global load or store even
