@@ -544,9 +544,6 @@ int upload_pending(dc_ctx *ctx) {
     return DC_OK;
 }
 
-// Whether the context runs k = K fat-trees on the four default criteria
-// (CPU, RAM, active, path bandwidth; all benefits, TOPSIS), for which
-// kernels are also compiled with these as compile-time constants.
 // The large AHP case: k = K with CPU, RAM, uplink, path bandwidth and hops
 // (a cost), the list the CS = 5 kernels are compiled for.
 bool specialised_ahp5(const dc_ctx *ctx, int K) {
@@ -557,6 +554,9 @@ bool specialised_ahp5(const dc_ctx *ctx, int K) {
     return true;
 }
 
+// Whether the context runs k = K fat-trees on the four default criteria
+// (CPU, RAM, active, path bandwidth; all benefits, TOPSIS), for which
+// kernels are also compiled with these as compile-time constants.
 bool specialised(const dc_ctx *ctx, int K) {
     if (ctx->t.k != K || ctx->m.method != DC_TOPSIS || ctx->m.nc != 4) return false;
     for (int c = 0; c < 4; ++c)
