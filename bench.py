@@ -320,10 +320,10 @@ TILE_T, TILE_C, TILE_N = 32768, 4, 1024
 # (their SHA-256); reported as null otherwise.
 TILE_TRAFFIC = {
     "sources": ('paper_1909_07673_amd/csrc/dc_tiles.hpp', 'paper_1909_07673_amd/csrc/dc_step.hpp'),
-    "sha256": "939980b337badb0e989294da85da2ab7c37ca9d506a13e13e061596644aa17c8",
+    "sha256": "08556909eae8570b3b7579798445f363612b5a483a503d8710709e86ecb2d892",
     "copy_kib": 524288.0,
-    "fetch_kib": 262216.59, "fetch_copy_kib": 262162.13,
-    "write_kib": 517.58, "write_copy_kib": 524288.0,
+    "fetch_kib": 262212.31, "fetch_copy_kib": 262162.13,
+    "write_kib": 517.64, "write_copy_kib": 524288.0,
 }
 # the batched kernel at the default workload (taken with
 # `bench.py --workload batched --no-extras --no-cpu-baseline --steps 1
@@ -332,10 +332,10 @@ TILE_TRAFFIC = {
 # launch shape (workgroup size, servers per thread, peer chunk) does not change
 BATCHED_TRAFFIC = {
     "sources": ('paper_1909_07673_amd/csrc/dc_kernels.hpp', 'paper_1909_07673_amd/csrc/dc_step.hpp'),
-    "sha256": "b5d78ae8c72ef5ac54fff583d88e58ded14d78925e1104beb57d9bcac190e7ce",
+    "sha256": "ca7aa44e0890ffe041a6034f91d4e5c7c362a0e19566e8175c74f09c93c173b4",
     "copy_kib": 524288.0,
-    "fetch_kib": 122288.13, "fetch_copy_kib": 262161.63,
-    "write_kib": 39380.94, "write_copy_kib": 524288.0,
+    "fetch_kib": 119050.13, "fetch_copy_kib": 262161.5,
+    "write_kib": 39380.88, "write_copy_kib": 524288.0,
 }
 
 

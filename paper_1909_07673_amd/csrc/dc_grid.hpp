@@ -277,6 +277,10 @@ __device__ __forceinline__ bool grid_topsis_step(const Topo &t, const State &st,
     }
     int cp = 0;
     for (int x = threadIdx.x; x < hh; x += BS) cp += st.ac[w * hh + x];
+    // the deficit slots and the error flag of phase D, reset here so that
+    // the barriers below order them before their use
+    if (threadIdx.x < 6) sm.misc[M_DH0 + threadIdx.x] = (threadIdx.x & 1) ? -1 : kBig;
+    if (threadIdx.x == 6) sm.misc[M_OK] = 0;
     const int capP_own = block_sum<BS>(cp, sm.misc + M_MISC - 1);   // ends with barriers
     // ---- B: path tables for this pod (T: its aggregation switches, E: its edge switches)
     for (int it = threadIdx.x; it < P * h; it += BS) {
@@ -373,20 +377,35 @@ __device__ __forceinline__ bool grid_topsis_step(const Topo &t, const State &st,
         if (w == 0) rec_put(g, 0, kRecTrace, stag, my_slot);
     }
     // ---- D: block totals, peer-side deficits, scores, workgroup best
-    // every wave reads the statistics words of all workgroups (lane x:
-    // workgroup x, G <= 64), waiting until all carry this step's tag
+    // One poll per thread of all it needs from the records, waiting until
+    // every word carries this step's tag: in every wave, lane x the
+    // statistics words of workgroup x (G <= 64; the lanes past G read
+    // workgroup 0's and count identities instead), and thread p < P (P <=
+    // 63) the capacity words of peer p's edge switch and pod (the other
+    // threads read their own pod's word in their place).
     constexpr int NF = 5 * (CS ? CS : kMaxCrit);
+    const bool hp = static_cast<int>(threadIdx.x) < P;
+    const int4 me = hp ? sm.pk[threadIdx.x] : make_int4(-1, 0, 0, 0);
     bool bad = false;
     int fv[NF];
+    int cv[2];
     {
-        int fw[NF], fx[NF];
+        int ww[NF + 2], wx[NF + 2], wv[NF + 2];
+        const int e = me.y & 0xffff, d = me.y >> 16;
+        ww[0] = hp ? e / h : w;
+        wx[0] = hp ? kRecCapE + e % h : kRecCapP;
+        ww[1] = hp ? d : w;
+        wx[1] = kRecCapP;
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
-            fw[f] = lane;
-            fx[f] = f;
-            fv[f] = (f % 5) < 3 ? 0 : -kBig - 1;
+            ww[2 + f] = lane < G ? lane : 0;
+            wx[2 + f] = f;
         }
-        if (lane < G) bad = !rec_get(g, 5 * nc, fw, fx, stag, timeout, fv);
+        bad = !rec_get(g, 2 + 5 * nc, ww, wx, stag, timeout, wv);
+        cv[0] = wv[0];
+        cv[1] = wv[1];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) fv[f] = lane < G ? wv[2 + f] : ((f % 5) < 3 ? 0 : -kBig - 1);
     }
     unsigned long long S2[kMaxCrit];
     int MX[kMaxCrit], MN[kMaxCrit];
@@ -406,12 +425,9 @@ __device__ __forceinline__ bool grid_topsis_step(const Topo &t, const State &st,
         MN[c] = -wave_max(nlo);
     }
     // peer-side deficits (server uplink, edge switch, pod) as in the
-    // single-workgroup step; they only narrow the candidates
-    if (threadIdx.x < 6) sm.misc[M_DH0 + threadIdx.x] = (threadIdx.x & 1) ? -1 : kBig;
-    if (threadIdx.x == 6) sm.misc[M_OK] = 0;
-    __syncthreads();
-    for (int p = threadIdx.x; p < P; p += BS) {
-        const int4 me = sm.pk[p];
+    // single-workgroup step; they only narrow the candidates (slots reset
+    // in phase A)
+    if (hp) {
         const int v = me.x, e = me.y & 0xffff, d = me.y >> 16;
         int sh = 0, se = 0, sp = 0;
         for (int q = 0; q < P; ++q) {
@@ -421,10 +437,6 @@ __device__ __forceinline__ bool grid_topsis_step(const Topo &t, const State &st,
             sp += (o.y >> 16) == d ? o.z : 0;
         }
         if (me.w < sh) { atomicMin(sm.misc + M_DH0, v); atomicMax(sm.misc + M_DH1, v); }
-        // the peer's edge switch and pod capacities, from their owners' records
-        const int cw[2] = {e / h, d}, cx[2] = {kRecCapE + e % h, kRecCapP};
-        int cv[2];
-        bad |= !rec_get(g, 2, cw, cx, stag, timeout, cv);
         if (cv[0] < se) {
             atomicMin(sm.misc + M_DE0, e);
             atomicMax(sm.misc + M_DE1, e);
