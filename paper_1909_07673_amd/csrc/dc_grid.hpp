@@ -1,10 +1,10 @@
 // Cooperative container step for large data centers: one workgroup per pod
 // (k workgroups, launched cooperatively so that all are resident).  Each
 // workgroup builds the path tables for its own pod's aggregation and edge
-// switches, scores its pod's servers; the column statistics are exchanged
-// through global memory at a grid barrier, the argmax and the commit's
-// outcome through tagged slots (selection rounds, below); workgroup 0
-// commits.  Same arithmetic as the single-workgroup step, so
+// switches, scores its pod's servers; the column statistics and the
+// capacity sums are exchanged through tagged per-workgroup records, the
+// argmax and the commit's outcome through tagged slots (selection rounds),
+// so that a step has no grid barrier; workgroup 0 commits.  Same arithmetic as the single-workgroup step, so
 // results are bit-identical.  Used by the plain form (one cooperative launch
 // per container step) and the serving form (one persistent cooperative
 // kernel) when k is large.
@@ -14,7 +14,8 @@
 namespace dcs {
 
 // Threads per pod workgroup.  The step is bound by memory latency and the
-// grid barriers, not by threads: 1024 threads measured no faster than 256.
+// waits between workgroups, not by threads: 1024 threads measured no faster
+// than 256.
 constexpr int kGridBlock = 256;
 
 // Cross-workgroup state, in device memory.
@@ -25,7 +26,7 @@ struct GridCtl {
     unsigned long long *rflag;    // outcome of a selection round's commit, tagged
     unsigned long long *rec;      // [G][kRecWords] per-workgroup records of a step, tagged (below)
     unsigned *round;              // selection rounds so far (kept across launches)
-    int *flag;                    // [kGridFlags]: trace slot, command buffers
+    int *flag;                    // [kGridFlags]: command buffers
 };
 
 // Selection rounds.  Round r of the argmax and commit needs no grid barrier:
